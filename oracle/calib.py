@@ -1,0 +1,339 @@
+"""Algorithm layer of the oracle: the per-antenna calibration updates.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  complex128 NumPy.
+
+Every function takes one solution interval as a flat list of stored rows with
+per-row antenna indices p, q (p != q; either orientation), following the
+compound row index [pqs] of Sect. 2.3:
+  scalar : d [R], m [R], gains g [Na]
+  2x2    : D [R, 2, 2], M [R, 2, 2], gains G [Na, 2, 2]        (Sect. 4)
+  DD     : d [R], m [R, Nd], gains g [Nd, Na]                  (Sect. 2.5)
+flags [R] bool: a flagged row is weight 0 (Sect. 2.4), removed from every sum
+by selection, so non-finite values under a flag have no effect.
+
+Each stored row (p, q) enters the normal equations twice (row folding,
+Eq. JJ:di): for antenna p with y_pq = m conj(g_q) against d, and for antenna q
+with y_qp = conj(m) conj(g_p) against conj(d), because d_qp = conj(d_pq) and
+m_qp = conj(m_pq).
+
+Readings taken where the paper is silent or garbled:
+  * schedule: updates are counted k = 0, 1, 2, ... from the starting gains; the
+    LM lambda=1 average (Eq. stefcal-lambda-average) is used on even k and the
+    GN step (Eq. stefcal) on odd k ("avg_first"); "gn_first" swaps the parity
+    and "gn_only" never averages (Sect. 3.1).
+  * 2x2 update order: G_p = (sum_q D_pq Y_pq^H)(sum_q Y_pq Y_pq^H)^-1, i.e. the
+    least-squares solution of D = G_p Y; the printed order Y^H D of
+    Eq. (update:DI:diag:pol) does not satisfy the normal equations.
+  * convergence: relative parameter change ||g_{k+1} - g_k||_F / ||g_{k+1}||_F
+    over all antennas (and directions) of the interval, below tol
+    (the parameter-update criterion of the convergence appendix).
+  * singular blocks: an antenna whose block is not invertible keeps its gain
+    and raises SINGULAR_ANT.  Scalar: A_p <= 0.  2x2: Z_00 <= 0 or
+    det Z <= EPS_PIVOT * Z_00 * Z_11.  Nd x Nd: a Cholesky pivot
+    <= EPS_PIVOT * H_jj.
+  * non-finite sums: the interval stops before applying the update, keeps the
+    previous gains and raises NONFINITE.
+  * residuals of flagged rows are 0; chi^2 sums |r|^2 over unflagged stored rows.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CONVERGED = 1
+MAXITER = 2
+SINGULAR_ANT = 4
+NONFINITE = 8
+
+AVG_FIRST = "avg_first"
+GN_FIRST = "gn_first"
+GN_ONLY = "gn_only"
+
+EPS_PIVOT = 1e-5
+
+
+# ------------------------------------------------------------------ helpers
+def _keep(flags, n):
+    if flags is None:
+        return np.ones(n, dtype=bool)
+    return ~np.asarray(flags, dtype=bool)
+
+
+def _is_average_step(k, schedule):
+    """True when update k (0-based) is the lambda=1 average of Eq. (stefcal-lambda-average)."""
+    if schedule == GN_ONLY:
+        return False
+    if schedule == AVG_FIRST:
+        return k % 2 == 0
+    if schedule == GN_FIRST:
+        return k % 2 == 1
+    raise ValueError(schedule)
+
+
+def rel_change(g_new, g_old):
+    """||g_new - g_old||_F / ||g_new||_F (the parameter-update convergence test)."""
+    num = np.sqrt(np.sum(np.abs(g_new - g_old) ** 2))
+    den = np.sqrt(np.sum(np.abs(g_new) ** 2))
+    if den == 0:
+        return 0.0 if num == 0 else np.inf
+    return num / den
+
+
+def cholesky_solve(H, b, eps=EPS_PIVOT):
+    """Solve H x = b for Hermitian positive-definite H by the textbook Cholesky
+    factorisation H = L L^H, then forward and back substitution.
+    Returns None when a pivot is <= eps * H_jj (the singular-block reading)."""
+    n = H.shape[0]
+    L = np.zeros_like(H, dtype=np.complex128)
+    for j in range(n):
+        piv = H[j, j].real - np.sum(np.abs(L[j, :j]) ** 2)
+        if not (piv > eps * H[j, j].real) or not np.isfinite(piv):
+            return None
+        L[j, j] = np.sqrt(piv)
+        for i in range(j + 1, n):
+            L[i, j] = (H[i, j] - np.sum(L[i, :j] * np.conj(L[j, :j]))) / L[j, j]
+    z = np.zeros(n, dtype=np.complex128)
+    for i in range(n):
+        z[i] = (b[i] - np.sum(L[i, :i] * z[:i])) / L[i, i]
+    x = np.zeros(n, dtype=np.complex128)
+    for i in reversed(range(n)):
+        x[i] = (z[i] - np.sum(np.conj(L[i + 1:, i]) * x[i + 1:])) / np.conj(L[i, i])
+    return x
+
+
+# ------------------------------------------------------------------ scalar DI
+def accumulate_scalar(d, m, p, q, flags, g):
+    """Diagonal of (J^H W J)_UL and top half of J^H W D, J^H W r for scalar gains
+    (Eqs. JHJ:DI:tfw and JHR:DI:tfw; J^H D by Eq. ghat).
+
+    Returns dict(A [Na] real, c [Na] = J^H D, jhr [Na] = J^H r, count [Na] int)."""
+    na = g.shape[0]
+    k = _keep(flags, d.shape[0])
+    d, m, p, q = d[k], m[k], p[k], q[k]
+    y_pq = m * np.conj(g[q])
+    y_qp = np.conj(m) * np.conj(g[p])
+    r = d - g[p] * m * np.conj(g[q])
+    A = np.zeros(na)
+    c = np.zeros(na, dtype=np.complex128)
+    jhr = np.zeros(na, dtype=np.complex128)
+    np.add.at(A, p, np.abs(y_pq) ** 2)
+    np.add.at(A, q, np.abs(y_qp) ** 2)
+    np.add.at(c, p, np.conj(y_pq) * d)
+    np.add.at(c, q, np.conj(y_qp) * np.conj(d))
+    np.add.at(jhr, p, np.conj(y_pq) * r)
+    np.add.at(jhr, q, np.conj(y_qp) * np.conj(r))
+    count = np.bincount(p, minlength=na) + np.bincount(q, minlength=na)
+    return dict(A=A, c=c, jhr=jhr, count=count)
+
+
+def gn_scalar(acc, g):
+    """GN value of Eq. (stefcal): g_p = c_p / A_p; singular antennas keep g_p."""
+    A, c = acc["A"], acc["c"]
+    sing = ~(A > 0)
+    ghat = np.where(sing, g, c / np.where(sing, 1.0, A))
+    return ghat, sing
+
+
+def residual_scalar(d, m, p, q, flags, g):
+    """r = d - g_p m conj(g_q) (Eq. cal:DI); flagged rows 0; chi^2 over unflagged rows."""
+    k = _keep(flags, d.shape[0])
+    r = np.zeros_like(d, dtype=np.complex128)
+    r[k] = d[k] - g[p[k]] * m[k] * np.conj(g[q[k]])
+    return r, float(np.sum(np.abs(r[k]) ** 2))
+
+
+# ------------------------------------------------------------------ 2x2 DI
+def _H(X):
+    return np.conj(np.swapaxes(X, -1, -2))
+
+
+def accumulate_2x2(D, M, p, q, flags, G):
+    """Operator-diagonal blocks of J^H J and J^H D, J^H r for 2x2 Jones (Sect. 4.2-4.3):
+    Z_p = sum Y Y^H and N_p = sum D Y^H with Y_pq = M_pq G_q^H; the folded row qp has
+    Y_qp = M_pq^H G_p^H and D_qp = D_pq^H.  J^H r = sum R Y^H."""
+    na = G.shape[0]
+    k = _keep(flags, D.shape[0])
+    D, M, p, q = D[k], M[k], p[k], q[k]
+    Y_pq = M @ _H(G[q])
+    Y_qp = _H(M) @ _H(G[p])
+    R = D - G[p] @ M @ _H(G[q])
+    Z = np.zeros((na, 2, 2), dtype=np.complex128)
+    N = np.zeros((na, 2, 2), dtype=np.complex128)
+    jhr = np.zeros((na, 2, 2), dtype=np.complex128)
+    np.add.at(Z, p, Y_pq @ _H(Y_pq))
+    np.add.at(Z, q, Y_qp @ _H(Y_qp))
+    np.add.at(N, p, D @ _H(Y_pq))
+    np.add.at(N, q, _H(D) @ _H(Y_qp))
+    np.add.at(jhr, p, R @ _H(Y_pq))
+    np.add.at(jhr, q, _H(R) @ _H(Y_qp))
+    count = np.bincount(p, minlength=na) + np.bincount(q, minlength=na)
+    return dict(Z=Z, N=N, jhr=jhr, count=count)
+
+
+def gn_2x2(acc, G, eps=EPS_PIVOT):
+    """GN value G_p = N_p Z_p^-1 (2x2 inverse by the adjugate); singular antennas keep G_p."""
+    Z, N = acc["Z"], acc["N"]
+    na = G.shape[0]
+    Gh = G.copy()
+    sing = np.zeros(na, dtype=bool)
+    for a in range(na):
+        z00, z11 = Z[a, 0, 0].real, Z[a, 1, 1].real
+        det = (Z[a, 0, 0] * Z[a, 1, 1] - Z[a, 0, 1] * Z[a, 1, 0]).real
+        if not (z00 > 0) or not (det > eps * z00 * z11):
+            sing[a] = True
+            continue
+        Zinv = np.array([[Z[a, 1, 1], -Z[a, 0, 1]], [-Z[a, 1, 0], Z[a, 0, 0]]]) / det
+        Gh[a] = N[a] @ Zinv
+    return Gh, sing
+
+
+def residual_2x2(D, M, p, q, flags, G):
+    """R = D - G_p M G_q^H (Eq. cal:DI:pol); flagged rows 0; chi^2 = sum ||R||_F^2."""
+    k = _keep(flags, D.shape[0])
+    R = np.zeros_like(D, dtype=np.complex128)
+    R[k] = D[k] - G[p[k]] @ M[k] @ _H(G[q[k]])
+    return R, float(np.sum(np.abs(R[k]) ** 2))
+
+
+# ------------------------------------------------------------------ DD (CohJones / AllJones)
+def accumulate_dd(d, m, p, q, flags, g):
+    """Per-antenna Nd x Nd blocks of the CAD-ordered J^H J and the vectors J^H D, J^H r
+    (Eqs. JHJ:DD:unpol and JHR:DD:unpol): with y^d_pq = m^d conj(g^d_q),
+    H_p[c, d] = sum conj(y^c) y^d, c_p[d] = sum conj(y^d) d."""
+    nd, na = g.shape
+    k = _keep(flags, d.shape[0])
+    d, m, p, q = d[k], m[k], p[k], q[k]
+    y_pq = m * np.conj(g[:, q]).T            # [R, Nd]
+    y_qp = np.conj(m) * np.conj(g[:, p]).T
+    r = d - np.sum(g[:, p].T * m * np.conj(g[:, q]).T, axis=1)
+    H = np.zeros((na, nd, nd), dtype=np.complex128)
+    c = np.zeros((na, nd), dtype=np.complex128)
+    jhr = np.zeros((na, nd), dtype=np.complex128)
+    np.add.at(H, p, np.conj(y_pq)[:, :, None] * y_pq[:, None, :])
+    np.add.at(H, q, np.conj(y_qp)[:, :, None] * y_qp[:, None, :])
+    np.add.at(c, p, np.conj(y_pq) * d[:, None])
+    np.add.at(c, q, np.conj(y_qp) * np.conj(d)[:, None])
+    np.add.at(jhr, p, np.conj(y_pq) * r[:, None])
+    np.add.at(jhr, q, np.conj(y_qp) * np.conj(r)[:, None])
+    count = np.bincount(p, minlength=na) + np.bincount(q, minlength=na)
+    return dict(H=H, c=c, jhr=jhr, count=count)
+
+
+def gn_cohjones(acc, g, eps=EPS_PIVOT, form="data", H_used=None):
+    """CohJones GN value per antenna (Sect. 3.2.2): g_p = H_p^-1 c_p by Cholesky.
+    form="residual" uses g_p + H~_p^-1 J^H r (Eq. ghat:approx) with H~ = H_used."""
+    nd, na = g.shape
+    H = acc["H"] if H_used is None else H_used
+    gh = g.copy()
+    sing = np.zeros(na, dtype=bool)
+    for a in range(na):
+        rhs = acc["c"][a] if form == "data" else acc["jhr"][a]
+        x = cholesky_solve(H[a], rhs, eps)
+        if x is None:
+            sing[a] = True
+            continue
+        gh[:, a] = x if form == "data" else g[:, a] + x
+    return gh, sing
+
+
+def gn_alljones(acc, g):
+    """AllJones GN value (Eq. stefcal:dd:unpol): residual form with the diagonal of H_p,
+    g^d_p + (sum |y^d|^2)^-1 sum conj(y^d) r."""
+    nd, na = g.shape
+    diag = np.real(np.einsum("add->ad", acc["H"]))     # [Na, Nd]
+    sing = ~(diag > 0)
+    step = np.where(sing, 0, acc["jhr"] / np.where(sing, 1.0, diag))
+    return g + step.T, sing.T
+
+
+def residual_dd(d, m, p, q, flags, g):
+    """r = d - sum_d g^d_p m^d conj(g^d_q) (Eq. cal:dd:unpol); flagged rows 0."""
+    k = _keep(flags, d.shape[0])
+    r = np.zeros_like(d, dtype=np.complex128)
+    r[k] = d[k] - np.sum(g[:, p[k]].T * m[k] * np.conj(g[:, q[k]]).T, axis=1)
+    return r, float(np.sum(np.abs(r[k]) ** 2))
+
+
+# ------------------------------------------------------------------ iteration driver
+def _solve(accumulate, gn, residual, finite, sing_to_ant, d, m, p, q, flags, g0,
+           tol, max_iter, schedule):
+    g = np.array(g0, dtype=np.complex128, copy=True)
+    status = 0
+    hist = []
+    n_iter = 0
+    k_rows = _keep(flags, d.shape[0])
+    if not (np.all(np.isfinite(d[k_rows])) and np.all(np.isfinite(m[k_rows]))):
+        status |= NONFINITE
+    else:
+        for k in range(max_iter):
+            acc = accumulate(d, m, p, q, flags, g)
+            if not finite(acc):
+                status |= NONFINITE
+                break
+            ghat, sing = gn(acc, g)
+            if np.any(sing):
+                status |= SINGULAR_ANT
+            g_new = 0.5 * (g + ghat) if _is_average_step(k, schedule) else ghat
+            rel = rel_change(g_new, g)
+            hist.append(rel)
+            g = g_new
+            n_iter = k + 1
+            if rel < tol:
+                status |= CONVERGED
+                break
+        else:
+            status |= MAXITER
+    r, chi2 = residual(d, m, p, q, flags, g)
+    return dict(g=g, n_iter=n_iter, status=status, residual=r, chi2=chi2, history=hist)
+
+
+def stefcal_scalar(d, m, p, q, flags, g0, tol=1e-6, max_iter=100, schedule=AVG_FIRST):
+    """Scalar StefCal: diagonal J^H J, GN (Eq. stefcal) alternating with the
+    lambda=1 LM average (Eq. stefcal-lambda-average), Jacobi over antennas."""
+    fin = lambda a: np.all(np.isfinite(a["A"])) and np.all(np.isfinite(a["c"]))
+    return _solve(accumulate_scalar, gn_scalar, residual_scalar, fin, None,
+                  d, m, p, q, flags, g0, tol, max_iter, schedule)
+
+
+def stefcal_2x2(D, M, p, q, flags, G0, tol=1e-6, max_iter=100, schedule=AVG_FIRST):
+    """Polarized StefCal (Eq. update:DI:diag:pol, order per the least-squares reading)."""
+    fin = lambda a: np.all(np.isfinite(a["Z"])) and np.all(np.isfinite(a["N"]))
+    return _solve(accumulate_2x2, gn_2x2, residual_2x2, fin, None,
+                  D, M, p, q, flags, G0, tol, max_iter, schedule)
+
+
+def cohjones(d, m, p, q, flags, g0, tol=1e-6, max_iter=100, schedule=AVG_FIRST,
+             form="data", perturb=None):
+    """CohJones (Sect. 3.2.2): per-antenna Nd x Nd blocks inverted exactly.
+    perturb(H) -> H~ replaces the blocks by an approximation (used with form="residual")."""
+    fin = lambda a: np.all(np.isfinite(a["H"])) and np.all(np.isfinite(a["c"]))
+
+    def gn(acc, g):
+        Hu = None if perturb is None else perturb(acc["H"])
+        return gn_cohjones(acc, g, form=form, H_used=Hu)
+    return _solve(accumulate_dd, gn, residual_dd, fin, None,
+                  d, m, p, q, flags, g0, tol, max_iter, schedule)
+
+
+def alljones(d, m, p, q, flags, g0, tol=1e-6, max_iter=200, schedule=AVG_FIRST):
+    """AllJones (Sect. 3.2.3): fully diagonal DD update in residual form."""
+    fin = lambda a: np.all(np.isfinite(a["H"])) and np.all(np.isfinite(a["jhr"]))
+    return _solve(accumulate_dd, gn_alljones, residual_dd, fin, None,
+                  d, m, p, q, flags, g0, tol, max_iter, schedule)
+
+
+# ------------------------------------------------------------------ gauge
+def align_phase(g, ref):
+    """g * exp(i phi) with phi = arg sum conj(g) ref: the least-squares global phase
+    that maps g onto ref (the solution is unique only up to this phase)."""
+    s = np.sum(np.conj(g) * ref)
+    return g * (s / abs(s) if abs(s) > 0 else 1.0)
+
+
+def align_phase_per_direction(g, ref):
+    """DD gains [Nd, Na]: one phase per direction (the DD model is invariant under
+    g^d -> g^d exp(i phi_d))."""
+    return np.stack([align_phase(g[i], ref[i]) for i in range(g.shape[0])])
+
+
+def rel_err(a, b):
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2)) / np.sqrt(np.sum(np.abs(b) ** 2)))
