@@ -1,0 +1,162 @@
+/*
+ * wcal.h -- C ABI of the MI355X (gfx950) Wirtinger-Jacobian gain-calibration library.
+ *
+ * The library solves the weighted least-squares gain calibration problem of
+ * Smirnov & Tasse, "Radio interferometric gain calibration as a complex
+ * optimization problem" (MNRAS 2015):
+ *
+ *   scalar DI   : d_pqs = g_p m_pqs conj(g_q) + n        (Sect. 2.1, 2.3, Eq. cal:DI:tf)
+ *   2x2 DI      : D_pqs = G_p M_pqs G_q^H + N            (Sect. 4, Eq. cal:DI:pol)
+ *   DD (Nd dirs): d_pqs = sum_d g^d_p m^d_pqs conj(g^d_q) (Sect. 2.5, Eq. cal:dd:unpol)
+ *
+ * with 0/1 weights given as flags (Sect. 2.4), independently for every
+ * time/frequency solution interval (Sect. 2.3).  Algorithms: StefCal, the
+ * diagonal approximation of J^H J (Sect. 3.1, Eq. stefcal; polarized form
+ * Eq. update:DI:diag:pol), CohJones, the per-antenna Nd x Nd block
+ * approximation (Sect. 3.2.2), and AllJones, the fully diagonal DD update in
+ * residual form (Sect. 3.2.3, Eq. stefcal:dd:unpol).
+ *
+ * Conventions (all arrays are C-contiguous):
+ *   complex       : wcal_c64, interleaved float32 (re, im) -- the bytes of torch.complex64.
+ *   baselines     : ant1[b], ant2[b] for b < n_bl, antenna indices in [0, n_ant), ant1 != ant2.
+ *                   Either orientation is accepted; a row stored as (q, p) must hold the
+ *                   conjugate (2x2: Hermitian transpose) data and model.
+ *   intervals     : ns[k] >= 1 samples per baseline in interval k; interval k owns rows
+ *                   [row_off[k], row_off[k+1]) with row_off = n_bl * prefix_sum(ns), ordered
+ *                   sample-major: row = row_off[k] + s * n_bl + b.
+ *   data          : [rows][n_corr]          (n_corr = 1 scalar, 4 = 2x2 row-major xx,xy,yx,yy)
+ *   model         : [rows][n_dir][n_corr]
+ *   flags         : [rows] uint8, nonzero = flagged (all correlations), or NULL = none.
+ *                   A flagged row is removed from every sum by selection, so NaN/Inf under a
+ *                   flag has no effect; its residual is written as exactly 0.
+ *   gains         : [n_int][n_dir][n_ant][n_corr]; 2x2 gains are Jones matrices row-major.
+ *
+ * Memory: every data pointer passed to a compute call is DEVICE memory owned by the
+ * caller, which must stay valid until the stream has passed the call.  Host pointers
+ * are only taken by wcal_plan_create (tables are copied into plan-owned device memory).
+ * Calls are asynchronous on the given stream (a hipStream_t; NULL = default stream).
+ * One plan must not be used on two streams at the same time.  data/model/gains/residual
+ * pointers must be 8-byte aligned (16-byte for n_corr = 4).
+ *
+ * Return codes: 0 = success; negative = argument or runtime error detected
+ * synchronously (nothing was launched); wcal_last_error() then describes it.
+ * Numerical outcomes are never errors: they are written per interval to status[k].
+ */
+#ifndef WCAL_H
+#define WCAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } wcal_c64;
+
+/* return codes */
+#define WCAL_OK       0
+#define WCAL_EINVAL  (-1)  /* NULL required pointer, non-positive size, unsupported combination */
+#define WCAL_EINDEX  (-2)  /* antenna index outside [0, n_ant) or ant1 == ant2 (autocorrelation) */
+#define WCAL_ESHAPE  (-3)  /* ns[k] < 1, or a size beyond the library limits */
+#define WCAL_EHIP    (-4)  /* a HIP runtime call failed */
+#define WCAL_ENOMEM  (-5)  /* device allocation failed */
+
+/* per-interval status bits */
+#define WCAL_CONVERGED    1u  /* ||g_{k+1} - g_k||_F / ||g_{k+1}||_F < tol                      */
+#define WCAL_MAXITER      2u  /* max_iter updates applied without meeting tol                     */
+#define WCAL_SINGULAR_ANT 4u  /* some antenna's block was not invertible: its gain was kept       */
+#define WCAL_NONFINITE    8u  /* a sum over unflagged rows was not finite: the interval stopped   */
+                              /* before that update and kept the previous gains                   */
+
+/* algorithms */
+#define WCAL_STEFCAL   0   /* n_dir == 1; n_corr 1 or 4                     (Sect. 3.1, 4.3)   */
+#define WCAL_COHJONES  1   /* n_corr == 1; per-antenna Nd x Nd blocks        (Sect. 3.2.2)      */
+#define WCAL_ALLJONES  2   /* n_corr == 1; fully diagonal, residual form     (Sect. 3.2.3)      */
+
+/* update schedules: update k = 0, 1, ... from the starting gains either applies the
+ * GN value (Eq. stefcal / its block forms) or the lambda = 1 LM average
+ * g_{k+1} = (g_k + GN) / 2 (Eq. stefcal-lambda-average). */
+#define WCAL_AVG_FIRST 0   /* average on even k, GN on odd k (default) */
+#define WCAL_GN_FIRST  1   /* GN on even k, average on odd k           */
+#define WCAL_GN_ONLY   2   /* GN on every update                        */
+
+/* singular-block threshold: a 2x2 block with det Z <= EPS * Z00 * Z11 or an Nd x Nd
+ * Cholesky pivot <= EPS * H_jj is treated as not invertible. */
+#define WCAL_EPS_PIVOT 1e-5
+
+typedef struct {
+    int32_t n_ant;     /* antennas                                   */
+    int32_t n_bl;      /* baselines (rows per sample)                */
+    int32_t n_dir;     /* directions (1 for StefCal)                 */
+    int32_t n_corr;    /* 1 = scalar, 4 = 2x2 Jones                  */
+    int32_t n_int;     /* solution intervals                         */
+    int32_t algo;      /* WCAL_STEFCAL | WCAL_COHJONES | WCAL_ALLJONES */
+    int32_t schedule;  /* WCAL_AVG_FIRST | WCAL_GN_FIRST | WCAL_GN_ONLY */
+    int32_t max_iter;  /* maximum number of updates (>= 1)           */
+    double  tol;       /* relative parameter-change tolerance (>= 0) */
+} wcal_problem;
+
+typedef struct wcal_plan wcal_plan;
+
+/* Message for the last non-zero return on the calling thread ("" if none). */
+const char* wcal_last_error(void);
+
+/* Library version string. */
+const char* wcal_version(void);
+
+/* Validate a problem and build a plan on HIP device `device`.
+ * ant1_h, ant2_h [n_bl] and ns_h [n_int] are HOST arrays, copied into plan-owned device
+ * tables.  Fails with WCAL_EINDEX for an antenna outside [0, n_ant) or ant1 == ant2
+ * (autocorrelations are excluded from the problem, Sect. 2.1 footnote), WCAL_ESHAPE for
+ * ns[k] < 1 or sizes beyond the limits, WCAL_EINVAL for an unsupported combination. */
+int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int32_t* ant2_h,
+                     const int64_t* ns_h, int device, wcal_plan** out);
+
+/* Release a plan and its device tables (NULL is a no-op).  The caller must make sure
+ * no call using the plan is still in flight. */
+void wcal_plan_destroy(wcal_plan* plan);
+
+/* Total rows (sum over intervals of n_bl * ns[k]) described by the plan. */
+int64_t wcal_plan_rows(const wcal_plan* plan);
+
+/* Solve every interval: iterate the algorithm's update from the gains held in `gains`
+ * until the relative parameter change drops below tol or max_iter updates were applied,
+ * then predict the residual R = D - sum_d G_p M G_q^H with the final gains.
+ *   gains    in/out [n_int][n_dir][n_ant][n_corr]
+ *   residual out    [rows][n_corr], or NULL (flagged rows are written as 0)
+ *   n_iter   out    [n_int] updates applied
+ *   status   out    [n_int] WCAL_* status bits
+ *   chi2     out    [n_int] sum of |R|^2 over unflagged rows (FP64), or NULL
+ * The whole batch runs on the device: StefCal in one persistent launch, CohJones /
+ * AllJones as a statistics pass, a per-interval solve and a residual pass. */
+int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
+               const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
+               int32_t* n_iter, uint32_t* status, double* chi2, void* stream);
+
+/* One fused pass at fixed gains, no iteration: per interval and antenna the blocks of
+ * the approximate J^H J that the algorithm inverts, the top half of J^H D and of J^H r,
+ * the number of unflagged stored rows touching the antenna, chi^2 and optionally R.
+ *   jhj  [n_int][n_ant][blk]  scalar: blk = 1 (A_p, imaginary part 0; Eq. JHJ:DI:tfw);
+ *                             2x2: blk = 4, Z_p = sum Y Y^H (Eq. JHJ:pol diagonal);
+ *                             DD:  blk = n_dir * n_dir, H_p[c][d] = sum conj(y^c) y^d
+ *                             (Eq. JHJ:DD:unpol diagonal blocks)
+ *   jhd  [n_int][n_ant][n_dir * n_corr]  J^H D (scalar/DD: sum conj(y) d; 2x2: sum D Y^H)
+ *   jhr  [n_int][n_ant][n_dir * n_corr]  J^H r (same with r in place of d)
+ *   count [n_int][n_ant] int32, chi2 [n_int] (FP64), residual [rows][n_corr] or NULL. */
+int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
+                    const uint8_t* flags, const wcal_c64* gains, wcal_c64* jhj, wcal_c64* jhd,
+                    wcal_c64* jhr, int32_t* count, double* chi2, wcal_c64* residual,
+                    void* stream);
+
+/* Residual prediction only: R = D - sum_d G_p M G_q^H, flagged rows 0 (Eq. cal:DI,
+ * Eq. cal:DI:pol, Eq. cal:dd:unpol); chi2 [n_int] or NULL. */
+int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
+                  const uint8_t* flags, const wcal_c64* gains, wcal_c64* residual,
+                  double* chi2, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCAL_H */

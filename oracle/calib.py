@@ -58,6 +58,21 @@ def _keep(flags, n):
     return ~np.asarray(flags, dtype=bool)
 
 
+def _scatter(out, idx, vals):
+    """out[idx[i]] += vals[i] along the first axis (a bincount per trailing element)."""
+    n = out.shape[0]
+    flat = vals.reshape(vals.shape[0], -1)
+    o = out.reshape(n, -1)
+    for j in range(flat.shape[1]):
+        col = flat[:, j]
+        if np.iscomplexobj(o):
+            o[:, j] += (np.bincount(idx, weights=col.real, minlength=n)
+                        + 1j * np.bincount(idx, weights=col.imag, minlength=n))
+        else:
+            o[:, j] += np.bincount(idx, weights=col, minlength=n)
+    return out
+
+
 def _is_average_step(k, schedule):
     """True when update k (0-based) is the lambda=1 average of Eq. (stefcal-lambda-average)."""
     if schedule == GN_ONLY:
@@ -115,12 +130,12 @@ def accumulate_scalar(d, m, p, q, flags, g):
     A = np.zeros(na)
     c = np.zeros(na, dtype=np.complex128)
     jhr = np.zeros(na, dtype=np.complex128)
-    np.add.at(A, p, np.abs(y_pq) ** 2)
-    np.add.at(A, q, np.abs(y_qp) ** 2)
-    np.add.at(c, p, np.conj(y_pq) * d)
-    np.add.at(c, q, np.conj(y_qp) * np.conj(d))
-    np.add.at(jhr, p, np.conj(y_pq) * r)
-    np.add.at(jhr, q, np.conj(y_qp) * np.conj(r))
+    _scatter(A, p, np.abs(y_pq) ** 2)
+    _scatter(A, q, np.abs(y_qp) ** 2)
+    _scatter(c, p, np.conj(y_pq) * d)
+    _scatter(c, q, np.conj(y_qp) * np.conj(d))
+    _scatter(jhr, p, np.conj(y_pq) * r)
+    _scatter(jhr, q, np.conj(y_qp) * np.conj(r))
     count = np.bincount(p, minlength=na) + np.bincount(q, minlength=na)
     return dict(A=A, c=c, jhr=jhr, count=count)
 
@@ -159,12 +174,12 @@ def accumulate_2x2(D, M, p, q, flags, G):
     Z = np.zeros((na, 2, 2), dtype=np.complex128)
     N = np.zeros((na, 2, 2), dtype=np.complex128)
     jhr = np.zeros((na, 2, 2), dtype=np.complex128)
-    np.add.at(Z, p, Y_pq @ _H(Y_pq))
-    np.add.at(Z, q, Y_qp @ _H(Y_qp))
-    np.add.at(N, p, D @ _H(Y_pq))
-    np.add.at(N, q, _H(D) @ _H(Y_qp))
-    np.add.at(jhr, p, R @ _H(Y_pq))
-    np.add.at(jhr, q, _H(R) @ _H(Y_qp))
+    _scatter(Z, p, Y_pq @ _H(Y_pq))
+    _scatter(Z, q, Y_qp @ _H(Y_qp))
+    _scatter(N, p, D @ _H(Y_pq))
+    _scatter(N, q, _H(D) @ _H(Y_qp))
+    _scatter(jhr, p, R @ _H(Y_pq))
+    _scatter(jhr, q, _H(R) @ _H(Y_qp))
     count = np.bincount(p, minlength=na) + np.bincount(q, minlength=na)
     return dict(Z=Z, N=N, jhr=jhr, count=count)
 
@@ -208,12 +223,12 @@ def accumulate_dd(d, m, p, q, flags, g):
     H = np.zeros((na, nd, nd), dtype=np.complex128)
     c = np.zeros((na, nd), dtype=np.complex128)
     jhr = np.zeros((na, nd), dtype=np.complex128)
-    np.add.at(H, p, np.conj(y_pq)[:, :, None] * y_pq[:, None, :])
-    np.add.at(H, q, np.conj(y_qp)[:, :, None] * y_qp[:, None, :])
-    np.add.at(c, p, np.conj(y_pq) * d[:, None])
-    np.add.at(c, q, np.conj(y_qp) * np.conj(d)[:, None])
-    np.add.at(jhr, p, np.conj(y_pq) * r[:, None])
-    np.add.at(jhr, q, np.conj(y_qp) * np.conj(r)[:, None])
+    _scatter(H, p, np.conj(y_pq)[:, :, None] * y_pq[:, None, :])
+    _scatter(H, q, np.conj(y_qp)[:, :, None] * y_qp[:, None, :])
+    _scatter(c, p, np.conj(y_pq) * d[:, None])
+    _scatter(c, q, np.conj(y_qp) * np.conj(d)[:, None])
+    _scatter(jhr, p, np.conj(y_pq) * r[:, None])
+    _scatter(jhr, q, np.conj(y_qp) * np.conj(r)[:, None])
     count = np.bincount(p, minlength=na) + np.bincount(q, minlength=na)
     return dict(H=H, c=c, jhr=jhr, count=count)
 

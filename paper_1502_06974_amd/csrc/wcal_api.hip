@@ -1,0 +1,294 @@
+// Host side of the C ABI declared in include/wcal.h: validation, plan tables, launches.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "wcal_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(WCAL_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (n) e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+int check_common(const wcal_plan* plan, const void* data, const void* model, const void* gains) {
+    if (!plan) return fail(WCAL_EINVAL, "plan is NULL");
+    if (!data || !model || !gains) return fail(WCAL_EINVAL, "data, model and gains are required");
+    const size_t al = plan->prob.n_corr == 4 ? 16 : 8;
+    if (!aligned(data, al) || !aligned(model, al) || !aligned(gains, 8))
+        return fail(WCAL_EINVAL, "data/model must be 8-byte aligned (16-byte for n_corr = 4)");
+    if (hipSetDevice(plan->device) != hipSuccess) return fail(WCAL_EHIP, "hipSetDevice failed");
+    return WCAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wcal_last_error(void) { return g_err.c_str(); }
+
+const char* wcal_version(void) { return "wcal 0.1 (gfx950)"; }
+
+int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int32_t* ant2_h,
+                     const int64_t* ns_h, int device, wcal_plan** out) {
+    g_err.clear();
+    if (!prob || !ant1_h || !ant2_h || !ns_h || !out) return fail(WCAL_EINVAL, "NULL argument");
+    *out = nullptr;
+    const wcal_problem& p = *prob;
+    if (p.n_ant < 2 || p.n_bl < 1 || p.n_dir < 1 || p.n_int < 1 || p.max_iter < 1)
+        return fail(WCAL_EINVAL, "n_ant >= 2, n_bl, n_dir, n_int, max_iter >= 1 required");
+    if (p.n_corr != 1 && p.n_corr != 4) return fail(WCAL_EINVAL, "n_corr must be 1 or 4");
+    if (!(p.tol >= 0.0)) return fail(WCAL_EINVAL, "tol must be >= 0");
+    if (p.schedule < WCAL_AVG_FIRST || p.schedule > WCAL_GN_ONLY) return fail(WCAL_EINVAL, "unknown schedule");
+    if (p.algo == WCAL_STEFCAL) {
+        if (p.n_dir != 1) return fail(WCAL_EINVAL, "StefCal needs n_dir == 1 (use CohJones/AllJones)");
+    } else if (p.algo == WCAL_COHJONES || p.algo == WCAL_ALLJONES) {
+        if (p.n_corr != 1) return fail(WCAL_EINVAL, "CohJones/AllJones are implemented for n_corr == 1");
+        if (p.n_dir > 32) return fail(WCAL_ESHAPE, "n_dir > 32 is not supported");
+    } else {
+        return fail(WCAL_EINVAL, "unknown algorithm");
+    }
+    for (int32_t b = 0; b < p.n_bl; ++b) {
+        const int32_t a1 = ant1_h[b], a2 = ant2_h[b];
+        if (a1 < 0 || a1 >= p.n_ant || a2 < 0 || a2 >= p.n_ant)
+            return fail(WCAL_EINDEX, "baseline " + std::to_string(b) + ": antenna index out of range");
+        if (a1 == a2) return fail(WCAL_EINDEX, "baseline " + std::to_string(b) + ": autocorrelation (ant1 == ant2)");
+    }
+    std::vector<int64_t> off(p.n_int + 1, 0);
+    std::vector<int32_t> ns32(p.n_int);
+    int32_t max_ns = 0;
+    for (int32_t k = 0; k < p.n_int; ++k) {
+        if (ns_h[k] < 1) return fail(WCAL_ESHAPE, "interval " + std::to_string(k) + ": ns < 1");
+        if (ns_h[k] > (int64_t)INT32_MAX / 4) return fail(WCAL_ESHAPE, "ns too large");
+        ns32[k] = (int32_t)ns_h[k];
+        max_ns = std::max(max_ns, ns32[k]);
+        off[k + 1] = off[k] + (int64_t)p.n_bl * ns_h[k];
+    }
+    // longest-processing-time order for the work queue
+    std::vector<int32_t> order(p.n_int);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return ns32[x] > ns32[y]; });
+
+    if (hipSetDevice(device) != hipSuccess) return fail(WCAL_EHIP, "hipSetDevice failed");
+    auto* plan = new wcal_plan();
+    plan->prob = p;
+    plan->device = device;
+    plan->rows = off[p.n_int];
+    plan->max_ns = max_ns;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete plan;
+        return fail(WCAL_EHIP, "hipGetDeviceProperties failed");
+    }
+    plan->n_cu = prop.multiProcessorCount;
+    // the kernels are compiled for at most 256 threads per workgroup
+    if (const char* s = std::getenv("WCAL_BLOCK")) plan->block = std::max(64, std::min(256, atoi(s)) / 64 * 64);
+    if (const char* s = std::getenv("WCAL_WG_PER_CU")) plan->wg_per_cu = atoi(s);
+    // LDS budget of the persistent kernels: per-antenna gains and per-wavefront accumulators
+    if (p.algo == WCAL_STEFCAL && di_smem_bytes(p.n_ant, p.n_corr, 1, plan->block) > 64 * 1024) {
+        delete plan;
+        return fail(WCAL_ESHAPE, "n_ant too large for the per-interval LDS working set");
+    }
+    hipError_t e = hipSuccess;
+    if ((e = upload(&plan->d_ant1, ant1_h, p.n_bl)) != hipSuccess ||
+        (e = upload(&plan->d_ant2, ant2_h, p.n_bl)) != hipSuccess ||
+        (e = upload(&plan->d_row_off, off.data(), off.size())) != hipSuccess ||
+        (e = upload(&plan->d_ns, ns32.data(), ns32.size())) != hipSuccess ||
+        (e = upload(&plan->d_order, order.data(), order.size())) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_queue), 4 * sizeof(int32_t))) != hipSuccess) {
+        wcal_plan_destroy(plan);
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tables");
+    }
+    if (p.algo != WCAL_STEFCAL) {
+        plan->stats_bytes = dd_stats_bytes(p);
+        if (plan->stats_bytes && (e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
+            wcal_plan_destroy(plan);
+            return fail(WCAL_ENOMEM, "statistics scratch allocation failed");
+        }
+    }
+    *out = plan;
+    return WCAL_OK;
+}
+
+void wcal_plan_destroy(wcal_plan* plan) {
+    if (!plan) return;
+    (void)hipSetDevice(plan->device);
+    for (void* p : {(void*)plan->d_ant1, (void*)plan->d_ant2, (void*)plan->d_row_off, (void*)plan->d_ns,
+                    (void*)plan->d_order, (void*)plan->d_queue, (void*)plan->d_stats})
+        if (p) (void)hipFree(p);
+    delete plan;
+}
+
+int64_t wcal_plan_rows(const wcal_plan* plan) { return plan ? plan->rows : -1; }
+
+static void fill_tables_di(const wcal_plan* plan, DiArgs& a) {
+    a.ant1 = plan->d_ant1;
+    a.ant2 = plan->d_ant2;
+    a.row_off = plan->d_row_off;
+    a.ns = plan->d_ns;
+    a.order = plan->d_order;
+    a.queue = plan->d_queue;
+    a.n_ant = plan->prob.n_ant;
+    a.n_bl = plan->prob.n_bl;
+    a.n_int = plan->prob.n_int;
+    a.max_iter = plan->prob.max_iter;
+    a.schedule = plan->prob.schedule;
+    a.tol = plan->prob.tol;
+}
+
+static void fill_tables_dd(const wcal_plan* plan, DdArgs& a) {
+    a.ant1 = plan->d_ant1;
+    a.ant2 = plan->d_ant2;
+    a.row_off = plan->d_row_off;
+    a.ns = plan->d_ns;
+    a.order = plan->d_order;
+    a.queue = plan->d_queue;
+    a.stats = plan->d_stats;
+    a.n_ant = plan->prob.n_ant;
+    a.n_bl = plan->prob.n_bl;
+    a.n_int = plan->prob.n_int;
+    a.n_dir = plan->prob.n_dir;
+    a.max_iter = plan->prob.max_iter;
+    a.schedule = plan->prob.schedule;
+    a.algo = plan->prob.algo;
+    a.tol = plan->prob.tol;
+}
+
+int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
+               wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
+               void* stream) {
+    g_err.clear();
+    int rc = check_common(plan, data, model, gains);
+    if (rc) return rc;
+    if (!n_iter || !status) return fail(WCAL_EINVAL, "n_iter and status are required");
+    if (residual && !aligned(residual, plan->prob.n_corr == 4 ? 16 : 8))
+        return fail(WCAL_EINVAL, "residual misaligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (plan->prob.algo == WCAL_STEFCAL) {
+        DiArgs a{};
+        fill_tables_di(plan, a);
+        a.data = reinterpret_cast<const float2*>(data);
+        a.model = reinterpret_cast<const float2*>(model);
+        a.flags = flags;
+        a.gains = reinterpret_cast<float2*>(gains);
+        a.residual = reinterpret_cast<float2*>(residual);
+        a.n_iter = n_iter;
+        a.status = status;
+        a.chi2 = chi2;
+        e = launch_di_solve(plan, a, s);
+    } else {
+        DdArgs a{};
+        fill_tables_dd(plan, a);
+        a.data = reinterpret_cast<const float2*>(data);
+        a.model = reinterpret_cast<const float2*>(model);
+        a.flags = flags;
+        a.gains = reinterpret_cast<float2*>(gains);
+        a.residual = reinterpret_cast<float2*>(residual);
+        a.n_iter = n_iter;
+        a.status = status;
+        a.chi2 = chi2;
+        e = launch_dd_solve(plan, a, s);
+    }
+    return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve launch");
+}
+
+int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
+                    const wcal_c64* gains, wcal_c64* jhj, wcal_c64* jhd, wcal_c64* jhr, int32_t* count,
+                    double* chi2, wcal_c64* residual, void* stream) {
+    g_err.clear();
+    int rc = check_common(plan, data, model, gains);
+    if (rc) return rc;
+    if (!jhj || !jhd || !jhr) return fail(WCAL_EINVAL, "jhj, jhd and jhr are required");
+    if (residual && !aligned(residual, plan->prob.n_corr == 4 ? 16 : 8))
+        return fail(WCAL_EINVAL, "residual misaligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (plan->prob.algo == WCAL_STEFCAL) {
+        DiArgs a{};
+        fill_tables_di(plan, a);
+        a.data = reinterpret_cast<const float2*>(data);
+        a.model = reinterpret_cast<const float2*>(model);
+        a.flags = flags;
+        a.gains_in = reinterpret_cast<const float2*>(gains);
+        a.residual = reinterpret_cast<float2*>(residual);
+        a.chi2 = chi2;
+        a.jhj = reinterpret_cast<float2*>(jhj);
+        a.jhd = reinterpret_cast<float2*>(jhd);
+        a.jhr = reinterpret_cast<float2*>(jhr);
+        a.count = count;
+        e = launch_di_accumulate(plan, a, s);
+    } else {
+        DdArgs a{};
+        fill_tables_dd(plan, a);
+        a.data = reinterpret_cast<const float2*>(data);
+        a.model = reinterpret_cast<const float2*>(model);
+        a.flags = flags;
+        a.gains_in = reinterpret_cast<const float2*>(gains);
+        a.residual = reinterpret_cast<float2*>(residual);
+        a.chi2 = chi2;
+        a.jhj = reinterpret_cast<float2*>(jhj);
+        a.jhd = reinterpret_cast<float2*>(jhd);
+        a.jhr = reinterpret_cast<float2*>(jhr);
+        a.count = count;
+        e = launch_dd_accumulate(plan, a, s);
+    }
+    return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_accumulate launch");
+}
+
+int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
+                  const wcal_c64* gains, wcal_c64* residual, double* chi2, void* stream) {
+    g_err.clear();
+    int rc = check_common(plan, data, model, gains);
+    if (rc) return rc;
+    if (!residual && !chi2) return fail(WCAL_EINVAL, "residual or chi2 is required");
+    if (residual && !aligned(residual, plan->prob.n_corr == 4 ? 16 : 8))
+        return fail(WCAL_EINVAL, "residual misaligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (plan->prob.algo == WCAL_STEFCAL) {
+        DiArgs a{};
+        fill_tables_di(plan, a);
+        a.data = reinterpret_cast<const float2*>(data);
+        a.model = reinterpret_cast<const float2*>(model);
+        a.flags = flags;
+        a.gains_in = reinterpret_cast<const float2*>(gains);
+        a.residual = reinterpret_cast<float2*>(residual);
+        a.chi2 = chi2;
+        e = launch_di_residual(plan, a, s);
+    } else {
+        DdArgs a{};
+        fill_tables_dd(plan, a);
+        a.data = reinterpret_cast<const float2*>(data);
+        a.model = reinterpret_cast<const float2*>(model);
+        a.flags = flags;
+        a.gains_in = reinterpret_cast<const float2*>(gains);
+        a.residual = reinterpret_cast<float2*>(residual);
+        a.chi2 = chi2;
+        e = launch_dd_residual(plan, a, s);
+    }
+    return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_residual launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+"""Python binding of the C ABI in include/wcal.h (ctypes).
+
+Argument marshalling only: every step of the calibration runs in the HIP
+kernels of libwcal.so.  torch tensors supply device memory and the stream.
+The library must have been built (``paper_1502_06974_amd.build``); loading
+fails loudly otherwise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwcal.so")
+
+OK, EINVAL, EINDEX, ESHAPE, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
+CONVERGED, MAXITER, SINGULAR_ANT, NONFINITE = 1, 2, 4, 8
+STEFCAL, COHJONES, ALLJONES = 0, 1, 2
+AVG_FIRST, GN_FIRST, GN_ONLY = 0, 1, 2
+_ALGOS = {"stefcal": STEFCAL, "cohjones": COHJONES, "alljones": ALLJONES}
+_SCHED = {"avg_first": AVG_FIRST, "gn_first": GN_FIRST, "gn_only": GN_ONLY}
+
+# every symbol the header declares
+EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
+           "wcal_plan_rows", "wcal_solve", "wcal_accumulate", "wcal_residual")
+
+
+class WcalError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"wcal error {code}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_ant", C.c_int32), ("n_bl", C.c_int32), ("n_dir", C.c_int32),
+                ("n_corr", C.c_int32), ("n_int", C.c_int32), ("algo", C.c_int32),
+                ("schedule", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libwcal.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build it with paper_1502_06974_amd.build "
+                           "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32p, u8p = C.c_void_p, C.c_void_p, C.c_void_p
+    L.wcal_last_error.restype = C.c_char_p
+    L.wcal_version.restype = C.c_char_p
+    L.wcal_plan_create.argtypes = [C.POINTER(Problem), vp, vp, vp, C.c_int, C.POINTER(C.c_void_p)]
+    L.wcal_plan_create.restype = C.c_int
+    L.wcal_plan_destroy.argtypes = [vp]
+    L.wcal_plan_destroy.restype = None
+    L.wcal_plan_rows.argtypes = [vp]
+    L.wcal_plan_rows.restype = C.c_int64
+    L.wcal_solve.argtypes = [vp] * 9 + [vp]
+    L.wcal_solve.restype = C.c_int
+    L.wcal_accumulate.argtypes = [vp] * 12
+    L.wcal_accumulate.restype = C.c_int
+    L.wcal_residual.argtypes = [vp] * 8
+    L.wcal_residual.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise WcalError(rc, lib().wcal_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A validated calibration problem with its device tables (wraps wcal_plan)."""
+
+    def __init__(self, n_ant: int, ant1, ant2, ns, n_dir: int = 1, n_corr: int = 1,
+                 algo: str = "stefcal", schedule: str = "avg_first", max_iter: int = 100,
+                 tol: float = 1e-6, device: int = 0):
+        L = lib()
+        a1 = torch.as_tensor(ant1, dtype=torch.int32).cpu().contiguous()
+        a2 = torch.as_tensor(ant2, dtype=torch.int32).cpu().contiguous()
+        nsv = torch.as_tensor(ns, dtype=torch.int64).cpu().contiguous()
+        self.prob = Problem(n_ant, a1.numel(), n_dir, n_corr, nsv.numel(), _ALGOS[algo],
+                            _SCHED[schedule], max_iter, tol)
+        self.n_ant, self.n_bl, self.n_dir, self.n_corr, self.n_int = n_ant, a1.numel(), n_dir, n_corr, nsv.numel()
+        self.device = device
+        self._h = C.c_void_p()
+        _check(L.wcal_plan_create(C.byref(self.prob), _ptr(a1), _ptr(a2), _ptr(nsv), device,
+                                  C.byref(self._h)))
+        self.rows = int(L.wcal_plan_rows(self._h))
+
+    def close(self):
+        if self._h:
+            lib().wcal_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- argument checks
+    def _dev(self, t, name, dtype, shape):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _inputs(self, data, model, flags, gains):
+        R, nc, nd = self.rows, self.n_corr, self.n_dir
+        self._dev(data, "data", torch.complex64, (R, nc))
+        self._dev(model, "model", torch.complex64, (R, nd, nc))
+        if flags is not None:
+            self._dev(flags, "flags", torch.uint8, (R,))
+        self._dev(gains, "gains", torch.complex64, (self.n_int, nd, self.n_ant, nc))
+
+    @staticmethod
+    def _stream(stream):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return C.c_void_p(stream.cuda_stream)
+
+    # ---------------------------------------------------------------- calls
+    def solve(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
+              chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True):
+        """wcal_solve: gains are updated in place.  Returns dict of output tensors."""
+        self._inputs(data, model, flags, gains)
+        dev = gains.device
+        if residual is None and want_residual:
+            residual = torch.empty_like(data)
+        if n_iter is None:
+            n_iter = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if chi2 is None and want_chi2:
+            chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
+        self._dev(residual, "residual", torch.complex64, (self.rows, self.n_corr))
+        self._dev(n_iter, "n_iter", torch.int32, (self.n_int,))
+        self._dev(status, "status", torch.int32, (self.n_int,))
+        self._dev(chi2, "chi2", torch.float64, (self.n_int,))
+        _check(lib().wcal_solve(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
+                                _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2),
+                                self._stream(stream)))
+        return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
+
+    def accumulate(self, data, model, flags, gains, residual=None, stream=None,
+                   want_residual: bool = False):
+        """wcal_accumulate: one fused pass at fixed gains."""
+        self._inputs(data, model, flags, gains)
+        dev = gains.device
+        nd, nc, na, ni = self.n_dir, self.n_corr, self.n_ant, self.n_int
+        blk = 4 if nc == 4 else nd * nd
+        jhj = torch.empty(ni, na, blk, dtype=torch.complex64, device=dev)
+        jhd = torch.empty(ni, na, nd * nc, dtype=torch.complex64, device=dev)
+        jhr = torch.empty(ni, na, nd * nc, dtype=torch.complex64, device=dev)
+        count = torch.empty(ni, na, dtype=torch.int32, device=dev)
+        chi2 = torch.empty(ni, dtype=torch.float64, device=dev)
+        if residual is None and want_residual:
+            residual = torch.empty_like(data)
+        self._dev(residual, "residual", torch.complex64, (self.rows, nc))
+        _check(lib().wcal_accumulate(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
+                                     _ptr(jhj), _ptr(jhd), _ptr(jhr), _ptr(count), _ptr(chi2),
+                                     _ptr(residual), self._stream(stream)))
+        return dict(jhj=jhj, jhd=jhd, jhr=jhr, count=count, chi2=chi2, residual=residual)
+
+    def residual(self, data, model, flags, gains, residual=None, stream=None):
+        """wcal_residual: R = D - sum_d G_p M G_q^H and chi^2 per interval."""
+        self._inputs(data, model, flags, gains)
+        if residual is None:
+            residual = torch.empty_like(data)
+        self._dev(residual, "residual", torch.complex64, (self.rows, self.n_corr))
+        chi2 = torch.empty(self.n_int, dtype=torch.float64, device=gains.device)
+        _check(lib().wcal_residual(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
+                                   _ptr(residual), _ptr(chi2), self._stream(stream)))
+        return dict(residual=residual, chi2=chi2)
+
+
+def plan_for(problem, algo: Optional[str] = None, **kw) -> Plan:
+    """Plan for a synthetic ``synth.Problem`` (uses its baseline table and interval sizes)."""
+    if algo is None:
+        algo = "stefcal" if problem.n_dir == 1 else "cohjones"
+    return Plan(problem.n_ant, problem.ant1.cpu(), problem.ant2.cpu(), problem.ns,
+                n_dir=problem.n_dir, n_corr=problem.n_corr, algo=algo, **kw)

@@ -1,0 +1,78 @@
+"""The C-ABI library: it loads, exports every symbol the header declares, and rejects
+invalid problems synchronously (validation runs before any device call)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1502_06974_amd import wcal
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "wcal.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(wcal_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = wcal.lib()
+    syms = header_symbols()
+    assert len(syms) >= 8
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(wcal.EXPORTS)
+    assert b"gfx950" in L.wcal_version()
+
+
+def _create(n_ant, a1, a2, ns, **kw):
+    p = wcal.Problem(n_ant, len(a1), kw.get("n_dir", 1), kw.get("n_corr", 1), len(ns),
+                     kw.get("algo", 0), kw.get("schedule", 0), kw.get("max_iter", 10), kw.get("tol", 1e-6))
+    a1 = np.asarray(a1, np.int32)
+    a2 = np.asarray(a2, np.int32)
+    ns = np.asarray(ns, np.int64)
+    h = C.c_void_p()
+    rc = wcal.lib().wcal_plan_create(C.byref(p), a1.ctypes.data_as(C.c_void_p), a2.ctypes.data_as(C.c_void_p),
+                                     ns.ctypes.data_as(C.c_void_p), 0, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("a1,a2,ns,kw,code", [
+    ([0, 0, 1], [1, 3, 2], [2], {}, wcal.EINDEX),          # antenna 3 out of range (n_ant = 3)
+    ([0, -1, 1], [1, 2, 2], [2], {}, wcal.EINDEX),          # negative index
+    ([0, 1, 1], [1, 1, 2], [2], {}, wcal.EINDEX),           # autocorrelation
+    ([0, 0, 1], [1, 2, 2], [2, 0], {}, wcal.ESHAPE),        # empty interval
+    ([0, 0, 1], [1, 2, 2], [2], {"n_corr": 2}, wcal.EINVAL),
+    ([0, 0, 1], [1, 2, 2], [2], {"n_dir": 2}, wcal.EINVAL),            # StefCal with 2 directions
+    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_corr": 4}, wcal.EINVAL),  # CohJones 2x2
+    ([0, 0, 1], [1, 2, 2], [2], {"max_iter": 0}, wcal.EINVAL),
+    ([0, 0, 1], [1, 2, 2], [2], {"tol": -1.0}, wcal.EINVAL),
+    ([0, 0, 1], [1, 2, 2], [2], {"schedule": 7}, wcal.EINVAL),
+])
+def test_plan_validation_errors(a1, a2, ns, kw, code):
+    rc, h = _create(3, a1, a2, ns, **kw)
+    assert rc == code
+    assert not h.value
+    assert len(wcal.lib().wcal_last_error()) > 0
+
+
+def test_null_arguments():
+    L = wcal.lib()
+    h = C.c_void_p()
+    assert L.wcal_plan_create(None, None, None, None, 0, C.byref(h)) == wcal.EINVAL
+    assert L.wcal_solve(None, None, None, None, None, None, None, None, None, None) == wcal.EINVAL
+    assert L.wcal_accumulate(*([None] * 12)) == wcal.EINVAL
+    assert L.wcal_residual(*([None] * 8)) == wcal.EINVAL
+    assert L.wcal_plan_rows(None) == -1
+    L.wcal_plan_destroy(None)
+
+
+def test_valid_plan_without_gpu_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    rc, h = _create(3, [0, 0, 1], [1, 2, 2], [2])
+    assert rc == wcal.EHIP

@@ -1,0 +1,259 @@
+"""GPU parity of the StefCal path (scalar and 2x2) against the CPU oracle, through the C ABI.
+
+Tolerances: solved gains within 1e-5 relative (after the global-phase alignment when the
+two sides converge independently); per-antenna sums of one pass within 2e-5 of the
+block's scale (FP32 accumulation over up to ~1e5 terms); integer outputs (row counts,
+status bits, iteration counts where the decision is structural) and the zeros written
+under flags are compared exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import calib as oc
+from paper_1502_06974_amd import synth, wcal
+from oracle import driver as glue
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def perturbed_gains(P, scale=0.3, seed=0):
+    g = torch.Generator(device=DEV)
+    g.manual_seed(seed)
+    noise = torch.randn(P.g_true.shape, dtype=torch.complex64, device=DEV, generator=g)
+    return (P.g_true + scale * noise).contiguous()
+
+
+def make(kind, n_ant, ns, flag_frac=0.1, seed=0):
+    if kind == "scalar":
+        return synth.scalar_di(n_ant, ns, sigma=0.01, seed=seed, flag_frac=flag_frac, device=DEV)
+    return synth.pol_di(n_ant, ns, sigma=0.01, seed=seed, flag_frac=flag_frac, device=DEV)
+
+
+# ------------------------------------------------------------------ one-pass accumulators
+@pytest.mark.parametrize("kind", ["scalar", "pol"])
+def test_accumulate_parity(kind):
+    log(f"[accumulate] kind={kind}")
+    P = make(kind, 40, [1, 3, 17, 64, 65], flag_frac=0.1, seed=1)
+    g = perturbed_gains(P)
+    plan = wcal.plan_for(P)
+    out = plan.accumulate(P.data, P.model, P.flags, g, want_residual=True)
+    torch.cuda.synchronize()
+    gh = g.cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.accumulate(P, k, gh[k])
+        cnt = out["count"][k].cpu().numpy()
+        assert np.array_equal(cnt, o["count"]), k
+        if kind == "scalar":
+            A = out["jhj"][k, :, 0].cpu().numpy()
+            assert np.all(A.imag == 0)
+            assert np.abs(A.real - o["A"]).max() <= 2e-5 * np.abs(o["A"]).max()
+            c = out["jhd"][k, :, 0].cpu().numpy()
+            assert np.abs(c - o["c"]).max() <= 2e-5 * np.abs(o["c"]).max()
+            r = out["jhr"][k, :, 0].cpu().numpy()
+            assert np.abs(r - o["jhr"]).max() <= 2e-5 * np.abs(o["c"]).max()
+        else:
+            Z = out["jhj"][k].cpu().numpy().reshape(-1, 2, 2)
+            assert np.abs(Z - o["Z"]).max() <= 2e-5 * np.abs(o["Z"]).max()
+            N = out["jhd"][k].cpu().numpy().reshape(-1, 2, 2)
+            assert np.abs(N - o["N"]).max() <= 2e-5 * np.abs(o["N"]).max()
+            R = out["jhr"][k].cpu().numpy().reshape(-1, 2, 2)
+            assert np.abs(R - o["jhr"]).max() <= 2e-5 * np.abs(o["N"]).max()
+        iv = P.interval(k)
+        d, m = glue.split(iv, P.n_corr, 1)
+        go = glue.gains_to_oracle(gh[k], P.n_corr, 1)
+        fn = oc.residual_scalar if kind == "scalar" else oc.residual_2x2
+        rr, chi = fn(d, m, iv["p"], iv["q"], iv["flags"], go)
+        a, b = int(P.row_off[k]), int(P.row_off[k + 1])
+        res = out["residual"][a:b].cpu().numpy()
+        rr = rr.reshape(res.shape)
+        assert np.abs(res - rr).max() <= 1e-5 * np.abs(rr).max()
+        assert np.all(res[iv["flags"]] == 0)
+        assert abs(float(out["chi2"][k]) - chi) <= 1e-5 * chi
+
+
+# ------------------------------------------------------------------ solve
+@pytest.mark.parametrize("kind", ["scalar", "pol"])
+@pytest.mark.parametrize("schedule", ["avg_first", "gn_first"])
+def test_solve_lockstep(kind, schedule):
+    """Both sides apply exactly 8 updates from the same start (tol = 0)."""
+    log(f"[lockstep] kind={kind} schedule={schedule}")
+    P = make(kind, 40, [2, 9, 33, 70], flag_frac=0.05, seed=2)
+    g0 = P.unit_gains()
+    plan = wcal.plan_for(P, tol=0.0, max_iter=8, schedule=schedule)
+    out = plan.solve(P.data, P.model, P.flags, g0.clone())
+    torch.cuda.synchronize()
+    g = out["gains"].cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=8, schedule=schedule)
+        go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
+        assert rel(g[k], go) <= 1e-5, (k, rel(g[k], go))
+        assert int(out["n_iter"][k]) == 8 and int(out["status"][k]) == oc.MAXITER
+        assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
+
+
+@pytest.mark.parametrize("kind", ["scalar", "pol"])
+def test_solve_converged(kind):
+    """GPU to tol 1e-6, oracle to 1e-12: same least-squares point within 1e-5 (phase gauge aligned)."""
+    log(f"[converged] kind={kind}")
+    P = make(kind, 40, [1, 4, 30, 66], flag_frac=0.05, seed=3)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=200)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    g = out["gains"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=1e-12, max_iter=2000)
+        go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
+        assert st[k] & oc.CONVERGED
+        e = rel(glue.align(g[k], go, 1), go)
+        assert e <= 1e-5, (k, e)
+
+
+def test_status_bits_exact():
+    """SINGULAR_ANT (antenna with every row flagged keeps its gain bit-for-bit), NONFINITE
+    (NaN in an unflagged row: no update applied) and MAXITER, per interval."""
+    log("[status]")
+    P = make("pol", 12, [5, 5, 5], flag_frac=0.0, seed=4)
+    flags = torch.zeros(P.n_rows, dtype=torch.uint8, device=DEV)
+    a1, a2 = P.ant1.cpu().numpy(), P.ant2.cpu().numpy()
+    bad = np.where((a1 == 3) | (a2 == 3))[0]
+    r0 = int(P.row_off[0])
+    for s in range(5):
+        flags[r0 + s * P.n_bl + torch.as_tensor(bad, device=DEV)] = 1
+    data = P.data.clone()
+    data[int(P.row_off[1]) + 7, 2] = float("nan")
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
+    g0 = P.unit_gains()
+    g0[:, :, 3] = torch.tensor([0.5 + 0.25j, 0.125j, -0.25, 1.5], dtype=torch.complex64)
+    out = plan.solve(data, P.model, flags, g0.clone())
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    ni = out["n_iter"].cpu().numpy()
+    g = out["gains"].cpu().numpy()
+    for k in range(3):
+        Pk = P
+        iv = Pk.interval(k)
+        d, m = glue.split(iv, 4, 1)
+        if k == 1:
+            d = d.copy()
+            d.reshape(-1, 4)[7, 2] = np.nan
+        fl = flags[int(P.row_off[k]):int(P.row_off[k + 1])].cpu().numpy() != 0
+        o = oc.stefcal_2x2(d, m, iv["p"], iv["q"], fl, glue.gains_to_oracle(g0[k].cpu().numpy(), 4, 1),
+                           tol=1e-6, max_iter=100)
+        assert st[k] == o["status"], (k, st[k], o["status"])
+    assert st[0] & oc.SINGULAR_ANT and st[0] & oc.CONVERGED
+    assert np.array_equal(g[0, 0, 3], g0[0, 0, 3].cpu().numpy())
+    assert st[1] == oc.NONFINITE and ni[1] == 0
+    assert np.array_equal(g[1], g0[1].cpu().numpy())
+    assert st[2] == oc.CONVERGED
+    plan1 = wcal.plan_for(P, tol=1e-6, max_iter=1)
+    out1 = plan1.solve(P.data, P.model, None, P.unit_gains())
+    assert np.all(out1["status"].cpu().numpy() == oc.MAXITER)
+    assert np.all(out1["n_iter"].cpu().numpy() == 1)
+
+
+@pytest.mark.parametrize("kind", ["scalar", "pol"])
+def test_garbage_under_flags_is_bit_identical(kind):
+    log(f"[flags] kind={kind}")
+    P = make(kind, 20, [3, 8, 40], flag_frac=0.15, seed=5)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=50)
+    clean = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    d2, m2 = P.data.clone(), P.model.clone()
+    f = P.flags.bool()
+    d2[f] = float("nan")
+    m2[f] = 1e30
+    dirty = plan.solve(d2, m2, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    for key in ("gains", "residual", "n_iter", "status", "chi2"):
+        a, b = clean[key].cpu(), dirty[key].cpu()
+        assert torch.equal(a.view(torch.uint8) if a.is_complex() else a,
+                           b.view(torch.uint8) if b.is_complex() else b), key
+    assert torch.all(dirty["residual"][f] == 0)
+
+
+def test_residual_entry_point():
+    log("[residual]")
+    P = make("pol", 16, [2, 7], flag_frac=0.1, seed=6)
+    g = perturbed_gains(P)
+    plan = wcal.plan_for(P)
+    out = plan.residual(P.data, P.model, P.flags, g)
+    torch.cuda.synchronize()
+    for k in range(P.n_int):
+        iv = P.interval(k)
+        d, m = glue.split(iv, 4, 1)
+        rr, chi = oc.residual_2x2(d, m, iv["p"], iv["q"], iv["flags"],
+                                  glue.gains_to_oracle(g[k].cpu().numpy(), 4, 1))
+        a, b = int(P.row_off[k]), int(P.row_off[k + 1])
+        res = out["residual"][a:b].cpu().numpy().reshape(-1, 2, 2)
+        assert np.abs(res - rr).max() <= 1e-5 * np.abs(rr).max()
+        assert np.all(res[iv["flags"]] == 0)
+        assert abs(float(out["chi2"][k]) - chi) <= 1e-5 * chi
+
+
+# ------------------------------------------------------------------ full-size workloads
+def _check_sampled(P, out, ks, tol_oracle=1e-10):
+    g = out["gains"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    for k in ks:
+        o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=tol_oracle, max_iter=2000)
+        go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
+        e = rel(glue.align(g[k], go, 1), go)
+        log(f"  interval {k}: ns={int(P.ns[k])} gpu_iter={int(out['n_iter'][k])} "
+            f"oracle_iter={o['n_iter']} status={st[k]} err={e:.2e}")
+        assert st[k] & oc.CONVERGED
+        assert e <= 1e-5
+        assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
+
+
+def test_scalar_na27_full():
+    """Na = 27, 351 baselines, one interval of 240 samples, sigma 0.01, unit start."""
+    log("[scalar_na27]")
+    P = synth.workload("scalar_na27", device=DEV)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=200)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    _check_sampled(P, out, [0])
+
+
+def test_pol2x2_na64_full_size_sampled():
+    """The 2x2 workload at full size (1000 ragged intervals, 5% flags) in the benchmark's
+    launch configuration; the largest, smallest and random intervals are checked."""
+    log("[pol2x2_na64] generating")
+    P = synth.workload("pol2x2_na64", device=DEV)
+    log(f"  rows={P.n_rows}")
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains(), want_residual=False)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    log(f"  solved: converged {np.mean(st & 1):.3f}, mean iters {out['n_iter'].float().mean():.2f}")
+    assert np.all(st & oc.CONVERGED)
+    ns = P.ns.numpy()
+    rng = np.random.default_rng(0)
+    ks = sorted({int(np.argmax(ns)), int(np.argmin(ns)), *rng.choice(P.n_int, 3, replace=False).tolist()})
+    _check_sampled(P, out, ks, tol_oracle=1e-9)
+
+
+def test_bandpass_na256_full_size_sampled():
+    """Na = 256, 32640 baselines, 4096 single-sample channel intervals."""
+    log("[bandpass_na256] generating")
+    P = synth.workload("bandpass_na256", device=DEV)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains(), want_residual=False)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    log(f"  solved: converged {np.mean(st & 1):.3f}, mean iters {out['n_iter'].float().mean():.2f}")
+    assert np.all(st & oc.CONVERGED)
+    _check_sampled(P, out, [0, 1234, 2048, 4095])
