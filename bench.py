@@ -73,6 +73,11 @@ def main():
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--mode", default="pass", choices=["pass", "stats"],
+                    help="pass: every update streams all samples (the measured metric); "
+                         "stats: per-baseline statistics once, updates on them")
+    ap.add_argument("--no-alt-mode", action="store_true",
+                    help="skip timing the other solve mode")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -90,7 +95,7 @@ def main():
     P = synth.workload(args.workload, device=dev)
     torch.cuda.synchronize()
     log(f"[bench] rows={P.n_rows} intervals={P.n_int} n_ant={P.n_ant} n_corr={P.n_corr} n_dir={P.n_dir}")
-    plan = wcal.plan_for(P, tol=args.tol, max_iter=args.max_iter)
+    plan = wcal.plan_for(P, tol=args.tol, max_iter=args.max_iter, mode=args.mode)
     g0 = P.unit_gains()
     gains = g0.clone()
     residual = torch.empty_like(P.data)
@@ -107,20 +112,17 @@ def main():
         step()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    plan.profile(True)            # HIP events around every kernel launch of the timed steps
+    plan.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        gains.copy_(g0)
-        ev[i][0].record(stream)
-        plan.solve(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter,
-                   status=status, chi2=chi2)
-        ev[i][1].record(stream)
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.profile(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
 
     rows_k = (P.row_off[1:] - P.row_off[:-1]).to(torch.float64)
     it = n_iter.cpu().to(torch.float64)
@@ -128,12 +130,22 @@ def main():
     vis_iter = float((rows_k * it).sum())
     value = vis_iter / (ms_step * 1e-3)
     bpr = bytes_per_row(P.n_corr, P.n_dir, P.flags is not None)
-    # per-sample passes read D, M, flags; the final pass also writes R
-    alg_bytes = float((rows_k * it).sum()) * bpr + P.n_rows * (bpr + 8 * P.n_corr)
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    resid_bytes = P.n_rows * (bpr + 8 * P.n_corr)
+    if args.mode == "pass":
+        # every update's pass streams D, M and flags of the interval once
+        kcls, kname = "pass", "di_pass_kernel<%d>" % P.n_corr
+        kbytes = float((rows_k * it).sum()) * bpr * args.steps
+    else:
+        kcls, kname = "stats", "di_stats_kernel<%d>" % P.n_corr
+        kbytes = float(P.n_rows) * bpr * args.steps
+    kms, klaunch = prof[kcls]
+    achieved = kbytes / (kms * 1e-3) / 1e9
     conv = float((st & 1).float().mean())
-    log(f"[bench] {ms_step:.3f} ms/step, kernel {kern_ms:.3f} ms, mean iters {float(it.mean()):.2f}, "
-        f"converged {conv:.4f}, {achieved:.1f} GB/s")
+    log(f"[bench] {ms_step:.3f} ms/step, {kname}: {kms / args.steps:.3f} ms/step over "
+        f"{klaunch // args.steps} launches, mean iters {float(it.mean()):.2f}, converged {conv:.4f}, "
+        f"{achieved:.1f} GB/s")
+    log("[bench] per-class ms/step: " + ", ".join(f"{c}={v[0] / args.steps:.3f}({v[1] // args.steps})"
+                                                  for c, v in prof.items()))
 
     out = {
         "metric": METRIC,
@@ -155,6 +167,7 @@ def main():
             "flag_frac": 0.0 if P.flags is None else round(float(P.flags.float().mean()), 4),
         },
         "solve_time_ms": ms_step,
+        "mode": args.mode,
         "mean_iters": float(it.mean()),
         "converged_frac": conv,
         "roofline": {
@@ -164,11 +177,29 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "di_solve_kernel<4>" if P.n_corr == 4 else "di_solve_kernel<1>",
-            "kernel_ms": kern_ms,
-            "alg_bytes_per_launch": alg_bytes,
+            "kernel": kname,
+            "kernel_ms_per_launch": kms / max(klaunch, 1),
+            "launches_per_step": klaunch / args.steps,
+            "alg_bytes_per_launch": kbytes / max(klaunch, 1),
         },
+        "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
+        "solve_effective_GBs": (kbytes / args.steps + resid_bytes) / (ms_step * 1e-3) / 1e9,
     }
+    if not args.no_alt_mode:
+        alt = "stats" if args.mode == "pass" else "pass"
+        plan_alt = wcal.plan_for(P, tol=args.tol, max_iter=args.max_iter, mode=alt)
+        plan, plan_main = plan_alt, plan
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms_alt = (time.perf_counter() - t0) * 1e3 / args.steps
+        out[f"solve_time_ms_{alt}_mode"] = ms_alt
+        out[f"mean_iters_{alt}_mode"] = float(n_iter.cpu().double().mean())
+        log(f"[bench] {alt} mode: {ms_alt:.3f} ms/solve")
+        plan = plan_main
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_budget)

@@ -81,6 +81,14 @@ typedef struct { float re, im; } wcal_c64;
 #define WCAL_GN_FIRST  1   /* GN on even k, average on odd k           */
 #define WCAL_GN_ONLY   2   /* GN on every update                        */
 
+/* solve modes (both give the same updates; Sect. 2.3 sums run over every sample):
+ * PASS  -- every update streams all samples of the interval (per-sample J^H J / J^H D pass);
+ * STATS -- the gain-independent per-baseline sums over samples are formed in one pass and
+ *          every update contracts them with the current gains (cost independent of the
+ *          number of samples per interval). */
+#define WCAL_MODE_PASS  0
+#define WCAL_MODE_STATS 1
+
 /* singular-block threshold: a 2x2 block with det Z <= EPS * Z00 * Z11 or an Nd x Nd
  * Cholesky pivot <= EPS * H_jj is treated as not invertible. */
 #define WCAL_EPS_PIVOT 1e-5
@@ -95,6 +103,7 @@ typedef struct {
     int32_t schedule;  /* WCAL_AVG_FIRST | WCAL_GN_FIRST | WCAL_GN_ONLY */
     int32_t max_iter;  /* maximum number of updates (>= 1)           */
     double  tol;       /* relative parameter-change tolerance (>= 0) */
+    int32_t mode;      /* WCAL_MODE_PASS | WCAL_MODE_STATS                 */
 } wcal_problem;
 
 typedef struct wcal_plan wcal_plan;
@@ -128,8 +137,10 @@ int64_t wcal_plan_rows(const wcal_plan* plan);
  *   n_iter   out    [n_int] updates applied
  *   status   out    [n_int] WCAL_* status bits
  *   chi2     out    [n_int] sum of |R|^2 over unflagged rows (FP64), or NULL
- * The whole batch runs on the device: StefCal in one persistent launch, CohJones /
- * AllJones as a statistics pass, a per-interval solve and a residual pass. */
+ * The whole batch runs on the device with no host synchronisation: in PASS mode each
+ * update is a tiled pass over the rows of the intervals still iterating plus a
+ * per-interval update launch; in STATS mode one statistics pass is followed by one
+ * launch that iterates every interval; both end with a tiled residual pass. */
 int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
                int32_t* n_iter, uint32_t* status, double* chi2, void* stream);
@@ -154,6 +165,21 @@ int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model
 int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                   const uint8_t* flags, const wcal_c64* gains, wcal_c64* residual,
                   double* chi2, void* stream);
+
+/* Kernel timing for benchmarks.  While enabled, every kernel launched by wcal_solve and
+ * wcal_residual on this plan is bracketed by HIP events on the call's stream.
+ * wcal_profile_read waits for those events and returns, per kernel class, the summed
+ * duration in milliseconds and the number of launches since the previous read (or since
+ * enabling), then clears the record.  ms and launches have WCAL_K_COUNT entries. */
+#define WCAL_K_PASS        0   /* per-sample J^H J / J^H D pass (PASS mode)            */
+#define WCAL_K_UPDATE      1   /* per-interval solve, schedule and convergence test    */
+#define WCAL_K_STATS       2   /* per-baseline statistics pass (STATS mode, DD)         */
+#define WCAL_K_SOLVE_STATS 3   /* iterations on the statistics                          */
+#define WCAL_K_RESID       4   /* residual and chi^2 pass                               */
+#define WCAL_K_OTHER       5   /* initialisation and small reductions                  */
+#define WCAL_K_COUNT       6
+int wcal_profile_enable(wcal_plan* plan, int enable);
+int wcal_profile_read(wcal_plan* plan, double* ms, int32_t* launches);
 
 #ifdef __cplusplus
 }

@@ -1,191 +1,149 @@
 // Direction-independent StefCal kernels for gfx950: scalar (n_corr = 1) and 2x2 Jones
-// (n_corr = 4) gains.
+// (n_corr = 4) gains, batched over many solution intervals (Sect. 2.3).
 //
-// One persistent launch solves the whole batch of solution intervals.  Each workgroup
-// pops an interval from a device work queue (intervals pre-sorted by decreasing size),
-// keeps that interval's gains in LDS and runs every update of Sect. 3.1 on it:
-//
-//   pass   : lane <-> baseline b; the lane walks the interval's samples s (rows
-//            s * n_bl + b are consecutive across lanes, so every load is coalesced) and
-//            accumulates, in registers, both sides of the folded row (Eq. JJ:di):
-//              antenna p:  y = m conj(g_q)        A_p += |y|^2,  c_p += conj(y) d
-//              antenna q:  y' = conj(m) conj(g_p) A_q += |y'|^2, c_q += conj(y') conj(d)
-//            (2x2: Y = M G_q^H, Z_p += Y Y^H, N_p += D Y^H and, with X = G_p M,
-//             Z_q += X^H X, N_q += D^H X -- the operator-diagonal blocks of Eq. JHJ:pol
-//             and the matching J^H D).  Gains are per-lane constants over s.
-//   reduce : a segmented wavefront scan over lanes that share an antenna, then one LDS
-//            atomic per run and value (baselines in p-major order share p across a
-//            wavefront, so the p side costs ~1 atomic per wave instead of 64).
-//   solve  : per antenna, in FP64: g = c / A (Eq. stefcal) or G = N Z^-1 (polarized
-//            update, least-squares order); singular blocks keep their gain; the
-//            GN value or the lambda = 1 average (Eq. stefcal-lambda-average) per the
-//            schedule; FP64 relative-change norm for the convergence test.
-//   final  : residual R = D - G_p M G_q^H (flagged rows 0) and chi^2 in FP64.
-//
-// Flags are applied by selection (a flagged row never enters a sum), so non-finite
-// values under a flag cannot leak into the results.
-#include "wcal_internal.h"
+// Per-sample solve (WCAL_MODE_PASS): every update streams all samples of the interval.
+// Each update is two launches:
+//   pass   : a persistent kernel pops tiles (baselines x samples of one interval) from the
+//            list of tiles whose interval is still iterating.  Lane <-> baseline; the lane
+//            walks the tile's samples (rows s * n_bl + b are consecutive across lanes, so
+//            loads are coalesced; several rows are in flight per lane) and accumulates the
+//            gain-independent statistics of its baseline: scalar sum |m|^2 and
+//            sum conj(m) d; 2x2 the outer products sum vec(M) vec(M)^H and
+//            sum vec(D) vec(M)^H.  At the end of the baseline they are contracted with
+//            the current gains into both sides of the folded row (Eq. JJ:di):
+//              antenna p:  A_p += |g_q|^2 sum|m|^2,  c_p += g_q sum conj(m) d
+//              antenna q:  A_q += |g_p|^2 sum|m|^2,  c_q += g_p conj(sum conj(m) d)
+//            (2x2: Z_p += sum M W_q M^H with W_q = G_q^H G_q, N_p += sum D G_q M^H,
+//             Z_q += sum M^H W_p M, N_q += sum D^H G_p M -- the operator-diagonal blocks
+//             of Eq. JHJ:pol and J^H D), i.e. exactly sum Y Y^H and sum D Y^H with
+//            Y = M G_q^H.  A segmented wavefront scan over lanes that share an antenna
+//            feeds per-wavefront LDS slices, folded in fixed order into one per-tile
+//            partial per antenna.
+//   update : one workgroup per iterating interval folds its tiles' partials in tile
+//            order (bit-reproducible), solves every antenna in FP64 -- g = c / A
+//            (Eq. stefcal) or G = N Z^-1 (the least-squares order of the polarized
+//            update) -- applies the GN value or the lambda = 1 average
+//            (Eq. stefcal-lambda-average) per the schedule, evaluates the FP64 relative
+//            change and, if the interval keeps iterating, appends its tiles to the next
+//            list.  Singular blocks keep their gain.
+// Statistics solve (WCAL_MODE_STATS): the statistics above do not depend on the gains,
+// so one pass stores them per baseline and one persistent launch iterates every interval
+// on them (the gains factor out of the sum over samples, as in the cross-direction
+// terms of Sect. 3.2.1).
+// Both modes end with a tiled residual pass R = D - G_p M G_q^H (flagged rows 0) and
+// chi^2 in FP64.  Flags are applied by selection, so non-finite values under a flag
+// cannot leak into any sum.
+#include "di_common.h"
+
+using namespace wcal_dev;
 
 namespace {
 
-constexpr int WAVE = 64;
+// Data and model of one row.
+template <int NC> struct Vis;
+template <> struct Vis<1> { float2 d, m; };
+template <> struct Vis<4> { J2 D, M; };
 
-// ------------------------------------------------------------------ complex helpers
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// a * conj(b)
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
-    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-// conj(a) * b
-__device__ __forceinline__ float2 ccmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
-__device__ __forceinline__ float nrm(float2 a) { return a.x * a.x + a.y * a.y; }
-
-struct J2 { float2 a, b, c, d; };   // 2x2 row-major: [[a, b], [c, d]]
-
-__device__ __forceinline__ J2 mul(const J2& x, const J2& y) {
-    J2 r;
-    r.a = cadd(cmul(x.a, y.a), cmul(x.b, y.c));
-    r.b = cadd(cmul(x.a, y.b), cmul(x.b, y.d));
-    r.c = cadd(cmul(x.c, y.a), cmul(x.d, y.c));
-    r.d = cadd(cmul(x.c, y.b), cmul(x.d, y.d));
-    return r;
-}
-// x * y^H
-__device__ __forceinline__ J2 mulH(const J2& x, const J2& y) {
-    J2 r;
-    r.a = cadd(cmulc(x.a, y.a), cmulc(x.b, y.b));
-    r.b = cadd(cmulc(x.a, y.c), cmulc(x.b, y.d));
-    r.c = cadd(cmulc(x.c, y.a), cmulc(x.d, y.b));
-    r.d = cadd(cmulc(x.c, y.c), cmulc(x.d, y.d));
-    return r;
-}
-// x^H * y
-__device__ __forceinline__ J2 Hmul(const J2& x, const J2& y) {
-    J2 r;
-    r.a = cadd(ccmul(x.a, y.a), ccmul(x.c, y.c));
-    r.b = cadd(ccmul(x.a, y.b), ccmul(x.c, y.d));
-    r.c = cadd(ccmul(x.b, y.a), ccmul(x.d, y.c));
-    r.d = cadd(ccmul(x.b, y.b), ccmul(x.d, y.d));
-    return r;
-}
-__device__ __forceinline__ J2 jsub(const J2& x, const J2& y) {
-    return J2{csub(x.a, y.a), csub(x.b, y.b), csub(x.c, y.c), csub(x.d, y.d)};
+template <int NC>
+__device__ __forceinline__ Vis<NC> load_vis(const DiArgs& a, int64_t row) {
+    if constexpr (NC == 1) return Vis<1>{a.data[row], a.model[row]};
+    else return Vis<4>{load_j2(a.data, row), load_j2(a.model, row)};
 }
 
-__device__ __forceinline__ J2 load_j2(const float2* base, int64_t row) {
-    const float4* p = reinterpret_cast<const float4*>(base) + 2 * row;
-    float4 u = p[0], v = p[1];
-    return J2{make_float2(u.x, u.y), make_float2(u.z, u.w), make_float2(v.x, v.y), make_float2(v.z, v.w)};
-}
-__device__ __forceinline__ void store_j2(float2* base, int64_t row, const J2& x) {
-    float4* p = reinterpret_cast<float4*>(base) + 2 * row;
-    p[0] = make_float4(x.a.x, x.a.y, x.b.x, x.b.y);
-    p[1] = make_float4(x.c.x, x.c.y, x.d.x, x.d.y);
-}
+// Gains of the two antennas of a baseline, constant over the interval's samples.
+template <int NC> struct Pair;
+template <> struct Pair<1> { float2 gp, gq; float gp2, gq2; };
+template <> struct Pair<4> { J2 Gp, Gq; };
 
-// ------------------------------------------------------------------ reductions
-// Segmented inclusive scan across the wavefront over runs of equal `key` (lanes in
-// order), then the last lane of each run adds the run total into acc[key * stride + i].
-// Lanes with key < 0 contribute nothing.  Every lane of the wavefront must call this.
-template <int NV>
-__device__ __forceinline__ void seg_add(int key, float (&v)[NV], float* acc, int stride) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int prev = __shfl_up(key, 1, WAVE);
-    int rs = (lane == 0 || prev != key) ? lane : 0;
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        int t = __shfl_up(rs, off, WAVE);
-        if (lane >= off) rs = max(rs, t);
-    }
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            float t = __shfl_up(v[i], off, WAVE);
-            if (lane - off >= rs) v[i] += t;
+// Both folded rows of one stored row (Eq. JJ:di): the antenna-p terms into vp and the
+// antenna-q terms into vq.  MODE 1 also forms the residual and J^H r.
+template <int NC, int MODE, int NV>
+__device__ __forceinline__ void row_work(const DiArgs& a, const Pair<NC>& g, const Vis<NC>& v, bool fl,
+                                         int64_t row, bool write_res, float (&vp)[NV], float (&vq)[NV],
+                                         double& chi, int& nrow) {
+    if constexpr (NC == 1) {
+        if (!fl) {
+            const float m2 = nrm(v.m);
+            const float2 y = cmulc(v.m, g.gq);      // y_pq = m conj(g_q)
+            const float2 yq = cmul(v.m, g.gp);      // conj(y_qp) = m g_p
+            vp[0] += m2 * g.gq2;
+            vq[0] += m2 * g.gp2;
+            const float2 cp = ccmul(y, v.d);        // conj(y) d
+            const float2 cq = cmulc(yq, v.d);       // conj(y') conj(d)
+            vp[1] += cp.x; vp[2] += cp.y;
+            vq[1] += cq.x; vq[2] += cq.y;
+            if constexpr (MODE == 1) {
+                const float2 r = csub(v.d, cmul(g.gp, y));   // d - g_p m conj(g_q)
+                const float2 rp = ccmul(y, r);
+                const float2 rq = cmulc(yq, r);
+                vp[3] += rp.x; vp[4] += rp.y;
+                vq[3] += rq.x; vq[4] += rq.y;
+                chi += (double)nrm(r);
+                ++nrow;
+                if (write_res) a.residual[row] = r;
+            }
+        } else if (write_res) {
+            a.residual[row] = make_float2(0.f, 0.f);
+        }
+    } else {
+        if (!fl) {
+            const J2 Y = mulH(v.M, g.Gq);   // Y_pq = M G_q^H
+            const J2 X = mul(g.Gp, v.M);    // X = G_p M = Y_qp^H
+            // Z_p += Y Y^H (Hermitian: z00, z11, z01)
+            vp[0] += nrm(Y.a) + nrm(Y.b);
+            vp[1] += nrm(Y.c) + nrm(Y.d);
+            {
+                const float2 z = cadd(cmulc(Y.a, Y.c), cmulc(Y.b, Y.d));
+                vp[2] += z.x; vp[3] += z.y;
+            }
+            // Z_q += X^H X
+            vq[0] += nrm(X.a) + nrm(X.c);
+            vq[1] += nrm(X.b) + nrm(X.d);
+            {
+                const float2 z = cadd(ccmul(X.a, X.b), ccmul(X.c, X.d));
+                vq[2] += z.x; vq[3] += z.y;
+            }
+            // N_p += D Y^H ; N_q += D^H X
+            const J2 Np = mulH(v.D, Y);
+            const J2 Nq = Hmul(v.D, X);
+            vp[4] += Np.a.x; vp[5] += Np.a.y; vp[6] += Np.b.x; vp[7] += Np.b.y;
+            vp[8] += Np.c.x; vp[9] += Np.c.y; vp[10] += Np.d.x; vp[11] += Np.d.y;
+            vq[4] += Nq.a.x; vq[5] += Nq.a.y; vq[6] += Nq.b.x; vq[7] += Nq.b.y;
+            vq[8] += Nq.c.x; vq[9] += Nq.c.y; vq[10] += Nq.d.x; vq[11] += Nq.d.y;
+            if constexpr (MODE == 1) {
+                const J2 R = jsub(v.D, mul(g.Gp, Y));   // D - G_p M G_q^H
+                const J2 Rp = mulH(R, Y);                // R Y^H
+                const J2 Rq = Hmul(R, X);                // R^H X
+                vp[12] += Rp.a.x; vp[13] += Rp.a.y; vp[14] += Rp.b.x; vp[15] += Rp.b.y;
+                vp[16] += Rp.c.x; vp[17] += Rp.c.y; vp[18] += Rp.d.x; vp[19] += Rp.d.y;
+                vq[12] += Rq.a.x; vq[13] += Rq.a.y; vq[14] += Rq.b.x; vq[15] += Rq.b.y;
+                vq[16] += Rq.c.x; vq[17] += Rq.c.y; vq[18] += Rq.d.x; vq[19] += Rq.d.y;
+                chi += (double)(nrm(R.a) + nrm(R.b) + nrm(R.c) + nrm(R.d));
+                ++nrow;
+                if (write_res) store_j2(a.residual, row, R);
+            }
+        } else if (write_res) {
+            const float2 z = make_float2(0.f, 0.f);
+            store_j2(a.residual, row, J2{z, z, z, z});
         }
     }
-    const int next = __shfl_down(key, 1, WAVE);
-    const bool tail = (lane == WAVE - 1) || (next != key);
-    if (tail && key >= 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) atomicAdd(&acc[key * stride + i], v[i]);
-    }
 }
 
-__device__ __forceinline__ void seg_add_int(int key, int v, int* acc) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int prev = __shfl_up(key, 1, WAVE);
-    int rs = (lane == 0 || prev != key) ? lane : 0;
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        int t = __shfl_up(rs, off, WAVE);
-        if (lane >= off) rs = max(rs, t);
-    }
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        int t = __shfl_up(v, off, WAVE);
-        if (lane - off >= rs) v += t;
-    }
-    const int next = __shfl_down(key, 1, WAVE);
-    const bool tail = (lane == WAVE - 1) || (next != key);
-    if (tail && key >= 0) atomicAdd(&acc[key], v);
-}
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);
-    return x;
-}
-
-// Sum of x over the workgroup; `red` holds >= blockDim/64 doubles.  Result valid in every
-// thread.  Contains barriers: call from uniform control flow only.
-__device__ double block_sum(double x, double* red) {
-    x = wave_sum(x);
-    const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    __syncthreads();
-    if ((threadIdx.x & (WAVE - 1)) == 0) red[w] = x;
-    __syncthreads();
-    double t = 0;
-    for (int i = 0; i < nw; ++i) t += red[i];
-    return t;
-}
-
-// acc[0][i] = sum over wavefronts w (in order) of acc[w][i], i < n.  Barrier before return.
-__device__ void fold_waves(float* acc, int n) {
-    const int nw = blockDim.x / WAVE;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        float t = acc[i];
-        for (int w = 1; w < nw; ++w) t += acc[w * n + i];
-        acc[i] = t;
-    }
-    __syncthreads();
-}
-
-// ------------------------------------------------------------------ per-row work
-// Number of floats accumulated per antenna.  MODE 0 = solve (J^H J block + J^H D),
-// MODE 1 = accumulate (adds J^H r).
-template <int NC, int MODE> struct Nv;
-template <> struct Nv<1, 0> { static constexpr int v = 3; };
-template <> struct Nv<1, 1> { static constexpr int v = 5; };
-template <> struct Nv<4, 0> { static constexpr int v = 12; };
-template <> struct Nv<4, 1> { static constexpr int v = 20; };
+// Rows whose loads are issued together before any of them is used (memory-level
+// parallelism per lane).
+// Rows whose loads are issued together before any of them is used; sized so that the
+// accumulate kernel does not spill at its workgroup size.
+template <int NC, int MODE> struct Unroll { static constexpr int u = NC == 1 ? (MODE ? 4 : 8) : (MODE ? 2 : 4); };
 
 // One interval pass over all (baseline, sample) rows; wavefront w accumulates into its
 // own slice acc[w][na][NV] (and cnt[na] in MODE 1), so the later fold over wavefronts in
-// fixed order makes every result bit-reproducible.  In MODE 1 also forms the residual, writes it when
-// requested and returns this thread's chi^2 contribution.
+// fixed order makes every result bit-reproducible.  In MODE 1 also forms the residual,
+// writes it when requested and returns this thread's chi^2 contribution.
 template <int NC, int MODE>
 __device__ double interval_pass(const DiArgs& a, int64_t off, int ns, const float2* G,
                                 float* acc, int* cnt) {
     constexpr int NV = Nv<NC, MODE>::v;
+    constexpr int U = Unroll<NC, MODE>::u;
     const int nbl = a.n_bl;
     const bool has_flags = a.flags != nullptr;
     const bool write_res = (MODE == 1) && a.residual != nullptr;
@@ -201,89 +159,34 @@ __device__ double interval_pass(const DiArgs& a, int64_t off, int ns, const floa
         for (int i = 0; i < NV; ++i) { vp[i] = 0.f; vq[i] = 0.f; }
         int nrow = 0;
         if (act) {
+            Pair<NC> g;
             if constexpr (NC == 1) {
-                const float2 gp = G[p], gq = G[q];
-                const float gp2 = nrm(gp), gq2 = nrm(gq);
-#pragma unroll 4
-                for (int s = 0; s < ns; ++s) {
-                    const int64_t row = off + (int64_t)s * nbl + b;
-                    const float2 d = a.data[row];
-                    const float2 m = a.model[row];
-                    const bool fl = has_flags && a.flags[row] != 0;
-                    if (!fl) {
-                        const float m2 = nrm(m);
-                        const float2 y = cmulc(m, gq);      // y_pq = m conj(g_q)
-                        const float2 yq = cmul(m, gp);      // conj(y_qp) = m g_p
-                        vp[0] += m2 * gq2;
-                        vq[0] += m2 * gp2;
-                        const float2 cp = ccmul(y, d);      // conj(y) d
-                        const float2 cq = cmulc(yq, d);     // conj(y') conj(d)
-                        vp[1] += cp.x; vp[2] += cp.y;
-                        vq[1] += cq.x; vq[2] += cq.y;
-                        if constexpr (MODE == 1) {
-                            const float2 r = csub(d, cmul(gp, y));   // d - g_p m conj(g_q)
-                            const float2 rp = ccmul(y, r);
-                            const float2 rq = cmulc(yq, r);
-                            vp[3] += rp.x; vp[4] += rp.y;
-                            vq[3] += rq.x; vq[4] += rq.y;
-                            chi += (double)nrm(r);
-                            ++nrow;
-                            if (write_res) a.residual[row] = r;
-                        }
-                    } else if (write_res) {
-                        a.residual[row] = make_float2(0.f, 0.f);
-                    }
-                }
+                g.gp = G[p]; g.gq = G[q]; g.gp2 = nrm(g.gp); g.gq2 = nrm(g.gq);
             } else {
-                const J2 Gp{G[4 * p], G[4 * p + 1], G[4 * p + 2], G[4 * p + 3]};
-                const J2 Gq{G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]};
-#pragma unroll 2
-                for (int s = 0; s < ns; ++s) {
-                    const int64_t row = off + (int64_t)s * nbl + b;
-                    const J2 D = load_j2(a.data, row);
-                    const J2 M = load_j2(a.model, row);
-                    const bool fl = has_flags && a.flags[row] != 0;
-                    if (!fl) {
-                        const J2 Y = mulH(M, Gq);    // Y_pq = M G_q^H
-                        const J2 X = mul(Gp, M);     // X = G_p M = Y_qp^H
-                        // Z_p += Y Y^H (Hermitian: z00, z11, z01)
-                        vp[0] += nrm(Y.a) + nrm(Y.b);
-                        vp[1] += nrm(Y.c) + nrm(Y.d);
-                        {
-                            const float2 z = cadd(cmulc(Y.a, Y.c), cmulc(Y.b, Y.d));
-                            vp[2] += z.x; vp[3] += z.y;
-                        }
-                        // Z_q += X^H X
-                        vq[0] += nrm(X.a) + nrm(X.c);
-                        vq[1] += nrm(X.b) + nrm(X.d);
-                        {
-                            const float2 z = cadd(ccmul(X.a, X.b), ccmul(X.c, X.d));
-                            vq[2] += z.x; vq[3] += z.y;
-                        }
-                        // N_p += D Y^H ; N_q += D^H X
-                        const J2 Np = mulH(D, Y);
-                        const J2 Nq = Hmul(D, X);
-                        vp[4] += Np.a.x; vp[5] += Np.a.y; vp[6] += Np.b.x; vp[7] += Np.b.y;
-                        vp[8] += Np.c.x; vp[9] += Np.c.y; vp[10] += Np.d.x; vp[11] += Np.d.y;
-                        vq[4] += Nq.a.x; vq[5] += Nq.a.y; vq[6] += Nq.b.x; vq[7] += Nq.b.y;
-                        vq[8] += Nq.c.x; vq[9] += Nq.c.y; vq[10] += Nq.d.x; vq[11] += Nq.d.y;
-                        if constexpr (MODE == 1) {
-                            const J2 R = jsub(D, mul(Gp, Y));   // D - G_p M G_q^H
-                            const J2 Rp = mulH(R, Y);            // R Y^H
-                            const J2 Rq = Hmul(R, X);            // R^H X
-                            vp[12] += Rp.a.x; vp[13] += Rp.a.y; vp[14] += Rp.b.x; vp[15] += Rp.b.y;
-                            vp[16] += Rp.c.x; vp[17] += Rp.c.y; vp[18] += Rp.d.x; vp[19] += Rp.d.y;
-                            vq[12] += Rq.a.x; vq[13] += Rq.a.y; vq[14] += Rq.b.x; vq[15] += Rq.b.y;
-                            vq[16] += Rq.c.x; vq[17] += Rq.c.y; vq[18] += Rq.d.x; vq[19] += Rq.d.y;
-                            chi += (double)(nrm(R.a) + nrm(R.b) + nrm(R.c) + nrm(R.d));
-                            ++nrow;
-                            if (write_res) store_j2(a.residual, row, R);
-                        }
-                    } else if (write_res) {
-                        const float2 z = make_float2(0.f, 0.f);
-                        store_j2(a.residual, row, J2{z, z, z, z});
-                    }
+                g.Gp = J2{G[4 * p], G[4 * p + 1], G[4 * p + 2], G[4 * p + 3]};
+                g.Gq = J2{G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]};
+            }
+            const int64_t base = off + b;
+            int s = 0;
+            for (; s + U <= ns; s += U) {
+                Vis<NC> v[U];
+                bool fl[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t row = base + (int64_t)(s + u) * nbl;
+                    v[u] = load_vis<NC>(a, row);
+                    fl[u] = has_flags && a.flags[row] != 0;
                 }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    row_work<NC, MODE, NV>(a, g, v[u], fl[u], base + (int64_t)(s + u) * nbl, write_res,
+                                           vp, vq, chi, nrow);
+            }
+            for (; s < ns; ++s) {
+                const int64_t row = base + (int64_t)s * nbl;
+                const Vis<NC> v = load_vis<NC>(a, row);
+                const bool fl = has_flags && a.flags[row] != 0;
+                row_work<NC, MODE, NV>(a, g, v, fl, row, write_res, vp, vq, chi, nrow);
             }
         }
         seg_add<NV>(p, vp, acc, NV);
@@ -296,179 +199,12 @@ __device__ double interval_pass(const DiArgs& a, int64_t off, int ns, const floa
     return chi;
 }
 
-// Residual pass with fixed gains; writes R (if requested) and returns this thread's chi^2.
-template <int NC>
-__device__ double residual_pass(const DiArgs& a, int64_t off, int ns, const float2* G) {
-    const int nbl = a.n_bl;
-    const bool has_flags = a.flags != nullptr;
-    float2* res = a.residual;
-    double chi = 0.0;
-    for (int b = threadIdx.x; b < nbl; b += blockDim.x) {
-        const int p = a.ant1[b], q = a.ant2[b];
-        float part = 0.f;
-        if constexpr (NC == 1) {
-            const float2 gp = G[p], gq = G[q];
-#pragma unroll 4
-            for (int s = 0; s < ns; ++s) {
-                const int64_t row = off + (int64_t)s * nbl + b;
-                const bool fl = has_flags && a.flags[row] != 0;
-                float2 r = make_float2(0.f, 0.f);
-                if (!fl) {
-                    r = csub(a.data[row], cmul(gp, cmulc(a.model[row], gq)));
-                    part += nrm(r);
-                }
-                if (res) res[row] = r;
-            }
-        } else {
-            const J2 Gp{G[4 * p], G[4 * p + 1], G[4 * p + 2], G[4 * p + 3]};
-            const J2 Gq{G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]};
-#pragma unroll 2
-            for (int s = 0; s < ns; ++s) {
-                const int64_t row = off + (int64_t)s * nbl + b;
-                const bool fl = has_flags && a.flags[row] != 0;
-                const float2 z = make_float2(0.f, 0.f);
-                J2 R{z, z, z, z};
-                if (!fl) {
-                    R = jsub(load_j2(a.data, row), mul(Gp, mulH(load_j2(a.model, row), Gq)));
-                    part += nrm(R.a) + nrm(R.b) + nrm(R.c) + nrm(R.d);
-                }
-                if (res) store_j2(res, row, R);
-            }
-        }
-        chi += (double)part;
-    }
-    return chi;
-}
 
-__device__ __forceinline__ bool avg_step(int k, int schedule) {
-    return schedule == WCAL_AVG_FIRST ? (k % 2 == 0) : schedule == WCAL_GN_FIRST ? (k % 2 == 1) : false;
-}
-
-// Per-antenna GN value in FP64.  Returns false when the block is singular (gain kept).
-template <int NC>
-__device__ bool gn_value(const float* ac, const float2* g, double (&gh)[2 * NC], bool& finite) {
-    if constexpr (NC == 1) {
-        const double A = ac[0], cr = ac[1], ci = ac[2];
-        finite = isfinite(A) && isfinite(cr) && isfinite(ci);
-        if (!(A > 0.0)) { gh[0] = g[0].x; gh[1] = g[0].y; return false; }
-        gh[0] = cr / A; gh[1] = ci / A;
-        return true;
-    } else {
-        bool fin = true;
-#pragma unroll
-        for (int i = 0; i < 12; ++i) fin = fin && isfinite(ac[i]);
-        finite = fin;
-        const double z00 = ac[0], z11 = ac[1], zr = ac[2], zi = ac[3];
-        const double det = z00 * z11 - (zr * zr + zi * zi);
-        if (!(z00 > 0.0) || !(det > WCAL_EPS_PIVOT * z00 * z11)) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { gh[2 * i] = g[i].x; gh[2 * i + 1] = g[i].y; }
-            return false;
-        }
-        const double inv = 1.0 / det;
-        // Z^-1 = [[z11, -z01], [-conj(z01), z00]] / det ; G = N Z^-1
-        const double nar = ac[4], nai = ac[5], nbr = ac[6], nbi = ac[7];
-        const double ncr = ac[8], nci = ac[9], ndr = ac[10], ndi = ac[11];
-        // row 0: [na, nb] ; row 1: [nc, nd]
-        // G00 = na z11 - nb conj(z01) ; G01 = -na z01 + nb z00
-        gh[0] = (nar * z11 - (nbr * zr + nbi * zi)) * inv;
-        gh[1] = (nai * z11 - (nbi * zr - nbr * zi)) * inv;
-        gh[2] = (-(nar * zr - nai * zi) + nbr * z00) * inv;
-        gh[3] = (-(nar * zi + nai * zr) + nbi * z00) * inv;
-        gh[4] = (ncr * z11 - (ndr * zr + ndi * zi)) * inv;
-        gh[5] = (nci * z11 - (ndi * zr - ndr * zi)) * inv;
-        gh[6] = (-(ncr * zr - nci * zi) + ndr * z00) * inv;
-        gh[7] = (-(ncr * zi + nci * zr) + ndi * z00) * inv;
-        return true;
-    }
-}
-
-struct Ctl {
-    int k;
-    int flag;
-};
+// Workgroup size of the one-pass accumulate kernel: scalar 1024 threads, 2x2 512.
+template <int NC> struct AccBlock { static constexpr int v = NC == 1 ? 1024 : 512; };
 
 template <int NC>
-__global__ void __launch_bounds__(256) di_solve_kernel(DiArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int NV = Nv<NC, 0>::v;
-    const int na = a.n_ant;
-    float2* G = reinterpret_cast<float2*>(smem);
-    float2* Gn = G + na * NC;
-    float* acc = reinterpret_cast<float*>(Gn + na * NC);
-    __shared__ double red[16];
-    __shared__ int s_k;
-    __shared__ int s_bad, s_sing;
-
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_k = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int idx = s_k;
-        if (idx >= a.n_int) break;
-        const int k = a.order[idx];
-        const int64_t off = a.row_off[k];
-        const int ns = a.ns[k];
-        float2* gk = a.gains + (int64_t)k * na * NC;
-        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) G[i] = gk[i];
-        uint32_t status = 0;
-        int n_it = 0;
-        const int nacc = na * NV * (int)(blockDim.x / WAVE);
-        for (int it = 0; it < a.max_iter; ++it) {
-            for (int i = threadIdx.x; i < nacc; i += blockDim.x) acc[i] = 0.f;
-            if (threadIdx.x == 0) { s_bad = 0; s_sing = 0; }
-            __syncthreads();
-            interval_pass<NC, 0>(a, off, ns, G, acc, nullptr);
-            __syncthreads();
-            fold_waves(acc, na * NV);
-            const bool avg = avg_step(it, a.schedule);
-            double dsum = 0.0, nsum = 0.0;
-            for (int ant = threadIdx.x; ant < na; ant += blockDim.x) {
-                double gh[2 * NC];
-                bool fin = true;
-                const bool ok = gn_value<NC>(acc + ant * NV, G + ant * NC, gh, fin);
-                if (!fin) s_bad = 1;
-                if (!ok) s_sing = 1;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    const float2 go = G[ant * NC + c];
-                    double nr = gh[2 * c], ni = gh[2 * c + 1];
-                    if (avg) { nr = 0.5 * (go.x + nr); ni = 0.5 * (go.y + ni); }
-                    const float2 gn = make_float2((float)nr, (float)ni);
-                    Gn[ant * NC + c] = gn;
-                    const double dr = (double)gn.x - go.x, di = (double)gn.y - go.y;
-                    dsum += dr * dr + di * di;
-                    nsum += (double)gn.x * gn.x + (double)gn.y * gn.y;
-                }
-            }
-            dsum = block_sum(dsum, red);
-            nsum = block_sum(nsum, red);
-            // block_sum ends with a barrier, so s_bad / s_sing are final here
-            if (s_bad) { status |= WCAL_NONFINITE; break; }
-            if (s_sing) status |= WCAL_SINGULAR_ANT;
-            for (int i = threadIdx.x; i < na * NC; i += blockDim.x) G[i] = Gn[i];
-            n_it = it + 1;
-            const double num = sqrt(dsum), den = sqrt(nsum);
-            const double rel = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : num / den;
-            __syncthreads();
-            if (rel < a.tol) { status |= WCAL_CONVERGED; break; }
-        }
-        if (!(status & (WCAL_CONVERGED | WCAL_NONFINITE))) status |= WCAL_MAXITER;
-        __syncthreads();
-        double chi = 0.0;
-        if (a.residual != nullptr || a.chi2 != nullptr) chi = residual_pass<NC>(a, off, ns, G);
-        chi = block_sum(chi, red);
-        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) gk[i] = G[i];
-        if (threadIdx.x == 0) {
-            a.n_iter[k] = n_it;
-            a.status[k] = status;
-            if (a.chi2) a.chi2[k] = chi;
-        }
-    }
-}
-
-template <int NC>
-__global__ void __launch_bounds__(256) di_accumulate_kernel(DiArgs a) {
+__global__ void __launch_bounds__(AccBlock<NC>::v) di_accumulate_kernel(DiArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NV = Nv<NC, 1>::v;
     const int na = a.n_ant;
@@ -521,26 +257,518 @@ __global__ void __launch_bounds__(256) di_accumulate_kernel(DiArgs a) {
     }
 }
 
+
+// ------------------------------------------------------------------ tiled solve
+constexpr int TB = 256;   // workgroup size of every tiled kernel
+
+// Floats of the per-baseline statistics: scalar sum|m|^2, sum conj(m) d; 2x2 the Hermitian
+// 4x4 sum vec(M) vec(M)^H (4 real diagonal + 6 complex upper entries) and the 4x4 complex
+// sum vec(D) vec(M)^H.  vec index e = 2 i + k for entry (i, k) of a 2x2 matrix.
+template <int NC> struct Ns { static constexpr int v = NC == 1 ? 3 : 48; };
+
+// Rows in flight per lane in the tiled passes.
+template <int NC> struct UT { static constexpr int v = NC == 1 ? 8 : 4; };
+
 template <int NC>
-__global__ void __launch_bounds__(256) di_residual_kernel(DiArgs a) {
+__device__ __forceinline__ void stat_add(float (&st)[Ns<NC>::v], const Vis<NC>& v) {
+    if constexpr (NC == 1) {
+        st[0] += nrm(v.m);
+        const float2 t = ccmul(v.m, v.d);        // conj(m) d
+        st[1] += t.x; st[2] += t.y;
+    } else {
+        const float2 M[4] = {v.M.a, v.M.b, v.M.c, v.M.d};
+        const float2 D[4] = {v.D.a, v.D.b, v.D.c, v.D.d};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) st[e] += nrm(M[e]);
+        int u = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int f = e + 1; f < 4; ++f, ++u) {
+                const float2 t = cmulc(M[e], M[f]);   // M_e conj(M_f)
+                st[4 + 2 * u] += t.x; st[5 + 2 * u] += t.y;
+            }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const float2 t = cmulc(D[e], M[f]);   // D_e conj(M_f)
+                st[16 + 2 * (4 * e + f)] += t.x; st[17 + 2 * (4 * e + f)] += t.y;
+            }
+    }
+}
+
+// entry (e, f) of sum vec(M) vec(M)^H from the packed Hermitian storage
+__device__ __forceinline__ float2 smm(const float* st, int e, int f) {
+    if (e == f) return make_float2(st[e], 0.f);
+    if (e < f) {
+        const int u = e * (7 - e) / 2 + (f - e - 1);
+        return make_float2(st[4 + 2 * u], st[5 + 2 * u]);
+    }
+    const int u = f * (7 - f) / 2 + (e - f - 1);
+    return make_float2(st[4 + 2 * u], -st[5 + 2 * u]);
+}
+__device__ __forceinline__ float2 sdm(const float* st, int e, int f) {
+    return make_float2(st[16 + 2 * (4 * e + f)], st[17 + 2 * (4 * e + f)]);
+}
+
+// Contract one baseline's statistics with the gains of its antennas: per-antenna
+// contributions in the layout of gn_value (scalar: A, c; 2x2: z00, z11, z01, N).
+template <int NC>
+__device__ __forceinline__ void contract(const float (&st)[Ns<NC>::v], const Pair<NC>& g,
+                                         float (&vp)[Nv<NC, 0>::v], float (&vq)[Nv<NC, 0>::v]) {
+    if constexpr (NC == 1) {
+        const float2 s = make_float2(st[1], st[2]);
+        vp[0] = g.gq2 * st[0];
+        vq[0] = g.gp2 * st[0];
+        const float2 cp = cmul(g.gq, s);
+        const float2 cq = cmulc(g.gp, s);
+        vp[1] = cp.x; vp[2] = cp.y;
+        vq[1] = cq.x; vq[2] = cq.y;
+    } else {
+        const float2 Gp[4] = {g.Gp.a, g.Gp.b, g.Gp.c, g.Gp.d};
+        const float2 Gq[4] = {g.Gq.a, g.Gq.b, g.Gq.c, g.Gq.d};
+        // W = G^H G
+        float2 Wp[4], Wq[4];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                Wp[2 * k + l] = cadd(ccmul(Gp[k], Gp[l]), ccmul(Gp[2 + k], Gp[2 + l]));
+                Wq[2 * k + l] = cadd(ccmul(Gq[k], Gq[l]), ccmul(Gq[2 + k], Gq[2 + l]));
+            }
+        float2 Zp[4], Zq[4], Np[4], Nq[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                float2 zp = make_float2(0.f, 0.f), zq = zp, np = zp, nq = zp;
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int l = 0; l < 2; ++l) {
+                        zp = cadd(zp, cmul(Wq[2 * k + l], smm(st, 2 * i + k, 2 * j + l)));
+                        zq = cadd(zq, cmul(Wp[2 * k + l], smm(st, 2 * l + j, 2 * k + i)));
+                        np = cadd(np, cmul(Gq[2 * k + l], sdm(st, 2 * i + k, 2 * j + l)));
+                        nq = cadd(nq, cmulc(Gp[2 * k + l], sdm(st, 2 * k + i, 2 * l + j)));
+                    }
+                Zp[2 * i + j] = zp; Zq[2 * i + j] = zq; Np[2 * i + j] = np; Nq[2 * i + j] = nq;
+            }
+        vp[0] = Zp[0].x; vp[1] = Zp[3].x; vp[2] = Zp[1].x; vp[3] = Zp[1].y;
+        vq[0] = Zq[0].x; vq[1] = Zq[3].x; vq[2] = Zq[1].x; vq[3] = Zq[1].y;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            vp[4 + 2 * c] = Np[c].x; vp[5 + 2 * c] = Np[c].y;
+            vq[4 + 2 * c] = Nq[c].x; vq[5 + 2 * c] = Nq[c].y;
+        }
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ Pair<NC> pair_from(const float2* G, int p, int q) {
+    Pair<NC> g;
+    if constexpr (NC == 1) {
+        g.gp = G[p]; g.gq = G[q]; g.gp2 = nrm(g.gp); g.gq2 = nrm(g.gq);
+    } else {
+        g.Gp = J2{G[4 * p], G[4 * p + 1], G[4 * p + 2], G[4 * p + 3]};
+        g.Gq = J2{G[4 * q], G[4 * q + 1], G[4 * q + 2], G[4 * q + 3]};
+    }
+    return g;
+}
+
+// Contract the statistics of the lane's current baseline and add both sides into this
+// wavefront's LDS slice.  Every lane of the wavefront must call this.
+template <int NC>
+__device__ __forceinline__ void flush_acc(int p, int q, float (&st)[Ns<NC>::v], const float2* G, float* acc) {
+    constexpr int NVP = Nv<NC, 0>::v;
+    float vp[NVP], vq[NVP];
+    if (p >= 0) {
+        contract<NC>(st, pair_from<NC>(G, p, q), vp, vq);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NVP; ++i) { vp[i] = 0.f; vq[i] = 0.f; }
+    }
+    seg_add<NVP>(p, vp, acc, NVP);
+    seg_add<NVP>(q, vq, acc, NVP);
+#pragma unroll
+    for (int i = 0; i < Ns<NC>::v; ++i) st[i] = 0.f;
+}
+
+// Walk a tile: items j = r * S + s (baseline round r of blockDim lanes, sample s), UT rows
+// in flight per lane.  At each new round the previous round's statistics are handed to
+// `flush(key_b, p, q, st)`; every lane reaches every flush (round changes are uniform).
+template <int NC, typename Flush>
+__device__ __forceinline__ void tile_walk(const DiArgs& a, const Tile& T, Flush flush) {
+    constexpr int U = UT<NC>::v;
+    constexpr int NS = Ns<NC>::v;
+    const int BS = blockDim.x;
+    const int R = (T.b1 - T.b0 + BS - 1) / BS;
+    const int S = T.s1 - T.s0;
+    const int total = R * S;
+    const int64_t off = a.row_off[T.k];
+    const bool has_flags = a.flags != nullptr;
+    float st[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) st[i] = 0.f;
+    int cur_b = -1, cur_p = -1, cur_q = -1;
+    int r = 0, s = T.s0;
+    for (int j0 = 0; j0 < total; j0 += U) {
+        Vis<NC> v[U];
+        bool valid[U], use[U], nr[U];
+        int pp[U], qq[U], bb[U];
+        int rr = r, ss = s;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            nr[u] = ss == T.s0;
+            const int b = T.b0 + rr * BS + (int)threadIdx.x;
+            bb[u] = b;
+            valid[u] = (j0 + u < total) && (b < T.b1);
+            use[u] = false;
+            pp[u] = -1; qq[u] = -1;
+            if (valid[u]) {
+                const int64_t row = off + (int64_t)ss * a.n_bl + b;
+                v[u] = load_vis<NC>(a, row);
+                use[u] = !(has_flags && a.flags[row] != 0);
+                if (nr[u]) { pp[u] = a.ant1[b]; qq[u] = a.ant2[b]; }
+            }
+            if (++ss == T.s1) { ss = T.s0; ++rr; }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (j0 + u >= total) break;
+            if (nr[u]) {
+                if (j0 + u > 0) flush(cur_b, cur_p, cur_q, st);
+                cur_b = valid[u] ? bb[u] : -1;
+                cur_p = pp[u];
+                cur_q = qq[u];
+            }
+            if (use[u]) stat_add<NC>(st, v[u]);
+        }
+        r = rr; s = ss;
+    }
+    if (total > 0) flush(cur_b, cur_p, cur_q, st);
+}
+
+// Residual rows of a tile with the gains in LDS; returns this lane's chi^2 share.
+template <int NC>
+__device__ double tile_residual(const DiArgs& a, const Tile& T, const float2* G) {
+    constexpr int U = UT<NC>::v;
+    const int BS = blockDim.x;
+    const int R = (T.b1 - T.b0 + BS - 1) / BS;
+    const int S = T.s1 - T.s0;
+    const int total = R * S;
+    const int64_t off = a.row_off[T.k];
+    const bool has_flags = a.flags != nullptr;
+    float2* res = a.residual;
+    double chi = 0.0;
+    float part = 0.f;
+    Pair<NC> g{};
+    int r = 0, s = T.s0;
+    for (int j0 = 0; j0 < total; j0 += U) {
+        Vis<NC> v[U];
+        bool valid[U], use[U], nr[U];
+        int pp[U], qq[U];
+        int64_t rows[U];
+        int rr = r, ss = s;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            nr[u] = ss == T.s0;
+            const int b = T.b0 + rr * BS + (int)threadIdx.x;
+            valid[u] = (j0 + u < total) && (b < T.b1);
+            use[u] = false;
+            pp[u] = 0; qq[u] = 0;
+            rows[u] = off + (int64_t)ss * a.n_bl + b;
+            if (valid[u]) {
+                v[u] = load_vis<NC>(a, rows[u]);
+                use[u] = !(has_flags && a.flags[rows[u]] != 0);
+                if (nr[u]) { pp[u] = a.ant1[b]; qq[u] = a.ant2[b]; }
+            }
+            if (++ss == T.s1) { ss = T.s0; ++rr; }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (nr[u] && valid[u]) {
+                g = pair_from<NC>(G, pp[u], qq[u]);
+                chi += (double)part;
+                part = 0.f;
+            }
+            if (!valid[u]) continue;
+            if constexpr (NC == 1) {
+                float2 rv = make_float2(0.f, 0.f);
+                if (use[u]) {
+                    rv = csub(v[u].d, cmul(g.gp, cmulc(v[u].m, g.gq)));
+                    part += nrm(rv);
+                }
+                if (res) res[rows[u]] = rv;
+            } else {
+                const float2 z = make_float2(0.f, 0.f);
+                J2 R2{z, z, z, z};
+                if (use[u]) {
+                    R2 = jsub(v[u].D, mul(g.Gp, mulH(v[u].M, g.Gq)));
+                    part += nrm(R2.a) + nrm(R2.b) + nrm(R2.c) + nrm(R2.d);
+                }
+                if (res) store_j2(res, rows[u], R2);
+            }
+        }
+        r = rr; s = ss;
+    }
+    return chi + (double)part;
+}
+
+// One update of an interval from its folded per-antenna sums acc[na][NVP] (LDS).
+// G holds the current gains (LDS), Gn receives the candidate.  Returns 1 when the
+// interval stops (converged or non-finite), 0 when it keeps iterating; on a non-finite
+// sum G is left unchanged.  Contains barriers: call from uniform control flow.
+template <int NC>
+__device__ int update_step(const DiArgs& a, int it, const float* acc, float2* G, float2* Gn, double* red,
+                           int* s_flags, uint32_t& status) {
+    constexpr int NVP = Nv<NC, 0>::v;
+    const int na = a.n_ant;
+    if (threadIdx.x == 0) { s_flags[0] = 0; s_flags[1] = 0; }
+    __syncthreads();
+    const bool avg = avg_step(it, a.schedule);
+    double dsum = 0.0, nsum = 0.0;
+    for (int ant = threadIdx.x; ant < na; ant += blockDim.x) {
+        double gh[2 * NC];
+        bool fin = true;
+        const bool ok = gn_value<NC>(acc + ant * NVP, G + ant * NC, gh, fin);
+        if (!fin) s_flags[0] = 1;
+        if (!ok) s_flags[1] = 1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const float2 go = G[ant * NC + c];
+            double nr = gh[2 * c], ni = gh[2 * c + 1];
+            if (avg) { nr = 0.5 * (go.x + nr); ni = 0.5 * (go.y + ni); }
+            const float2 gn = make_float2((float)nr, (float)ni);
+            Gn[ant * NC + c] = gn;
+            const double dr = (double)gn.x - go.x, di = (double)gn.y - go.y;
+            dsum += dr * dr + di * di;
+            nsum += (double)gn.x * gn.x + (double)gn.y * gn.y;
+        }
+    }
+    dsum = block_sum(dsum, red);
+    nsum = block_sum(nsum, red);
+    const int bad = s_flags[0], sing = s_flags[1];
+    if (bad) { status |= WCAL_NONFINITE; __syncthreads(); return 1; }
+    if (sing) status |= WCAL_SINGULAR_ANT;
+    for (int i = threadIdx.x; i < na * NC; i += blockDim.x) G[i] = Gn[i];
+    __syncthreads();
+    const double num = sqrt(dsum), den = sqrt(nsum);
+    const double rel = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : num / den;
+    if (rel < a.tol) { status |= WCAL_CONVERGED; return 1; }
+    return 0;
+}
+
+// Counters: ctr[it] pops of the pass at update it, ctr[QOFF + it] tiles listed for it.
+__device__ __forceinline__ int qoff(const DiArgs& a) { return a.max_iter + 2; }
+
+__global__ void __launch_bounds__(TB) di_init_kernel(DiArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.n_int) {
+        a.status[i] = 0;
+        a.n_iter[i] = 0;
+        a.active[i] = 1;
+    }
+    if (i < 2 * (a.max_iter + 2)) a.ctr[i] = 0;
+}
+
+// Zero the work-queue counters only (the residual entry point has no per-interval state).
+__global__ void __launch_bounds__(TB) di_zero_ctr_kernel(DiArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * (a.max_iter + 2)) a.ctr[i] = 0;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(TB) di_pass_kernel(DiArgs a, int it) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NVP = Nv<NC, 0>::v;
+    const int na = a.n_ant;
+    float2* G = reinterpret_cast<float2*>(smem);
+    float* acc = reinterpret_cast<float*>(G + na * NC);
+    __shared__ int s_t;
+    const int nw = blockDim.x / WAVE;
+    const int n = it == 0 ? a.ntiles : a.ctr[qoff(a) + it];
+    const int32_t* list = a.lists + (it & 1) * a.ntiles;
+    float* myacc = acc + (threadIdx.x / WAVE) * na * NVP;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[it], 1);
+        __syncthreads();
+        const int idx = s_t;
+        if (idx >= n) break;
+        const int t = it == 0 ? idx : list[idx];
+        const Tile T = a.tiles[t];
+        const float2* gk = a.gains + (int64_t)T.k * na * NC;
+        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) G[i] = gk[i];
+        for (int i = threadIdx.x; i < nw * na * NVP; i += blockDim.x) acc[i] = 0.f;
+        __syncthreads();
+        tile_walk<NC>(a, T, [&](int, int p, int q, float (&st)[Ns<NC>::v]) {
+            flush_acc<NC>(p, q, st, G, myacc);
+        });
+        __syncthreads();
+        float* out = a.partial + (int64_t)t * na * NVP;
+        for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+            float v = acc[i];
+            for (int w = 1; w < nw; ++w) v += acc[w * na * NVP + i];
+            out[i] = v;
+        }
+    }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(TB) di_update_kernel(DiArgs a, int it) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NVP = Nv<NC, 0>::v;
+    const int k = blockIdx.x;
+    if (!a.active[k]) return;
+    const int na = a.n_ant;
+    float2* G = reinterpret_cast<float2*>(smem);
+    float2* Gn = G + na * NC;
+    float* acc = reinterpret_cast<float*>(Gn + na * NC);
+    __shared__ double red[TB / WAVE];
+    __shared__ int s_flags[2];
+    __shared__ int s_pos;
+    float2* gk = a.gains + (int64_t)k * na * NC;
+    for (int i = threadIdx.x; i < na * NC; i += blockDim.x) G[i] = gk[i];
+    const int t0 = a.tile_off[k], t1 = a.tile_off[k + 1];
+    for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+        float v = 0.f;
+        for (int t = t0; t < t1; ++t) v += a.partial[(int64_t)t * na * NVP + i];
+        acc[i] = v;
+    }
+    __syncthreads();
+    uint32_t status = 0;
+    const int stop = update_step<NC>(a, it, acc, G, Gn, red, s_flags, status);
+    bool finished = stop != 0;
+    if (!(status & WCAL_NONFINITE)) {
+        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) gk[i] = G[i];
+    }
+    if (!finished && it + 1 >= a.max_iter) {
+        status |= WCAL_MAXITER;
+        finished = true;
+    }
+    if (threadIdx.x == 0) {
+        a.status[k] |= status;
+        if (!(status & WCAL_NONFINITE)) a.n_iter[k] = it + 1;
+        if (finished) a.active[k] = 0;
+        else s_pos = atomicAdd(&a.ctr[qoff(a) + it + 1], t1 - t0);
+    }
+    if (!finished) {
+        __syncthreads();
+        int32_t* next = a.lists + ((it + 1) & 1) * a.ntiles;
+        for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) next[s_pos + i] = t0 + i;
+    }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(TB) di_resid_kernel(DiArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int na = a.n_ant;
     float2* G = reinterpret_cast<float2*>(smem);
-    __shared__ double red[16];
+    __shared__ double red[TB / WAVE];
+    __shared__ int s_t;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[2 * (a.max_iter + 2) - 1], 1);
+        __syncthreads();
+        const int t = s_t;
+        if (t >= a.ntiles) break;
+        const Tile T = a.tiles[t];
+        const float2* gk = a.gains_in + (int64_t)T.k * na * NC;
+        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) G[i] = gk[i];
+        __syncthreads();
+        double chi = tile_residual<NC>(a, T, G);
+        chi = block_sum(chi, red);
+        if (threadIdx.x == 0) a.chi_part[t] = chi;
+    }
+}
+
+__global__ void __launch_bounds__(TB) di_chi2_kernel(DiArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n_int || !a.chi2) return;
+    double c = 0.0;
+    for (int t = a.tile_off[k]; t < a.tile_off[k + 1]; ++t) c += a.chi_part[t];
+    a.chi2[k] = c;
+}
+
+// Statistics pass: the statistics of every baseline over all samples of its interval,
+// stored structure-of-arrays per interval: stats[(k * NS + i) * n_bl + b].
+template <int NC>
+__global__ void __launch_bounds__(TB) di_stats_kernel(DiArgs a, const Tile* stiles, int nst) {
+    constexpr int NS = Ns<NC>::v;
+    __shared__ int s_t;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[0], 1);
+        __syncthreads();
+        const int t = s_t;
+        if (t >= nst) break;
+        const Tile T = stiles[t];
+        float* base = a.stats + (int64_t)T.k * NS * a.n_bl;
+        tile_walk<NC>(a, T, [&](int b, int, int, float (&st)[NS]) {
+            if (b >= 0) {
+#pragma unroll
+                for (int i = 0; i < NS; ++i) base[(int64_t)i * a.n_bl + b] = st[i];
+            }
+#pragma unroll
+            for (int i = 0; i < NS; ++i) st[i] = 0.f;
+        });
+    }
+}
+
+// Iterate every interval on its stored statistics (one workgroup per interval, popped
+// from a queue in decreasing-size order); per update the cost is O(n_bl), independent of
+// the number of samples.
+template <int NC>
+__global__ void __launch_bounds__(TB) di_solve_stats_kernel(DiArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NVP = Nv<NC, 0>::v;
+    constexpr int NS = Ns<NC>::v;
+    const int na = a.n_ant;
+    const int nw = blockDim.x / WAVE;
+    float2* G = reinterpret_cast<float2*>(smem);
+    float2* Gn = G + na * NC;
+    float* acc = reinterpret_cast<float*>(Gn + na * NC);
+    float* myacc = acc + (threadIdx.x / WAVE) * na * NVP;
+    __shared__ double red[TB / WAVE];
+    __shared__ int s_flags[2];
     __shared__ int s_k;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_k = atomicAdd(a.queue, 1);
+        if (threadIdx.x == 0) s_k = atomicAdd(&a.ctr[1], 1);
         __syncthreads();
         const int idx = s_k;
         if (idx >= a.n_int) break;
         const int k = a.order[idx];
-        const float2* gk = a.gains_in + (int64_t)k * na * NC;
+        float2* gk = a.gains + (int64_t)k * na * NC;
         for (int i = threadIdx.x; i < na * NC; i += blockDim.x) G[i] = gk[i];
-        __syncthreads();
-        double chi = residual_pass<NC>(a, a.row_off[k], a.ns[k], G);
-        chi = block_sum(chi, red);
-        if (threadIdx.x == 0 && a.chi2) a.chi2[k] = chi;
+        const float* base = a.stats + (int64_t)k * NS * a.n_bl;
+        uint32_t status = 0;
+        int n_it = 0;
+        for (int it = 0; it < a.max_iter; ++it) {
+            for (int i = threadIdx.x; i < nw * na * NVP; i += blockDim.x) acc[i] = 0.f;
+            __syncthreads();
+            for (int b0 = 0; b0 < a.n_bl; b0 += blockDim.x) {
+                const int b = b0 + threadIdx.x;
+                const bool act = b < a.n_bl;
+                float st[NS];
+#pragma unroll
+                for (int i = 0; i < NS; ++i) st[i] = act ? base[(int64_t)i * a.n_bl + b] : 0.f;
+                flush_acc<NC>(act ? a.ant1[b] : -1, act ? a.ant2[b] : -1, st, G, myacc);
+            }
+            __syncthreads();
+            fold_waves(acc, na * NVP);
+            const int stop = update_step<NC>(a, it, acc, G, Gn, red, s_flags, status);
+            if (status & WCAL_NONFINITE) break;
+            n_it = it + 1;
+            if (stop) break;
+        }
+        if (!(status & (WCAL_CONVERGED | WCAL_NONFINITE))) status |= WCAL_MAXITER;
+        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) gk[i] = G[i];
+        if (threadIdx.x == 0) {
+            a.n_iter[k] = n_it;
+            a.status[k] = status;
+        }
     }
 }
 
@@ -548,24 +776,32 @@ __global__ void reset_queue_kernel(int32_t* q) {
     if (threadIdx.x < 4) q[threadIdx.x] = 0;
 }
 
-int grid_for(const wcal_plan* plan, const void* fn, int block, size_t smem) {
+int grid_resident(const wcal_plan* plan, const void* fn, int block, size_t smem, int64_t work) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, smem) != hipSuccess || per_cu < 1)
         per_cu = 1;
     if (plan->wg_per_cu > 0 && plan->wg_per_cu < per_cu) per_cu = plan->wg_per_cu;
     int64_t g = (int64_t)per_cu * plan->n_cu;
-    if (g > plan->prob.n_int) g = plan->prob.n_int;
+    if (g > work) g = work;
     return (int)(g < 1 ? 1 : g);
 }
 
 }  // namespace
 
-size_t di_smem_bytes(int n_ant, int nc, int mode, int block) {
+int di_nvp(int nc) { return nc == 1 ? Nv<1, 0>::v : Nv<4, 0>::v; }
+int di_nstat(int nc) { return nc == 1 ? Ns<1>::v : Ns<4>::v; }
+
+size_t di_accumulate_smem(int n_ant, int nc, int block) {
     const size_t g = (size_t)n_ant * nc * sizeof(float2);
     const size_t nw = (size_t)block / WAVE;
-    if (mode == 0) return 2 * g + nw * n_ant * (nc == 1 ? 3 : 12) * sizeof(float);
-    if (mode == 1) return g + nw * n_ant * (nc == 1 ? 5 : 20) * sizeof(float) + (size_t)n_ant * sizeof(int);
-    return g;
+    return g + nw * n_ant * (nc == 1 ? 5 : 20) * sizeof(float) + (size_t)n_ant * sizeof(int);
+}
+
+static size_t pass_smem(int na, int nc) {
+    return (size_t)na * nc * sizeof(float2) + (size_t)(TB / WAVE) * na * di_nvp(nc) * sizeof(float);
+}
+static size_t update_smem(int na, int nc) {
+    return 2 * (size_t)na * nc * sizeof(float2) + (size_t)(TB / WAVE) * na * di_nvp(nc) * sizeof(float);
 }
 
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
@@ -573,34 +809,88 @@ hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename K>
-static hipError_t launch_persistent(const wcal_plan* plan, K kernel, const DiArgs& a, size_t smem,
-                                    hipStream_t s) {
-    hipError_t e = launch_reset_queue(a.queue, s);
+template <int NC>
+static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
+    const int na = plan->prob.n_ant;
+    prof_begin(plan, WCAL_K_OTHER, s);
+    hipLaunchKernelGGL(di_init_kernel, dim3((std::max(a.n_int, 2 * (a.max_iter + 2)) + TB - 1) / TB), dim3(TB),
+                       0, s, a);
+    prof_end(plan, WCAL_K_OTHER, s);
+    const size_t us = update_smem(na, NC);
+    if (plan->prob.mode == WCAL_MODE_STATS) {
+        const int g1 = grid_resident(plan, reinterpret_cast<const void*>(di_stats_kernel<NC>), TB, 0, plan->nstiles);
+        prof_begin(plan, WCAL_K_STATS, s);
+        hipLaunchKernelGGL(di_stats_kernel<NC>, dim3(g1), dim3(TB), 0, s, a, (const Tile*)plan->d_stiles,
+                           plan->nstiles);
+        prof_end(plan, WCAL_K_STATS, s);
+        const int g2 = grid_resident(plan, reinterpret_cast<const void*>(di_solve_stats_kernel<NC>), TB, us,
+                                     a.n_int);
+        prof_begin(plan, WCAL_K_SOLVE_STATS, s);
+        hipLaunchKernelGGL(di_solve_stats_kernel<NC>, dim3(g2), dim3(TB), us, s, a);
+        prof_end(plan, WCAL_K_SOLVE_STATS, s);
+    } else {
+        const size_t ps = pass_smem(na, NC);
+        const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_pass_kernel<NC>), TB, ps, a.ntiles);
+        for (int it = 0; it < a.max_iter; ++it) {
+            prof_begin(plan, WCAL_K_PASS, s);
+            hipLaunchKernelGGL(di_pass_kernel<NC>, dim3(gp), dim3(TB), ps, s, a, it);
+            prof_end(plan, WCAL_K_PASS, s);
+            prof_begin(plan, WCAL_K_UPDATE, s);
+            hipLaunchKernelGGL(di_update_kernel<NC>, dim3(a.n_int), dim3(TB), us, s, a, it);
+            prof_end(plan, WCAL_K_UPDATE, s);
+        }
+    }
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int block = plan->block;
-    const int grid = grid_for(plan, reinterpret_cast<const void*>(kernel), block, smem);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), smem, s, a);
+    if (a.residual || a.chi2) {
+        DiArgs r = a;
+        r.gains_in = a.gains;
+        const size_t rs = (size_t)na * NC * sizeof(float2);
+        const int gr = grid_resident(plan, reinterpret_cast<const void*>(di_resid_kernel<NC>), TB, rs, a.ntiles);
+        prof_begin(plan, WCAL_K_RESID, s);
+        hipLaunchKernelGGL(di_resid_kernel<NC>, dim3(gr), dim3(TB), rs, s, r);
+        prof_end(plan, WCAL_K_RESID, s);
+        prof_begin(plan, WCAL_K_OTHER, s);
+        hipLaunchKernelGGL(di_chi2_kernel, dim3((a.n_int + TB - 1) / TB), dim3(TB), 0, s, r);
+        prof_end(plan, WCAL_K_OTHER, s);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_di_solve(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
-    const int nc = plan->prob.n_corr;
-    const size_t smem = di_smem_bytes(plan->prob.n_ant, nc, 0, plan->block);
-    return nc == 1 ? launch_persistent(plan, di_solve_kernel<1>, a, smem, s)
-                   : launch_persistent(plan, di_solve_kernel<4>, a, smem, s);
+    return plan->prob.n_corr == 1 ? solve_nc<1>(plan, a, s) : solve_nc<4>(plan, a, s);
 }
 
-hipError_t launch_di_accumulate(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
-    const int nc = plan->prob.n_corr;
-    const size_t smem = di_smem_bytes(plan->prob.n_ant, nc, 1, plan->block);
-    return nc == 1 ? launch_persistent(plan, di_accumulate_kernel<1>, a, smem, s)
-                   : launch_persistent(plan, di_accumulate_kernel<4>, a, smem, s);
+template <int NC>
+static hipError_t residual_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
+    const int na = plan->prob.n_ant;
+    // status / n_iter are not outputs here: only the counters are reset
+    hipLaunchKernelGGL(di_zero_ctr_kernel, dim3((2 * (a.max_iter + 2) + TB - 1) / TB), dim3(TB), 0, s, a);
+    const size_t rs = (size_t)na * NC * sizeof(float2);
+    const int gr = grid_resident(plan, reinterpret_cast<const void*>(di_resid_kernel<NC>), TB, rs, a.ntiles);
+    prof_begin(plan, WCAL_K_RESID, s);
+    hipLaunchKernelGGL(di_resid_kernel<NC>, dim3(gr), dim3(TB), rs, s, a);
+    prof_end(plan, WCAL_K_RESID, s);
+    hipLaunchKernelGGL(di_chi2_kernel, dim3((a.n_int + TB - 1) / TB), dim3(TB), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_di_residual(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
-    const int nc = plan->prob.n_corr;
-    const size_t smem = di_smem_bytes(plan->prob.n_ant, nc, 2, plan->block);
-    return nc == 1 ? launch_persistent(plan, di_residual_kernel<1>, a, smem, s)
-                   : launch_persistent(plan, di_residual_kernel<4>, a, smem, s);
+    return plan->prob.n_corr == 1 ? residual_nc<1>(plan, a, s) : residual_nc<4>(plan, a, s);
+}
+
+template <int NC>
+static hipError_t accumulate_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
+    hipError_t e = launch_reset_queue(a.queue, s);
+    if (e != hipSuccess) return e;
+    const int block = AccBlock<NC>::v;
+    const size_t smem = di_accumulate_smem(plan->prob.n_ant, NC, block);
+    const int grid = grid_resident(plan, reinterpret_cast<const void*>(di_accumulate_kernel<NC>), block, smem,
+                                   plan->prob.n_int);
+    hipLaunchKernelGGL(di_accumulate_kernel<NC>, dim3(grid), dim3(block), smem, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_di_accumulate(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
+    return plan->prob.n_corr == 1 ? accumulate_nc<1>(plan, a, s) : accumulate_nc<4>(plan, a, s);
 }

@@ -44,7 +44,74 @@ int check_common(const wcal_plan* plan, const void* data, const void* model, con
 
 }  // namespace
 
+struct Profiler {
+    struct Rec { int cls; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    std::vector<hipEvent_t> open;   // begin events awaiting their end, per class
+};
+
+void prof_begin(const wcal_plan* plan, int cls, hipStream_t s) {
+    Profiler* p = plan->prof;
+    if (!p) return;
+    if (p->open.size() < WCAL_K_COUNT) p->open.assign(WCAL_K_COUNT, nullptr);
+    hipEvent_t e = p->get();
+    (void)hipEventRecord(e, s);
+    p->open[cls] = e;
+}
+
+void prof_end(const wcal_plan* plan, int cls, hipStream_t s) {
+    Profiler* p = plan->prof;
+    if (!p || p->open.size() < WCAL_K_COUNT || !p->open[cls]) return;
+    hipEvent_t e = p->get();
+    (void)hipEventRecord(e, s);
+    p->recs.push_back({cls, p->open[cls], e});
+    p->open[cls] = nullptr;
+}
+
 extern "C" {
+
+int wcal_profile_enable(wcal_plan* plan, int enable) {
+    g_err.clear();
+    if (!plan) return fail(WCAL_EINVAL, "plan is NULL");
+    if (enable && !plan->prof) plan->prof = new Profiler();
+    if (!enable && plan->prof) {
+        for (auto& r : plan->prof->recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : plan->prof->pool) (void)hipEventDestroy(e);
+        delete plan->prof;
+        plan->prof = nullptr;
+    }
+    return WCAL_OK;
+}
+
+int wcal_profile_read(wcal_plan* plan, double* ms, int32_t* launches) {
+    g_err.clear();
+    if (!plan || !ms || !launches) return fail(WCAL_EINVAL, "NULL argument");
+    for (int i = 0; i < WCAL_K_COUNT; ++i) { ms[i] = 0.0; launches[i] = 0; }
+    if (!plan->prof) return WCAL_OK;
+    for (auto& r : plan->prof->recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(WCAL_EHIP, "hipEventSynchronize failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(WCAL_EHIP, "hipEventElapsedTime failed");
+        ms[r.cls] += t;
+        launches[r.cls] += 1;
+        plan->prof->pool.push_back(r.a);
+        plan->prof->pool.push_back(r.b);
+    }
+    plan->prof->recs.clear();
+    return WCAL_OK;
+}
+
 
 const char* wcal_last_error(void) { return g_err.c_str(); }
 
@@ -61,6 +128,8 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
     if (p.n_corr != 1 && p.n_corr != 4) return fail(WCAL_EINVAL, "n_corr must be 1 or 4");
     if (!(p.tol >= 0.0)) return fail(WCAL_EINVAL, "tol must be >= 0");
     if (p.schedule < WCAL_AVG_FIRST || p.schedule > WCAL_GN_ONLY) return fail(WCAL_EINVAL, "unknown schedule");
+    if (p.mode != WCAL_MODE_PASS && p.mode != WCAL_MODE_STATS) return fail(WCAL_EINVAL, "unknown mode");
+    if (p.max_iter > 100000) return fail(WCAL_ESHAPE, "max_iter > 100000");
     if (p.algo == WCAL_STEFCAL) {
         if (p.n_dir != 1) return fail(WCAL_EINVAL, "StefCal needs n_dir == 1 (use CohJones/AllJones)");
     } else if (p.algo == WCAL_COHJONES || p.algo == WCAL_ALLJONES) {
@@ -102,15 +171,68 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         return fail(WCAL_EHIP, "hipGetDeviceProperties failed");
     }
     plan->n_cu = prop.multiProcessorCount;
-    // the kernels are compiled for at most 256 threads per workgroup
-    if (const char* s = std::getenv("WCAL_BLOCK")) plan->block = std::max(64, std::min(256, atoi(s)) / 64 * 64);
+    if (const char* s = std::getenv("WCAL_BLOCK")) plan->block = std::max(64, std::min(1024, atoi(s)) / 64 * 64);
     if (const char* s = std::getenv("WCAL_WG_PER_CU")) plan->wg_per_cu = atoi(s);
-    // LDS budget of the persistent kernels: per-antenna gains and per-wavefront accumulators
-    if (p.algo == WCAL_STEFCAL && di_smem_bytes(p.n_ant, p.n_corr, 1, plan->block) > 64 * 1024) {
+    if (const char* s = std::getenv("WCAL_TILE_ROWS")) plan->tile_rows = atoi(s);
+    if (plan->tile_rows <= 0) plan->tile_rows = 65536;
+    // LDS budget of the kernels: per-antenna gains and per-wavefront accumulators
+    if (p.algo == WCAL_STEFCAL && di_accumulate_smem(p.n_ant, p.n_corr, p.n_corr == 1 ? 1024 : 512) > 96 * 1024) {
         delete plan;
         return fail(WCAL_ESHAPE, "n_ant too large for the per-interval LDS working set");
     }
+    // tiles: samples per tile S and baselines per tile (a multiple of the 256-lane
+    // workgroup) chosen for about tile_rows rows; interval k owns a contiguous tile range
+    const int TBL = 256;
+    auto round_up = [](int64_t x, int64_t m) { return (x + m - 1) / m * m; };
+    std::vector<Tile> tiles, stiles;
+    std::vector<int32_t> tile_off(p.n_int + 1, 0);
+    for (int32_t k = 0; k < p.n_int; ++k) {
+        const int64_t tr = plan->tile_rows;
+        const int32_t S = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tr / p.n_bl, ns32[k]));
+        const int32_t bc = (int32_t)std::min<int64_t>(std::max<int64_t>(round_up((tr + S - 1) / S, TBL), TBL),
+                                                       round_up(p.n_bl, TBL));
+        for (int32_t s0 = 0; s0 < ns32[k]; s0 += S)
+            for (int32_t b0 = 0; b0 < p.n_bl; b0 += bc)
+                tiles.push_back(Tile{k, b0, std::min(b0 + bc, p.n_bl), s0, std::min(s0 + S, ns32[k])});
+        tile_off[k + 1] = (int32_t)tiles.size();
+        if (p.mode == WCAL_MODE_STATS) {
+            const int32_t bs = (int32_t)std::min<int64_t>(
+                std::max<int64_t>(round_up((tr + ns32[k] - 1) / ns32[k], TBL), TBL), round_up(p.n_bl, TBL));
+            for (int32_t b0 = 0; b0 < p.n_bl; b0 += bs)
+                stiles.push_back(Tile{k, b0, std::min(b0 + bs, p.n_bl), 0, ns32[k]});
+        }
+        if (tiles.size() > (size_t)INT32_MAX / 2) {
+            delete plan;
+            return fail(WCAL_ESHAPE, "too many tiles");
+        }
+    }
+    // statistics tiles in decreasing-size order (longest first)
+    std::stable_sort(stiles.begin(), stiles.end(), [](const Tile& x, const Tile& y) {
+        return (int64_t)(x.b1 - x.b0) * (x.s1 - x.s0) > (int64_t)(y.b1 - y.b0) * (y.s1 - y.s0);
+    });
+    plan->ntiles = (int32_t)tiles.size();
+    plan->nstiles = (int32_t)stiles.size();
+    const int nvp = p.algo == WCAL_STEFCAL ? di_nvp(p.n_corr) : 0;
     hipError_t e = hipSuccess;
+    if ((e = upload(&plan->d_tiles, tiles.data(), tiles.size())) != hipSuccess ||
+        (e = upload(&plan->d_tile_off, tile_off.data(), tile_off.size())) != hipSuccess ||
+        (e = upload(&plan->d_stiles, stiles.data(), stiles.size())) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_lists), 2 * sizeof(int32_t) * std::max(1, plan->ntiles))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_ctr), 2 * sizeof(int32_t) * (p.max_iter + 2))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_partial),
+                       sizeof(float) * std::max<size_t>(1, (size_t)plan->ntiles * p.n_ant * nvp))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_active), sizeof(int32_t) * p.n_int)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_chi_part), sizeof(double) * std::max(1, plan->ntiles))) != hipSuccess) {
+        wcal_plan_destroy(plan);
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tiles");
+    }
+    if (p.algo == WCAL_STEFCAL && p.mode == WCAL_MODE_STATS) {
+        plan->stats_bytes = sizeof(float) * (size_t)p.n_int * p.n_bl * di_nstat(p.n_corr);
+        if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
+            wcal_plan_destroy(plan);
+            return fail(WCAL_ENOMEM, "statistics allocation failed");
+        }
+    }
     if ((e = upload(&plan->d_ant1, ant1_h, p.n_bl)) != hipSuccess ||
         (e = upload(&plan->d_ant2, ant2_h, p.n_bl)) != hipSuccess ||
         (e = upload(&plan->d_row_off, off.data(), off.size())) != hipSuccess ||
@@ -133,9 +255,12 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
 
 void wcal_plan_destroy(wcal_plan* plan) {
     if (!plan) return;
+    wcal_profile_enable(plan, 0);
     (void)hipSetDevice(plan->device);
     for (void* p : {(void*)plan->d_ant1, (void*)plan->d_ant2, (void*)plan->d_row_off, (void*)plan->d_ns,
-                    (void*)plan->d_order, (void*)plan->d_queue, (void*)plan->d_stats})
+                    (void*)plan->d_order, (void*)plan->d_queue, (void*)plan->d_stats, (void*)plan->d_tiles,
+                    (void*)plan->d_tile_off, (void*)plan->d_stiles, (void*)plan->d_lists, (void*)plan->d_ctr,
+                    (void*)plan->d_partial, (void*)plan->d_active, (void*)plan->d_chi_part})
         if (p) (void)hipFree(p);
     delete plan;
 }
@@ -149,6 +274,15 @@ static void fill_tables_di(const wcal_plan* plan, DiArgs& a) {
     a.ns = plan->d_ns;
     a.order = plan->d_order;
     a.queue = plan->d_queue;
+    a.tiles = plan->d_tiles;
+    a.tile_off = plan->d_tile_off;
+    a.ntiles = plan->ntiles;
+    a.lists = plan->d_lists;
+    a.ctr = plan->d_ctr;
+    a.partial = plan->d_partial;
+    a.active = plan->d_active;
+    a.chi_part = plan->d_chi_part;
+    a.stats = plan->d_stats;
     a.n_ant = plan->prob.n_ant;
     a.n_bl = plan->prob.n_bl;
     a.n_int = plan->prob.n_int;

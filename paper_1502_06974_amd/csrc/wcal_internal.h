@@ -7,6 +7,16 @@
 
 #include "wcal.h"
 
+// A tile of one interval's rows: baselines [b0, b1) x samples [s0, s1) of interval k.
+struct Tile {
+    int32_t k, b0, b1, s0, s1;
+};
+
+// Optional per-kernel-class timing with HIP events (benchmarks).
+struct Profiler;
+void prof_begin(const wcal_plan* plan, int cls, hipStream_t s);
+void prof_end(const wcal_plan* plan, int cls, hipStream_t s);
+
 // ------------------------------------------------------------------ plan
 struct wcal_plan {
     wcal_problem prob;
@@ -21,12 +31,26 @@ struct wcal_plan {
     int32_t* d_ns = nullptr;      // [n_int]
     int32_t* d_order = nullptr;   // [n_int] intervals by decreasing size (LPT order)
     int32_t* d_queue = nullptr;   // [4] work-queue counters
-    // DD statistics scratch (plan-owned, sized at creation)
-    float* d_stats = nullptr;
+    // tiles of the per-sample passes (interval k owns tiles [tile_off[k], tile_off[k+1]))
+    Tile* d_tiles = nullptr;
+    int32_t* d_tile_off = nullptr;
+    int32_t ntiles = 0;
+    // statistics tiles (every sample of a baseline chunk) for WCAL_MODE_STATS
+    Tile* d_stiles = nullptr;
+    int32_t nstiles = 0;
+    // per-iteration state of the tiled solve
+    int32_t* d_lists = nullptr;   // [2][ntiles] active tile lists
+    int32_t* d_ctr = nullptr;     // [2][max_iter + 2] pop counters and list lengths
+    float* d_partial = nullptr;   // [ntiles][n_ant][nvp] per-tile per-antenna sums
+    int32_t* d_active = nullptr;  // [n_int]
+    double* d_chi_part = nullptr; // [ntiles]
+    float* d_stats = nullptr;     // per-baseline statistics (STATS mode) or DD scratch
     size_t stats_bytes = 0;
     // launch configuration
-    int block = 256;              // threads per workgroup of the persistent kernels
+    int block = 0;                // threads per workgroup (0 = largest compiled for the kernel)
     int wg_per_cu = 0;            // resident workgroups per CU (0 = occupancy limit)
+    int tile_rows = 0;            // target rows per tile
+    Profiler* prof = nullptr;     // non-null while timing is enabled
 };
 
 // ------------------------------------------------------------------ kernel arguments
@@ -52,6 +76,16 @@ struct DiArgs {
     const int32_t* ns;
     const int32_t* order;
     int32_t* queue;
+    // tiled solve
+    const Tile* tiles;
+    const int32_t* tile_off;
+    int32_t ntiles;
+    int32_t* lists;
+    int32_t* ctr;
+    float* partial;
+    int32_t* active;
+    double* chi_part;
+    float* stats;
     int32_t n_ant, n_bl, n_int, max_iter, schedule;
     double tol;
 };
@@ -85,7 +119,9 @@ struct DdArgs {
 hipError_t launch_di_solve(const wcal_plan* plan, const DiArgs& a, hipStream_t s);
 hipError_t launch_di_accumulate(const wcal_plan* plan, const DiArgs& a, hipStream_t s);
 hipError_t launch_di_residual(const wcal_plan* plan, const DiArgs& a, hipStream_t s);
-size_t di_smem_bytes(int n_ant, int nc, int mode, int block);
+size_t di_accumulate_smem(int n_ant, int nc, int block);
+int di_nvp(int nc);                        // floats per antenna in a tile partial
+int di_nstat(int nc);                      // floats per baseline of the statistics
 
 hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
 hipError_t launch_dd_accumulate(const wcal_plan* plan, const DdArgs& a, hipStream_t s);

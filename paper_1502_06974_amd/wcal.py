@@ -22,10 +22,14 @@ STEFCAL, COHJONES, ALLJONES = 0, 1, 2
 AVG_FIRST, GN_FIRST, GN_ONLY = 0, 1, 2
 _ALGOS = {"stefcal": STEFCAL, "cohjones": COHJONES, "alljones": ALLJONES}
 _SCHED = {"avg_first": AVG_FIRST, "gn_first": GN_FIRST, "gn_only": GN_ONLY}
+MODE_PASS, MODE_STATS = 0, 1
+_MODES = {"pass": MODE_PASS, "stats": MODE_STATS}
 
 # every symbol the header declares
 EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
-           "wcal_plan_rows", "wcal_solve", "wcal_accumulate", "wcal_residual")
+           "wcal_plan_rows", "wcal_solve", "wcal_accumulate", "wcal_residual",
+           "wcal_profile_enable", "wcal_profile_read")
+K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
 class WcalError(RuntimeError):
@@ -37,7 +41,8 @@ class WcalError(RuntimeError):
 class Problem(C.Structure):
     _fields_ = [("n_ant", C.c_int32), ("n_bl", C.c_int32), ("n_dir", C.c_int32),
                 ("n_corr", C.c_int32), ("n_int", C.c_int32), ("algo", C.c_int32),
-                ("schedule", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double)]
+                ("schedule", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("mode", C.c_int32)]
 
 
 _lib = None
@@ -67,6 +72,10 @@ def lib() -> C.CDLL:
     L.wcal_accumulate.restype = C.c_int
     L.wcal_residual.argtypes = [vp] * 8
     L.wcal_residual.restype = C.c_int
+    L.wcal_profile_enable.argtypes = [vp, C.c_int]
+    L.wcal_profile_enable.restype = C.c_int
+    L.wcal_profile_read.argtypes = [vp, vp, vp]
+    L.wcal_profile_read.restype = C.c_int
     _lib = L
     return L
 
@@ -85,13 +94,13 @@ class Plan:
 
     def __init__(self, n_ant: int, ant1, ant2, ns, n_dir: int = 1, n_corr: int = 1,
                  algo: str = "stefcal", schedule: str = "avg_first", max_iter: int = 100,
-                 tol: float = 1e-6, device: int = 0):
+                 tol: float = 1e-6, device: int = 0, mode: str = "pass"):
         L = lib()
         a1 = torch.as_tensor(ant1, dtype=torch.int32).cpu().contiguous()
         a2 = torch.as_tensor(ant2, dtype=torch.int32).cpu().contiguous()
         nsv = torch.as_tensor(ns, dtype=torch.int64).cpu().contiguous()
         self.prob = Problem(n_ant, a1.numel(), n_dir, n_corr, nsv.numel(), _ALGOS[algo],
-                            _SCHED[schedule], max_iter, tol)
+                            _SCHED[schedule], max_iter, tol, _MODES[mode])
         self.n_ant, self.n_bl, self.n_dir, self.n_corr, self.n_int = n_ant, a1.numel(), n_dir, n_corr, nsv.numel()
         self.device = device
         self._h = C.c_void_p()
@@ -109,6 +118,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def profile(self, enable: bool = True):
+        """Bracket every kernel of later solve/residual calls with HIP events."""
+        _check(lib().wcal_profile_enable(self._h, int(enable)))
+
+    def profile_read(self) -> dict:
+        """{class: (total ms, launches)} since the previous read (waits for the events)."""
+        ms = (C.c_double * len(K_CLASSES))()
+        n = (C.c_int32 * len(K_CLASSES))()
+        _check(lib().wcal_profile_read(self._h, ms, n))
+        return {c: (ms[i], n[i]) for i, c in enumerate(K_CLASSES)}
 
     # ---------------------------------------------------------------- argument checks
     def _dev(self, t, name, dtype, shape):

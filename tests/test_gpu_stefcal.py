@@ -85,14 +85,18 @@ def test_accumulate_parity(kind):
 
 
 # ------------------------------------------------------------------ solve
+MODES = ["pass", "stats"]
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("kind", ["scalar", "pol"])
 @pytest.mark.parametrize("schedule", ["avg_first", "gn_first"])
-def test_solve_lockstep(kind, schedule):
+def test_solve_lockstep(kind, schedule, mode):
     """Both sides apply exactly 8 updates from the same start (tol = 0)."""
-    log(f"[lockstep] kind={kind} schedule={schedule}")
+    log(f"[lockstep] kind={kind} schedule={schedule} mode={mode}")
     P = make(kind, 40, [2, 9, 33, 70], flag_frac=0.05, seed=2)
     g0 = P.unit_gains()
-    plan = wcal.plan_for(P, tol=0.0, max_iter=8, schedule=schedule)
+    plan = wcal.plan_for(P, tol=0.0, max_iter=8, schedule=schedule, mode=mode)
     out = plan.solve(P.data, P.model, P.flags, g0.clone())
     torch.cuda.synchronize()
     g = out["gains"].cpu().numpy()
@@ -104,12 +108,13 @@ def test_solve_lockstep(kind, schedule):
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("kind", ["scalar", "pol"])
-def test_solve_converged(kind):
+def test_solve_converged(kind, mode):
     """GPU to tol 1e-6, oracle to 1e-12: same least-squares point within 1e-5 (phase gauge aligned)."""
-    log(f"[converged] kind={kind}")
+    log(f"[converged] kind={kind} mode={mode}")
     P = make(kind, 40, [1, 4, 30, 66], flag_frac=0.05, seed=3)
-    plan = wcal.plan_for(P, tol=1e-6, max_iter=200)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=200, mode=mode)
     out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
     torch.cuda.synchronize()
     g = out["gains"].cpu().numpy()
@@ -122,10 +127,11 @@ def test_solve_converged(kind):
         assert e <= 1e-5, (k, e)
 
 
-def test_status_bits_exact():
+@pytest.mark.parametrize("mode", MODES)
+def test_status_bits_exact(mode):
     """SINGULAR_ANT (antenna with every row flagged keeps its gain bit-for-bit), NONFINITE
     (NaN in an unflagged row: no update applied) and MAXITER, per interval."""
-    log("[status]")
+    log(f"[status] mode={mode}")
     P = make("pol", 12, [5, 5, 5], flag_frac=0.0, seed=4)
     flags = torch.zeros(P.n_rows, dtype=torch.uint8, device=DEV)
     a1, a2 = P.ant1.cpu().numpy(), P.ant2.cpu().numpy()
@@ -135,7 +141,7 @@ def test_status_bits_exact():
         flags[r0 + s * P.n_bl + torch.as_tensor(bad, device=DEV)] = 1
     data = P.data.clone()
     data[int(P.row_off[1]) + 7, 2] = float("nan")
-    plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=100, mode=mode)
     g0 = P.unit_gains()
     g0[:, :, 3] = torch.tensor([0.5 + 0.25j, 0.125j, -0.25, 1.5], dtype=torch.complex64)
     out = plan.solve(data, P.model, flags, g0.clone())
@@ -159,17 +165,18 @@ def test_status_bits_exact():
     assert st[1] == oc.NONFINITE and ni[1] == 0
     assert np.array_equal(g[1], g0[1].cpu().numpy())
     assert st[2] == oc.CONVERGED
-    plan1 = wcal.plan_for(P, tol=1e-6, max_iter=1)
+    plan1 = wcal.plan_for(P, tol=1e-6, max_iter=1, mode=mode)
     out1 = plan1.solve(P.data, P.model, None, P.unit_gains())
     assert np.all(out1["status"].cpu().numpy() == oc.MAXITER)
     assert np.all(out1["n_iter"].cpu().numpy() == 1)
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("kind", ["scalar", "pol"])
-def test_garbage_under_flags_is_bit_identical(kind):
-    log(f"[flags] kind={kind}")
+def test_garbage_under_flags_is_bit_identical(kind, mode):
+    log(f"[flags] kind={kind} mode={mode}")
     P = make(kind, 20, [3, 8, 40], flag_frac=0.15, seed=5)
-    plan = wcal.plan_for(P, tol=1e-6, max_iter=50)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=50, mode=mode)
     clean = plan.solve(P.data, P.model, P.flags, P.unit_gains())
     d2, m2 = P.data.clone(), P.model.clone()
     f = P.flags.bool()
@@ -218,11 +225,12 @@ def _check_sampled(P, out, ks, tol_oracle=1e-10):
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
 
-def test_scalar_na27_full():
+@pytest.mark.parametrize("mode", MODES)
+def test_scalar_na27_full(mode):
     """Na = 27, 351 baselines, one interval of 240 samples, sigma 0.01, unit start."""
-    log("[scalar_na27]")
+    log(f"[scalar_na27] mode={mode}")
     P = synth.workload("scalar_na27", device=DEV)
-    plan = wcal.plan_for(P, tol=1e-6, max_iter=200)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=200, mode=mode)
     out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
     torch.cuda.synchronize()
     _check_sampled(P, out, [0])
@@ -234,26 +242,61 @@ def test_pol2x2_na64_full_size_sampled():
     log("[pol2x2_na64] generating")
     P = synth.workload("pol2x2_na64", device=DEV)
     log(f"  rows={P.n_rows}")
-    plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
-    out = plan.solve(P.data, P.model, P.flags, P.unit_gains(), want_residual=False)
-    torch.cuda.synchronize()
-    st = out["status"].cpu().numpy()
-    log(f"  solved: converged {np.mean(st & 1):.3f}, mean iters {out['n_iter'].float().mean():.2f}")
-    assert np.all(st & oc.CONVERGED)
     ns = P.ns.numpy()
     rng = np.random.default_rng(0)
     ks = sorted({int(np.argmax(ns)), int(np.argmin(ns)), *rng.choice(P.n_int, 3, replace=False).tolist()})
-    _check_sampled(P, out, ks, tol_oracle=1e-9)
+    for mode in MODES:
+        plan = wcal.plan_for(P, tol=1e-6, max_iter=100, mode=mode)
+        out = plan.solve(P.data, P.model, P.flags, P.unit_gains(), want_residual=False)
+        torch.cuda.synchronize()
+        st = out["status"].cpu().numpy()
+        log(f"  mode={mode}: converged {np.mean(st & 1):.3f}, mean iters {out['n_iter'].float().mean():.2f}")
+        assert np.all(st & oc.CONVERGED)
+        _check_sampled(P, out, ks, tol_oracle=1e-9)
+        del plan, out
 
 
 def test_bandpass_na256_full_size_sampled():
     """Na = 256, 32640 baselines, 4096 single-sample channel intervals."""
     log("[bandpass_na256] generating")
     P = synth.workload("bandpass_na256", device=DEV)
-    plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
-    out = plan.solve(P.data, P.model, P.flags, P.unit_gains(), want_residual=False)
+    for mode in MODES:
+        plan = wcal.plan_for(P, tol=1e-6, max_iter=100, mode=mode)
+        out = plan.solve(P.data, P.model, P.flags, P.unit_gains(), want_residual=False)
+        torch.cuda.synchronize()
+        st = out["status"].cpu().numpy()
+        log(f"  mode={mode}: converged {np.mean(st & 1):.3f}, mean iters {out['n_iter'].float().mean():.2f}")
+        assert np.all(st & oc.CONVERGED)
+        _check_sampled(P, out, [0, 1234, 2048, 4095])
+        del plan, out
+
+
+def test_pass_and_stats_modes_agree():
+    """The two solve modes apply the same updates (only the summation order differs)."""
+    log("[modes]")
+    P = make("pol", 24, [1, 6, 50], flag_frac=0.1, seed=8)
+    outs = {}
+    for mode in MODES:
+        plan = wcal.plan_for(P, tol=0.0, max_iter=10, mode=mode)
+        outs[mode] = plan.solve(P.data, P.model, P.flags, P.unit_gains())
     torch.cuda.synchronize()
-    st = out["status"].cpu().numpy()
-    log(f"  solved: converged {np.mean(st & 1):.3f}, mean iters {out['n_iter'].float().mean():.2f}")
-    assert np.all(st & oc.CONVERGED)
-    _check_sampled(P, out, [0, 1234, 2048, 4095])
+    a, b = outs["pass"]["gains"].cpu().numpy(), outs["stats"]["gains"].cpu().numpy()
+    assert rel(a, b) < 1e-5
+    assert torch.equal(outs["pass"]["status"].cpu(), outs["stats"]["status"].cpu())
+
+
+@pytest.mark.parametrize("tile_rows", [300, 5000])
+def test_small_tiles_split_intervals(tile_rows, monkeypatch):
+    """Tiles that split an interval over samples and baselines give the same solve."""
+    log(f"[tiles] tile_rows={tile_rows}")
+    monkeypatch.setenv("WCAL_TILE_ROWS", str(tile_rows))
+    P = make("pol", 40, [1, 7, 64, 65], flag_frac=0.05, seed=9)
+    plan = wcal.plan_for(P, tol=0.0, max_iter=6)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    g = out["gains"].cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=6)
+        go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
+        assert rel(g[k], go) <= 1e-5
+        assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
