@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(AccBlock<NC>::v) di_accumulate_kernel(DiArgs a
         __syncthreads();
         if (threadIdx.x == 0) s_k = atomicAdd(a.queue, 1);
         __syncthreads();
-        const int idx = s_k;
+        const int idx = __builtin_amdgcn_readfirstlane(s_k);
         if (idx >= a.n_int) break;
         const int k = a.order[idx];
         const int64_t off = a.row_off[k];
@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(TB) di_pass_kernel(DiArgs a, int it) {
         __syncthreads();
         if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[it], 1);
         __syncthreads();
-        const int idx = s_t;
+        const int idx = __builtin_amdgcn_readfirstlane(s_t);
         if (idx >= n) break;
         const int t = it == 0 ? idx : list[idx];
         const Tile T = a.tiles[t];
@@ -671,7 +671,7 @@ __global__ void __launch_bounds__(TB) di_resid_kernel(DiArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[2 * (a.max_iter + 2) - 1], 1);
         __syncthreads();
-        const int t = s_t;
+        const int t = __builtin_amdgcn_readfirstlane(s_t);
         if (t >= a.ntiles) break;
         const Tile T = a.tiles[t];
         const float2* gk = a.gains_in + (int64_t)T.k * na * NC;
@@ -701,7 +701,7 @@ __global__ void __launch_bounds__(TB) di_stats_kernel(DiArgs a, const Tile* stil
         __syncthreads();
         if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[0], 1);
         __syncthreads();
-        const int t = s_t;
+        const int t = __builtin_amdgcn_readfirstlane(s_t);
         if (t >= nst) break;
         const Tile T = stiles[t];
         float* base = a.stats + (int64_t)T.k * NS * a.n_bl;
@@ -737,7 +737,7 @@ __global__ void __launch_bounds__(TB) di_solve_stats_kernel(DiArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) s_k = atomicAdd(&a.ctr[1], 1);
         __syncthreads();
-        const int idx = s_k;
+        const int idx = __builtin_amdgcn_readfirstlane(s_k);
         if (idx >= a.n_int) break;
         const int k = a.order[idx];
         float2* gk = a.gains + (int64_t)k * na * NC;

@@ -134,7 +134,7 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         if (p.n_dir != 1) return fail(WCAL_EINVAL, "StefCal needs n_dir == 1 (use CohJones/AllJones)");
     } else if (p.algo == WCAL_COHJONES || p.algo == WCAL_ALLJONES) {
         if (p.n_corr != 1) return fail(WCAL_EINVAL, "CohJones/AllJones are implemented for n_corr == 1");
-        if (p.n_dir > 32) return fail(WCAL_ESHAPE, "n_dir > 32 is not supported");
+        if (p.n_dir > dd_max_dir()) return fail(WCAL_ESHAPE, "n_dir above the supported maximum");
     } else {
         return fail(WCAL_EINVAL, "unknown algorithm");
     }
@@ -171,6 +171,11 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         return fail(WCAL_EHIP, "hipGetDeviceProperties failed");
     }
     plan->n_cu = prop.multiProcessorCount;
+    plan->max_smem = prop.sharedMemPerBlock;
+    if (p.algo != WCAL_STEFCAL && dd_smem_bytes(p.n_dir, p.n_ant) > plan->max_smem) {
+        delete plan;
+        return fail(WCAL_ESHAPE, "n_ant * n_dir too large for the per-interval LDS working set");
+    }
     if (const char* s = std::getenv("WCAL_BLOCK")) plan->block = std::max(64, std::min(1024, atoi(s)) / 64 * 64);
     if (const char* s = std::getenv("WCAL_WG_PER_CU")) plan->wg_per_cu = atoi(s);
     if (const char* s = std::getenv("WCAL_TILE_ROWS")) plan->tile_rows = atoi(s);
@@ -218,7 +223,7 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         (e = upload(&plan->d_tile_off, tile_off.data(), tile_off.size())) != hipSuccess ||
         (e = upload(&plan->d_stiles, stiles.data(), stiles.size())) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void**>(&plan->d_lists), 2 * sizeof(int32_t) * std::max(1, plan->ntiles))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_ctr), 2 * sizeof(int32_t) * (p.max_iter + 2))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_ctr), sizeof(int32_t) * (2 * (p.max_iter + 2) + 16))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void**>(&plan->d_partial),
                        sizeof(float) * std::max<size_t>(1, (size_t)plan->ntiles * p.n_ant * nvp))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void**>(&plan->d_active), sizeof(int32_t) * p.n_int)) != hipSuccess ||
@@ -244,9 +249,23 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
     }
     if (p.algo != WCAL_STEFCAL) {
         plan->stats_bytes = dd_stats_bytes(p);
-        if (plan->stats_bytes && (e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
+        if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
             wcal_plan_destroy(plan);
-            return fail(WCAL_ENOMEM, "statistics scratch allocation failed");
+            return fail(WCAL_ENOMEM, "Gram record allocation failed");
+        }
+        // rows touching each antenna: (baseline, side) in baseline order
+        std::vector<int32_t> ptr(p.n_ant + 1, 0), bl(2 * (size_t)p.n_bl);
+        for (int32_t b = 0; b < p.n_bl; ++b) { ++ptr[ant1_h[b] + 1]; ++ptr[ant2_h[b] + 1]; }
+        for (int32_t i = 0; i < p.n_ant; ++i) ptr[i + 1] += ptr[i];
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int32_t b = 0; b < p.n_bl; ++b) {
+            bl[fill[ant1_h[b]]++] = 2 * b;
+            bl[fill[ant2_h[b]]++] = 2 * b + 1;
+        }
+        if ((e = upload(&plan->d_ant_ptr, ptr.data(), ptr.size())) != hipSuccess ||
+            (e = upload(&plan->d_ant_bl, bl.data(), bl.size())) != hipSuccess) {
+            wcal_plan_destroy(plan);
+            return fail(WCAL_ENOMEM, "antenna tables allocation failed");
         }
     }
     *out = plan;
@@ -260,7 +279,8 @@ void wcal_plan_destroy(wcal_plan* plan) {
     for (void* p : {(void*)plan->d_ant1, (void*)plan->d_ant2, (void*)plan->d_row_off, (void*)plan->d_ns,
                     (void*)plan->d_order, (void*)plan->d_queue, (void*)plan->d_stats, (void*)plan->d_tiles,
                     (void*)plan->d_tile_off, (void*)plan->d_stiles, (void*)plan->d_lists, (void*)plan->d_ctr,
-                    (void*)plan->d_partial, (void*)plan->d_active, (void*)plan->d_chi_part})
+                    (void*)plan->d_partial, (void*)plan->d_active, (void*)plan->d_chi_part,
+                    (void*)plan->d_ant_ptr, (void*)plan->d_ant_bl})
         if (p) (void)hipFree(p);
     delete plan;
 }

@@ -44,8 +44,11 @@ struct wcal_plan {
     float* d_partial = nullptr;   // [ntiles][n_ant][nvp] per-tile per-antenna sums
     int32_t* d_active = nullptr;  // [n_int]
     double* d_chi_part = nullptr; // [ntiles]
-    float* d_stats = nullptr;     // per-baseline statistics (STATS mode) or DD scratch
+    float* d_stats = nullptr;     // per-baseline statistics (STATS mode) or DD Gram records
     size_t stats_bytes = 0;
+    int32_t* d_ant_ptr = nullptr; // [n_ant + 1] CSR: rows of each antenna (DD)
+    int32_t* d_ant_bl = nullptr;  // [2 n_bl]    2 * baseline + side (0: ant1, 1: ant2)
+    size_t max_smem = 65536;      // dynamic LDS limit per workgroup
     // launch configuration
     int block = 0;                // threads per workgroup (0 = largest compiled for the kernel)
     int wg_per_cu = 0;            // resident workgroups per CU (0 = occupancy limit)
@@ -127,5 +130,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a, hipStream_t s
 hipError_t launch_dd_accumulate(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
 hipError_t launch_dd_residual(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
 size_t dd_stats_bytes(const wcal_problem& p);
+size_t dd_smem_bytes(int nd, int na);
+int dd_max_dir();
 
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
