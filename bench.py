@@ -25,6 +25,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "visibility-iterations/s (JHJ+JHr+residual) and solve time to 1e-6 rel. tol."
 HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK_TFS = 157.3     # dense FP32 matrix peak of one MI355X
+MFMA_ISSUED_FLOP_PER_ROW = 3 * 2 * 16 * 16 * 4 / 4   # three 16x16x4 FP32 MFMAs per 4 samples
+
+
+def source_hash() -> str:
+    """sha256 of the library sources (kernels, host code, public header)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1502_06974_amd", "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "wcal.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch from the committed counter runs, if the sources are unchanged."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))[key]
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("src_sha") == source_hash() else None
 
 
 def log(*a):
@@ -35,11 +59,33 @@ def bytes_per_row(n_corr: int, n_dir: int, flags: bool) -> int:
     return 8 * n_corr + 8 * n_corr * n_dir + (1 if flags else 0)
 
 
+def cpu_baseline_dd(P, budget_s: float = 15.0):
+    """CPU oracle CohJones on the first samples of one interval (the oracle forms every
+    row's Nd x Nd product in complex128, so whole 1920-sample intervals do not fit)."""
+    import numpy as np
+    from oracle import calib as oc
+    ns_take = 32
+    iv = P.interval(0)
+    nsel = ns_take * P.n_bl
+    d, m = iv["d"][:nsel, 0], iv["m"][:nsel, :, 0]
+    p, q, fl = iv["p"][:nsel], iv["q"][:nsel], iv["flags"][:nsel]
+    g0 = np.ones((P.n_dir, P.n_ant), complex)
+    t0 = time.perf_counter()
+    o = oc.cohjones(d, m, p, q, fl, g0, tol=1e-6, max_iter=100)
+    dt = time.perf_counter() - t0
+    return dict(value=nsel * o["n_iter"] / dt, unit="vis-iter/s", cores=1, kind="oracle",
+                sample=f"CohJones on the first {ns_take} samples x {P.n_bl} baselines of one interval, "
+                       f"{P.n_dir} directions, unit start, tol 1e-6, {o['n_iter']} updates, one process",
+                seconds=round(dt, 2))
+
+
 def cpu_baseline(P, budget_s: float = 15.0):
     """Time the CPU oracle (as it stands) on whole intervals of the workload until about
     budget_s seconds of CPU work; report visibility-iterations per second."""
     import numpy as np
     from oracle import driver as glue
+    if P.n_dir > 1:
+        return cpu_baseline_dd(P, budget_s)
     rng = np.random.default_rng(0)
     order = rng.permutation(P.n_int)
     vis_it = 0
@@ -78,6 +124,10 @@ def main():
                          "stats: per-baseline statistics once, updates on them")
     ap.add_argument("--no-alt-mode", action="store_true",
                     help="skip timing the other solve mode")
+    ap.add_argument("--out-json", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the timed steps, run one plain device copy of this many MiB "
+                         "(a known-size reference for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -92,10 +142,12 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     log(f"[bench] generating workload {args.workload}")
-    P = synth.workload(args.workload, device=dev)
+    wl_kw = {"n_int": 16} if args.workload == "cohjones_na64" else {}
+    P = synth.workload(args.workload, device=dev, **wl_kw)
     torch.cuda.synchronize()
     log(f"[bench] rows={P.n_rows} intervals={P.n_int} n_ant={P.n_ant} n_corr={P.n_corr} n_dir={P.n_dir}")
-    plan = wcal.plan_for(P, tol=args.tol, max_iter=args.max_iter, mode=args.mode)
+    algo = "stefcal" if P.n_dir == 1 else "cohjones"
+    plan = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=args.mode)
     g0 = P.unit_gains()
     gains = g0.clone()
     residual = torch.empty_like(P.data)
@@ -108,6 +160,15 @@ def main():
         plan.solve(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter,
                    status=status, chi2=chi2)
 
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] reference copy of {args.calib_copy_mb} MiB done")
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -131,15 +192,25 @@ def main():
     value = vis_iter / (ms_step * 1e-3)
     bpr = bytes_per_row(P.n_corr, P.n_dir, P.flags is not None)
     resid_bytes = P.n_rows * (bpr + 8 * P.n_corr)
+    dd = P.n_dir > 1
     if args.mode == "pass":
         # every update's pass streams D, M and flags of the interval once
-        kcls, kname = "pass", "di_pass_kernel<%d>" % P.n_corr
-        kbytes = float((rows_k * it).sum()) * bpr * args.steps
+        kcls = "pass"
+        kname = "dd_gram_kernel<false>" if dd else "di_pass_kernel<%d>" % P.n_corr
+        krows = float((rows_k * it).sum()) * args.steps
     else:
-        kcls, kname = "stats", "di_stats_kernel<%d>" % P.n_corr
-        kbytes = float(P.n_rows) * bpr * args.steps
+        kcls = "stats"
+        kname = "dd_gram_kernel<false>" if dd else "di_stats_kernel<%d>" % P.n_corr
+        krows = float(P.n_rows) * args.steps
+    kbytes = krows * bpr
     kms, klaunch = prof[kcls]
     achieved = kbytes / (kms * 1e-3) / 1e9
+    if dd:
+        # Gram of [M | d]: Nd x Nd complex products and the Nd-vector with the data per row
+        useful = krows * (8 * P.n_dir * P.n_dir + 8 * P.n_dir)
+        issued = krows * MFMA_ISSUED_FLOP_PER_ROW
+        tfs = useful / (kms * 1e-3) / 1e12
+        tfs_issued = issued / (kms * 1e-3) / 1e12
     conv = float((st & 1).float().mean())
     log(f"[bench] {ms_step:.3f} ms/step, {kname}: {kms / args.steps:.3f} ms/step over "
         f"{klaunch // args.steps} launches, mean iters {float(it.mean()):.2f}, converged {conv:.4f}, "
@@ -176,7 +247,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(f"{kname}/{args.workload}"),
             "kernel": kname,
             "kernel_ms_per_launch": kms / max(klaunch, 1),
             "launches_per_step": klaunch / args.steps,
@@ -185,9 +256,25 @@ def main():
         "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
         "solve_effective_GBs": (kbytes / args.steps + resid_bytes) / (ms_step * 1e-3) / 1e9,
     }
+    if dd:
+        out["roofline_hbm"] = out["roofline"]
+        out["roofline"] = {
+            "bound": "mfma",
+            "achieved": tfs,
+            "peak": MFMA_FP32_PEAK_TFS,
+            "unit": "TFLOP/s",
+            "frac": tfs / MFMA_FP32_PEAK_TFS,
+            "traffic": None,
+            "kernel": kname,
+            "kernel_ms_per_launch": kms / max(klaunch, 1),
+            "launches_per_step": klaunch / args.steps,
+            "alg_flops_per_launch": useful / max(klaunch, 1),
+            "issued_TFLOPs": tfs_issued,
+            "issued_frac": tfs_issued / MFMA_FP32_PEAK_TFS,
+        }
     if not args.no_alt_mode:
         alt = "stats" if args.mode == "pass" else "pass"
-        plan_alt = wcal.plan_for(P, tol=args.tol, max_iter=args.max_iter, mode=alt)
+        plan_alt = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=alt)
         plan, plan_main = plan_alt, plan
         step()
         torch.cuda.synchronize()
@@ -203,7 +290,11 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_budget)
-    print(json.dumps(out), flush=True)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out_json:
+        with open(args.out_json, "w") as f:
+            f.write(line + "\n")
 
 
 if __name__ == "__main__":
