@@ -181,6 +181,66 @@ int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
 int wcal_profile_enable(wcal_plan* plan, int enable);
 int wcal_profile_read(wcal_plan* plan, double* ms, int32_t* launches);
 
+/* ------------------------------------------------------------------------------------
+ * Learned warm start.  Not part of the paper's method: a starting point for the solve,
+ * which stays the judge of the result (its convergence test decides, and intervals that
+ * do not converge from the warm start are solved again from unit gains).
+ * ---------------------------------------------------------------------------------- */
+
+/* Knots.  Consecutive intervals (one channel each) are grouped in bins of bin_width
+ * (the last bin may be shorter); bin B = [lo, hi) has the knot interval lo + (hi - lo - 1) / 2.
+ * wcal_bin_knots writes the n_bins = ceil(n_int / bin_width) knot indices to a host array. */
+int wcal_bin_knots(int32_t n_int, int32_t bin_width, int32_t* knots);
+
+/* Coarse pass input: copies the rows of every knot interval of the plan (bins in order, rows
+ * of each knot in order) into compact device arrays, to be solved by a second plan whose
+ * interval sizes are those of the knots.  data_out [rows_k][n_corr], model_out
+ * [rows_k][n_dir][n_corr], flags_out [rows_k] (zeros when flags is NULL; not written when
+ * flags_out is NULL), rows_k = sum of the knots' rows.  The caller owns every buffer. */
+int wcal_gather_knots(const wcal_plan* plan, int32_t bin_width, const wcal_c64* data,
+                      const wcal_c64* model, const uint8_t* flags, wcal_c64* data_out,
+                      wcal_c64* model_out, uint8_t* flags_out, void* stream);
+
+/* Knot values y [n_ant][2 * n_bins] (real parts, then imaginary parts; device) to gains
+ * [n_int][1][n_ant][1] (device): amplitude and phase linear in the interval index between
+ * neighbouring knots, the phase step between two knots being the principal argument of
+ * z_{B+1} conj(z_B) (so steps must stay below pi); constant beyond the outer knots. */
+int wcal_bins_to_gains(int32_t n_int, int32_t n_ant, int32_t bin_width, const float* y,
+                       wcal_c64* gains, void* stream);
+
+/* Gains [n_int][1][n_ant][1] referenced to antenna 0 per interval (times conj(g_0)/|g_0|,
+ * the phase gauge) and averaged over the intervals within halfwidth of each knot (clipped to
+ * [0, n_int)) -> y [n_ant][2 * n_bins].  With bin_width 1 and halfwidth 0 this is the
+ * referenced gains of every interval (the coarse-pass features); with the full solve's
+ * gains it gives the training targets. */
+int wcal_gains_to_bins(int32_t n_int, int32_t n_ant, int32_t bin_width, int32_t halfwidth,
+                       const wcal_c64* gains, float* y, void* stream);
+
+/* Fallback: reset the gains of every interval whose status lacks WCAL_CONVERGED to unit
+ * gains (identity Jones matrices), ready for another wcal_solve. */
+int wcal_reset_unconverged(wcal_plan* plan, const uint32_t* status, wcal_c64* gains, void* stream);
+
+/* Warm-start network: y = tanh(tanh(x W1 + b1) W2 + b2) W3 + b3 (+ x when skip is nonzero,
+ * which needs d_in == d_out) row-wise (FP32), trained on
+ * the mean squared error with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ * Parameters are one flat device array: W1 [d_in][d_hidden], b1, W2 [d_hidden][d_hidden],
+ * b2, W3 [d_hidden][d_out], b3, row-major; the caller supplies initial values.  x, y and
+ * targets are device arrays [batch][d]. */
+typedef struct wcal_mlp wcal_mlp;
+int wcal_mlp_create(int32_t d_in, int32_t d_hidden, int32_t d_out, int32_t max_batch, int32_t skip,
+                    int device, wcal_mlp** out);
+void wcal_mlp_destroy(wcal_mlp* mlp);
+int64_t wcal_mlp_num_params(const wcal_mlp* mlp);
+int wcal_mlp_set_params(wcal_mlp* mlp, const float* params, void* stream);  /* resets Adam */
+int wcal_mlp_get_params(const wcal_mlp* mlp, float* params, void* stream);
+int wcal_mlp_forward(wcal_mlp* mlp, const float* x, int32_t batch, float* y, void* stream);
+/* forward + backward without an update: gradient [num_params] and loss (FP64), either NULL */
+int wcal_mlp_gradients(wcal_mlp* mlp, const float* x, const float* target, int32_t batch,
+                       float* grads, double* loss, void* stream);
+/* one Adam step on the batch; loss (FP64, device) of the batch before the step, or NULL */
+int wcal_mlp_train_step(wcal_mlp* mlp, const float* x, const float* target, int32_t batch,
+                        float lr, double* loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

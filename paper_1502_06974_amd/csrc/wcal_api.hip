@@ -18,6 +18,7 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
+
 int hip_fail(hipError_t e, const char* where) {
     return fail(WCAL_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
@@ -43,6 +44,8 @@ int check_common(const wcal_plan* plan, const void* data, const void* model, con
 }
 
 }  // namespace
+
+int wcal_error(int code, const std::string& msg) { return fail(code, msg); }
 
 struct Profiler {
     struct Rec { int cls; hipEvent_t a, b; };

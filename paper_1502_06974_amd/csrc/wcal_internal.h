@@ -56,6 +56,9 @@ struct wcal_plan {
     Profiler* prof = nullptr;     // non-null while timing is enabled
 };
 
+// record the message returned by wcal_last_error() and return `code`
+int wcal_error(int code, const std::string& msg);
+
 // ------------------------------------------------------------------ kernel arguments
 struct DiArgs {
     const float2* data;      // [rows][nc]

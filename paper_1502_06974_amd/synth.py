@@ -235,11 +235,14 @@ def ragged_ns(n_int: int, t_max: int = 30, f_max: int = 16, seed: int = 0) -> li
 
 def bandpass_di(n_ant: int, n_chan: int, sigma: float = 0.05, seed: int = 0,
                 flag_frac: float = 0.0, device="cpu", dtype=torch.complex64,
-                nu_lo: float = 100e6, nu_hi: float = 200e6, noise: bool = True) -> Problem:
+                nu_lo: float = 100e6, nu_hi: float = 200e6, noise: bool = True,
+                model: Optional[torch.Tensor] = None) -> Problem:
     """Scalar problem with one interval per channel (Ns = 1): per antenna, amplitude is a
     cubic polynomial c0 + c1 x + c2 x^2 + c3 x^3 over x in [-1, 1] across the band with
     c0 = exp(N(0, 0.1^2)), c1..c3 ~ N(0, 0.05^2); phase phi0 + 2 pi tau (nu - nu_mid)
-    with phi0 ~ U(-pi, pi), tau ~ U(-50, 50) ns.  m ~ CN(0,1), noise CN(0, sigma^2)."""
+    with phi0 ~ U(-pi, pi), tau ~ U(-50, 50) ns.  m ~ CN(0,1), noise CN(0, sigma^2).
+    A given `model` [rows, 1, 1] is reused instead of drawing a new one (many observations
+    of the same sky with fresh gains and noise)."""
     gen = _gen(SEED_BASE * 16 + 3 + 7919 * seed, device)
     ant1, ant2 = baselines(n_ant, device)
     ns = torch.ones(n_chan, dtype=torch.int64)
@@ -255,7 +258,10 @@ def bandpass_di(n_ant: int, n_chan: int, sigma: float = 0.05, seed: int = 0,
     amp = c0[None] + c[0][None] * x[:, None] + c[1][None] * x[:, None] ** 2 + c[2][None] * x[:, None] ** 3
     ph = phi0[None] + 2 * math.pi * tau[None] * (nu[:, None] - nu_mid)
     gains = torch.polar(amp, ph).to(dtype).view(n_chan, 1, n_ant, 1)
-    model = _cn((rows, 1, 1), 1.0, gen, device, dtype)
+    if model is None:
+        model = _cn((rows, 1, 1), 1.0, gen, device, dtype)
+    else:
+        assert tuple(model.shape) == (rows, 1, 1)
     return _finish(n_ant, 1, 1, ant1, ant2, ns, model, gains, sigma, flag_frac, gen, device,
                    dtype, dict(kind="bandpass_di", sigma=sigma, seed=seed, nu=nu.cpu()), noise)
 

@@ -28,7 +28,10 @@ _MODES = {"pass": MODE_PASS, "stats": MODE_STATS}
 # every symbol the header declares
 EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
            "wcal_plan_rows", "wcal_solve", "wcal_accumulate", "wcal_residual",
-           "wcal_profile_enable", "wcal_profile_read")
+           "wcal_profile_enable", "wcal_profile_read", "wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains",
+           "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
+           "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
+           "wcal_mlp_gradients", "wcal_mlp_train_step")
 K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
@@ -76,6 +79,26 @@ def lib() -> C.CDLL:
     L.wcal_profile_enable.restype = C.c_int
     L.wcal_profile_read.argtypes = [vp, vp, vp]
     L.wcal_profile_read.restype = C.c_int
+    L.wcal_bin_knots.argtypes = [C.c_int32, C.c_int32, vp]
+    L.wcal_gather_knots.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    L.wcal_bins_to_gains.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+    L.wcal_gains_to_bins.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+    L.wcal_reset_unconverged.argtypes = [vp, vp, vp, vp]
+    L.wcal_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int,
+                                  C.POINTER(C.c_void_p)]
+    L.wcal_mlp_destroy.argtypes = [vp]
+    L.wcal_mlp_destroy.restype = None
+    L.wcal_mlp_num_params.argtypes = [vp]
+    L.wcal_mlp_num_params.restype = C.c_int64
+    L.wcal_mlp_set_params.argtypes = [vp, vp, vp]
+    L.wcal_mlp_get_params.argtypes = [vp, vp, vp]
+    L.wcal_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp]
+    L.wcal_mlp_gradients.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
+    L.wcal_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp, vp]
+    for f in ("wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains", "wcal_gains_to_bins", "wcal_reset_unconverged",
+              "wcal_mlp_create", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
+              "wcal_mlp_gradients", "wcal_mlp_train_step"):
+        getattr(L, f).restype = C.c_int
     _lib = L
     return L
 
@@ -103,6 +126,7 @@ class Plan:
                             _SCHED[schedule], max_iter, tol, _MODES[mode])
         self.n_ant, self.n_bl, self.n_dir, self.n_corr, self.n_int = n_ant, a1.numel(), n_dir, n_corr, nsv.numel()
         self.device = device
+        self.ant1, self.ant2, self.ns = a1, a2, nsv
         self._h = C.c_void_p()
         _check(L.wcal_plan_create(C.byref(self.prob), _ptr(a1), _ptr(a2), _ptr(nsv), device,
                                   C.byref(self._h)))
@@ -211,6 +235,105 @@ class Plan:
         _check(lib().wcal_residual(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
                                    _ptr(residual), _ptr(chi2), self._stream(stream)))
         return dict(residual=residual, chi2=chi2)
+
+
+def _cur_stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def bin_knots(n_int: int, bin_width: int) -> torch.Tensor:
+    """wcal_bin_knots: knot interval of every bin (host int32 tensor)."""
+    n_bins = (n_int + bin_width - 1) // bin_width
+    k = torch.empty(n_bins, dtype=torch.int32)
+    _check(lib().wcal_bin_knots(n_int, bin_width, _ptr(k)))
+    return k
+
+
+def gather_knots(plan: "Plan", bin_width: int, data, model, flags, data_out, model_out, flags_out=None,
+                 stream=None):
+    """wcal_gather_knots: rows of the knot intervals into the caller's compact buffers."""
+    plan._inputs(data, model, flags, torch.empty(plan.n_int, plan.n_dir, plan.n_ant, plan.n_corr,
+                                                 dtype=torch.complex64, device=data.device))
+    for t in (data_out, model_out, flags_out):
+        assert t is None or (t.is_cuda and t.is_contiguous())
+    _check(lib().wcal_gather_knots(plan._h, bin_width, _ptr(data), _ptr(model), _ptr(flags), _ptr(data_out),
+                                   _ptr(model_out), _ptr(flags_out), _cur_stream(stream)))
+
+
+def bins_to_gains(y, n_int: int, bin_width: int, stream=None) -> torch.Tensor:
+    """wcal_bins_to_gains: knot values [n_ant][2 n_bins] -> gains [n_int][1][n_ant][1]."""
+    assert y.is_cuda and y.dtype == torch.float32 and y.is_contiguous()
+    n_ant = y.shape[0]
+    g = torch.empty(n_int, 1, n_ant, 1, dtype=torch.complex64, device=y.device)
+    _check(lib().wcal_bins_to_gains(n_int, n_ant, bin_width, _ptr(y), _ptr(g), _cur_stream(stream)))
+    return g
+
+
+def gains_to_bins(gains, bin_width: int, halfwidth: int = 0, stream=None) -> torch.Tensor:
+    """wcal_gains_to_bins: gains [n_int][1][n_ant][1] -> referenced knot-window means [n_ant][2 n_bins]."""
+    assert gains.is_cuda and gains.dtype == torch.complex64 and gains.is_contiguous()
+    n_int, n_ant = gains.shape[0], gains.shape[2]
+    n_bins = (n_int + bin_width - 1) // bin_width
+    y = torch.empty(n_ant, 2 * n_bins, dtype=torch.float32, device=gains.device)
+    _check(lib().wcal_gains_to_bins(n_int, n_ant, bin_width, halfwidth, _ptr(gains), _ptr(y),
+                                    _cur_stream(stream)))
+    return y
+
+
+def reset_unconverged(plan: "Plan", status, gains, stream=None):
+    """wcal_reset_unconverged: unit gains for every interval that did not converge."""
+    _check(lib().wcal_reset_unconverged(plan._h, _ptr(status), _ptr(gains), _cur_stream(stream)))
+
+
+class Mlp:
+    """The warm-start network (wraps wcal_mlp)."""
+
+    def __init__(self, d_in: int, d_hidden: int, d_out: int, max_batch: int = 4096, skip: bool = False,
+                 device: int = 0):
+        self._h = C.c_void_p()
+        _check(lib().wcal_mlp_create(d_in, d_hidden, d_out, max_batch, int(skip), device, C.byref(self._h)))
+        self.skip = skip
+        self.d_in, self.d_hidden, self.d_out, self.max_batch = d_in, d_hidden, d_out, max_batch
+        self.n_params = int(lib().wcal_mlp_num_params(self._h))
+        self.device = torch.device("cuda", device)
+
+    def close(self):
+        if self._h:
+            lib().wcal_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta: torch.Tensor):
+        assert theta.is_cuda and theta.dtype == torch.float32 and theta.numel() == self.n_params
+        _check(lib().wcal_mlp_set_params(self._h, _ptr(theta.contiguous()), _cur_stream()))
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(lib().wcal_mlp_get_params(self._h, _ptr(out), _cur_stream()))
+        return out
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape[1] == self.d_in
+        y = torch.empty(x.shape[0], self.d_out, dtype=torch.float32, device=x.device)
+        _check(lib().wcal_mlp_forward(self._h, _ptr(x), x.shape[0], _ptr(y), _cur_stream()))
+        return y
+
+    def gradients(self, x, t):
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float64, device=x.device)
+        _check(lib().wcal_mlp_gradients(self._h, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _cur_stream()))
+        return g, loss
+
+    def train_step(self, x, t, lr: float, loss: Optional[torch.Tensor] = None):
+        _check(lib().wcal_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], float(lr), _ptr(loss),
+                                         _cur_stream()))
 
 
 def plan_for(problem, algo: Optional[str] = None, **kw) -> Plan:

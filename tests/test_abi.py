@@ -78,3 +78,23 @@ def test_valid_plan_without_gpu_reports_hip_error():
         pytest.skip("GPU present")
     rc, h = _create(3, [0, 0, 1], [1, 2, 2], [2])
     assert rc == wcal.EHIP
+
+
+def test_warm_start_host_entry_points():
+    """Knot indices (a host computation) match the oracle's definition; the warm-start
+    entry points reject bad arguments before touching a device."""
+    from oracle import mlp as om
+    for n_int, bw in [(14, 4), (1, 1), (4096, 64), (150, 32), (7, 16), (300, 7)]:
+        assert wcal.bin_knots(n_int, bw).tolist() == list(om.knots(n_int, bw))
+    L = wcal.lib()
+    k = np.zeros(4, np.int32)
+    assert L.wcal_bin_knots(0, 4, k.ctypes.data_as(C.c_void_p)) == wcal.EINVAL
+    assert L.wcal_bin_knots(5, 0, k.ctypes.data_as(C.c_void_p)) == wcal.EINVAL
+    assert L.wcal_gather_knots(None, 4, None, None, None, None, None, None, None) == wcal.EINVAL
+    assert L.wcal_bins_to_gains(5, 3, 0, None, None, None) == wcal.EINVAL
+    assert L.wcal_gains_to_bins(5, 3, 2, -1, None, None, None) == wcal.EINVAL
+    assert L.wcal_reset_unconverged(None, None, None, None) == wcal.EINVAL
+    h = C.c_void_p()
+    assert L.wcal_mlp_create(4, 8, 5, 16, 1, 0, C.byref(h)) == wcal.EINVAL      # skip needs d_in == d_out
+    assert L.wcal_mlp_create(0, 8, 5, 16, 0, 0, C.byref(h)) == wcal.EINVAL
+    assert not h.value

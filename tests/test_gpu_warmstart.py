@@ -1,0 +1,252 @@
+"""GPU parity of the learned warm start: the network's forward, gradients and Adam step
+against the float64 oracle network, the knot gather, the coarse-pass features and the
+knot <-> channel maps against their oracle definitions, the fallback reset, and an
+end-to-end check that the trained warm start reaches the oracle's solution in fewer
+updates than the unit start.
+
+Tolerances: network outputs and loss within 1e-5 relative (FP32 against FP64 through
+tanh layers of width <= 96), gradients within 1e-4 relative per parameter block, the Adam
+move within 1e-3 lr of the oracle's where the gradient is well above FP32 rounding,
+coarse features within 1e-5 relative (solved gains, as for StefCal), map outputs within
+1e-6 (a few FP32 roundings of O(1) values), gathered rows and status-driven resets
+bit-exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import calib as oc
+from oracle import driver as glue
+from oracle import mlp as om
+from paper_1502_06974_amd import synth, warmstart, wcal
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+BATCH = 130                                        # two 64-row tiles and a ragged third
+SHAPES = {False: (70, 96, 50), True: (66, 96, 66)}
+
+
+def _net(seed=0, skip=False):
+    d_in, d_h, d_out = SHAPES[skip]
+    net = wcal.Mlp(d_in, d_h, d_out, max_batch=256, skip=skip)
+    theta = warmstart.init_params(d_in, d_h, d_out, seed, torch.device(DEV))
+    net.set_params(theta)
+    rng = np.random.default_rng(seed + 100)
+    x = rng.standard_normal((BATCH, d_in)).astype(np.float32)
+    t = rng.standard_normal((BATCH, d_out)).astype(np.float32)
+    return net, theta.cpu().numpy().astype(np.float64), x, t
+
+
+@pytest.mark.parametrize("skip", [False, True])
+def test_mlp_forward_and_gradients(skip):
+    log(f"[mlp forward/gradients] skip={skip}")
+    D_IN, D_H, D_OUT = SHAPES[skip]
+    net, th, x, t = _net(1, skip)
+    xd, td = torch.as_tensor(x, device=DEV), torch.as_tensor(t, device=DEV)
+    y = net.forward(xd).cpu().numpy()
+    yo, _ = om.forward(th, x.astype(np.float64), D_IN, D_H, D_OUT, skip)
+    assert rel(y, yo) <= 1e-5
+    g, loss = net.gradients(xd, td)
+    lo, go = om.loss_and_grad(th, x.astype(np.float64), t.astype(np.float64), D_IN, D_H, D_OUT, skip)
+    assert abs(float(loss) - lo) <= 1e-5 * lo
+    g = g.cpu().numpy()
+    o = 0
+    for shp in om.sizes(D_IN, D_H, D_OUT):
+        n = int(np.prod(shp))
+        e = rel(g[o:o + n], go[o:o + n])
+        log(f"  block {shp}: rel {e:.2e}")
+        assert e <= 1e-4, (shp, e)
+        o += n
+    # forward of a single row and of a batch that is not a multiple of the tile
+    y1 = net.forward(xd[:1].contiguous()).cpu().numpy()
+    assert rel(y1, yo[:1]) <= 1e-5
+
+
+def test_mlp_adam_steps():
+    """Two Adam steps on one batch: parameters follow the oracle's optimiser."""
+    log("[mlp adam]")
+    D_IN, D_H, D_OUT = SHAPES[False]
+    net, th, x, t = _net(2)
+    xd, td = torch.as_tensor(x, device=DEV), torch.as_tensor(t, device=DEV)
+    lr = 1e-3
+    x64, t64 = x.astype(np.float64), t.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    th_o = th.copy()
+    th_gpu_prev = th.copy()
+    mask = np.ones(th.size, dtype=bool)
+    for step in (1, 2):
+        # the oracle steps from the GPU's current parameters (no drift between the two sides)
+        lo, g = om.loss_and_grad(th_gpu_prev, x64, t64, D_IN, D_H, D_OUT)
+        th_o, m, v = om.adam_step(th_gpu_prev, g, m, v, step, lr)
+        net.train_step(xd, td, lr, loss)
+        assert abs(float(loss) - lo) <= 1e-5 * lo
+        th_g = net.get_params().cpu().numpy().astype(np.float64)
+        mask &= np.abs(g) > 1e-4 * np.abs(g).max()
+        d = np.abs((th_g - th_gpu_prev) - (th_o - th_gpu_prev))
+        log(f"  step {step}: max move error on {mask.sum()}/{mask.size} params {d[mask].max() / lr:.2e} lr")
+        assert d[mask].max() <= 1e-3 * lr + 1e-7 * np.abs(th_o[mask]).max()
+        assert d.max() <= 4.0 * lr + 1e-7
+        th_gpu_prev = th_g
+
+
+def _bandpass(n_ant=12, n_chan=150, seed=3, flag_frac=0.05, model=None):
+    return synth.bandpass_di(n_ant, n_chan, seed=seed, device=DEV, flag_frac=flag_frac, model=model)
+
+
+def _oracle_intervals(P):
+    ivs = []
+    for k in range(P.n_int):
+        iv = P.interval(k)
+        ivs.append(dict(d=iv["d"][:, 0], m=iv["m"][:, 0, 0], p=iv["p"], q=iv["q"], flags=iv["flags"]))
+    return ivs
+
+
+@pytest.mark.parametrize("pol", [False, True])
+def test_gather_knots(pol):
+    """Rows of the knot intervals, bins in order: bit-exact copies (ragged intervals too)."""
+    log(f"[gather knots] pol={pol}")
+    ns = synth.ragged_ns(23, t_max=5, f_max=4, seed=2)
+    P = (synth.pol_di(7, ns, seed=4, device=DEV, flag_frac=0.2) if pol
+         else synth.scalar_di(7, ns, seed=4, device=DEV, flag_frac=0.2))
+    plan = wcal.plan_for(P)
+    bw = 5
+    ks = wcal.bin_knots(P.n_int, bw).tolist()
+    assert ks == list(om.knots(P.n_int, bw))
+    sel = torch.cat([torch.arange(int(P.row_off[k]), int(P.row_off[k + 1])) for k in ks]).to(DEV)
+    d = torch.empty(sel.numel(), P.n_corr, dtype=torch.complex64, device=DEV)
+    m = torch.empty(sel.numel(), 1, P.n_corr, dtype=torch.complex64, device=DEV)
+    f = torch.empty(sel.numel(), dtype=torch.uint8, device=DEV)
+    wcal.gather_knots(plan, bw, P.data, P.model, P.flags, d, m, f)
+    torch.cuda.synchronize()
+    assert torch.equal(d, P.data[sel]) and torch.equal(m, P.model[sel]) and torch.equal(f, P.flags[sel])
+    wcal.gather_knots(plan, bw, P.data, P.model, None, d, m, f)
+    assert int(f.sum()) == 0
+
+
+@pytest.mark.parametrize("bin_width", [1, 16, 150])
+def test_coarse_features(bin_width):
+    """The coarse pass (knot channels solved from unit gains) against the oracle's."""
+    log(f"[coarse features] bin_width={bin_width}")
+    P = _bandpass()
+    plan = wcal.plan_for(P)
+    ws = warmstart.WarmStart(plan, bin_width=bin_width, hidden=8, coarse_tol=1e-6, coarse_max_iter=500)
+    f, co = ws.features(P.data, P.model, P.flags)
+    f = f.cpu().numpy()
+    fo, res = om.coarse_features(_oracle_intervals(P), P.n_ant, bin_width, tol=1e-12, max_iter=3000)
+    assert f.shape == fo.shape
+    assert np.all(co["status"].cpu().numpy() & oc.CONVERGED)
+    nb = fo.shape[1] // 2
+    z, zo = f[:, :nb] + 1j * f[:, nb:], fo[:, :nb] + 1j * fo[:, nb:]
+    for B in range(nb):
+        assert rel(z[:, B], zo[:, B]) <= 1e-5, (B, rel(z[:, B], zo[:, B]))
+
+
+@pytest.mark.parametrize("n_int,bin_width", [(150, 32), (64, 64), (7, 1), (5, 16), (300, 7)])
+def test_bins_to_gains_and_back(n_int, bin_width):
+    log(f"[knot maps] n_int={n_int} bin_width={bin_width}")
+    n_ant = 9
+    n_bins = (n_int + bin_width - 1) // bin_width
+    rng = np.random.default_rng(n_int + bin_width)
+    y = rng.standard_normal((n_ant, 2 * n_bins)).astype(np.float32)
+    g = wcal.bins_to_gains(torch.as_tensor(y, device=DEV), n_int, bin_width)
+    go = om.bins_to_channels(y.astype(np.float64), n_ant, bin_width, n_int)
+    assert tuple(g.shape) == (n_int, 1, n_ant, 1)
+    assert np.abs(g[:, 0, :, 0].cpu().numpy() - go).max() <= 1e-6
+    gr = (rng.standard_normal((n_int, n_ant)) + 1j * rng.standard_normal((n_int, n_ant))).astype(np.complex64)
+    gd = torch.as_tensor(gr, device=DEV).view(n_int, 1, n_ant, 1).contiguous()
+    for hw in (0, 1, 3):
+        yb = wcal.gains_to_bins(gd, bin_width, hw)
+        yo = om.channels_to_bins(gr.astype(np.complex128), n_ant, bin_width, hw)
+        assert np.abs(yb.cpu().numpy() - yo).max() <= 1e-6, hw
+
+
+@pytest.mark.parametrize("pol", [False, True])
+def test_reset_unconverged(pol):
+    log(f"[reset unconverged] pol={pol}")
+    status = [oc.CONVERGED, oc.MAXITER, oc.NONFINITE, oc.CONVERGED | oc.SINGULAR_ANT, 0, oc.SINGULAR_ANT]
+    ns = [2] * len(status)
+    P = (synth.pol_di(6, ns, seed=1, device=DEV) if pol else synth.scalar_di(6, ns, seed=1, device=DEV))
+    plan = wcal.plan_for(P)
+    g = P.g_true.clone().contiguous()
+    st = torch.tensor(status, dtype=torch.int32, device=DEV)
+    wcal.reset_unconverged(plan, st, g)
+    g, g0, u = g.cpu(), P.g_true.cpu(), P.unit_gains().cpu()
+    for k, s in enumerate(status):
+        want = g0[k] if s & oc.CONVERGED else u[k]
+        assert torch.equal(g[k], want), k
+
+
+def test_fallback_restarts_failed_intervals_from_unit():
+    """Non-finite starting gains on two intervals: those intervals stop NONFINITE, are reset
+    to unit gains and solved again; their result equals a plain unit-start solve."""
+    log("[warm-start fallback]")
+    P = _bandpass(n_ant=16, n_chan=12, seed=5, flag_frac=0.0)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=200)
+    g0 = P.unit_gains()
+    g0[3] = float("nan")
+    g0[7, 0, 4, 0] = float("inf")
+    out = warmstart.WarmStart.solve_from(plan, P.data, P.model, P.flags, g0.contiguous())
+    torch.cuda.synchronize()
+    assert out["fallback"] == 2
+    assert bool(((out["status"] & wcal.CONVERGED) != 0).all())
+    ref = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    for k in (3, 7):
+        assert rel(out["gains"][k].cpu().numpy(), ref["gains"][k].cpu().numpy()) <= 1e-6
+        assert int(out["n_iter"][k]) == int(ref["n_iter"][k])
+
+
+def test_trained_warm_start_end_to_end():
+    """Train the network on device on unit-start solutions of 16 observations of one sky
+    (48 antennas, 256 channels, knots every 8 channels), then on 3 held-out observations:
+    the warm start (coarse pass counted at its share of the rows) needs at most 85% of the
+    unit start's updates, nothing falls back, and the solution agrees with the oracle's
+    unit-start solution (global phase aligned) on sampled channels."""
+    log("[warm start end-to-end]")
+    n_ant, n_chan, bw = 48, 256, 8
+    P0 = _bandpass(n_ant, n_chan, seed=1000, flag_frac=0.0)
+    plan = wcal.plan_for(P0, tol=1e-6, max_iter=500)
+    ws = warmstart.WarmStart(plan, bin_width=bw, hidden=64, seed=1, max_batch=1024)
+    X, T = [], []
+    for i in range(16):
+        P = P0 if i == 0 else _bandpass(n_ant, n_chan, seed=1000 + i, flag_frac=0.0, model=P0.model)
+        f, t, ok = ws.make_example(P)
+        assert ok
+        X.append(f)
+        T.append(t)
+    X, T = torch.cat(X).contiguous(), torch.cat(T).contiguous()
+    losses = ws.train(X, T, epochs=60, batch=96, lr=1e-3, seed=0)
+    log(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert np.isfinite(losses[-1]) and losses[-1] <= losses[0]
+    it = {"unit": [], "coarse": [], "mlp": []}
+    for j in range(3):
+        P = _bandpass(n_ant, n_chan, seed=5000 + j, flag_frac=0.0, model=P0.model)
+        r = warmstart.evaluate(ws, P)
+        for k in it:
+            it[k].append(r[k]["mean_iter"])
+        w = r["mlp"]
+        assert w["fallback"] == 0 and w["converged"] == n_chan
+        g = w["gains"].cpu().numpy()
+        for k in (0, 97, 255):
+            o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), algo="stefcal", tol=1e-10, max_iter=3000)
+            go = glue.gains_from_oracle(o["g"], 1, 1)[0, :, 0]
+            e = rel(oc.align_phase(g[k, 0, :, 0].astype(np.complex128), go), go)
+            assert e <= 1e-5, (j, k, e)
+    m = {k: float(np.mean(v)) for k, v in it.items()}
+    log(f"  mean updates per interval: unit {m['unit']:.2f}, coarse pass only {m['coarse']:.2f}, "
+        f"trained network {m['mlp']:.2f}")
+    assert m["mlp"] <= 0.85 * m["unit"]

@@ -530,3 +530,94 @@ def test_alljones_reaches_cohjones_fixed_point():
     aj = oc.alljones(d, m, p, q, None, g0, tol=1e-14, max_iter=20000)
     assert aj["status"] & oc.CONVERGED
     assert oc.rel_err(oc.align_phase_per_direction(aj["g"], cj["g"]), cj["g"]) < 1e-8
+
+
+# ------------------------------------------------------------------ P15 warm-start network
+@pytest.mark.parametrize("skip", [False, True])
+def test_p15_mlp_gradient_central_differences(skip):
+    """Backpropagated gradient of the float64 network equals central differences (1e-7 rel),
+    with and without the skip connection."""
+    from oracle import mlp
+    d_in, d_h, d_out, B = 6, 5, 6, 7
+    n = mlp.n_params(d_in, d_h, d_out)
+    theta = 0.5 * rng.standard_normal(n)
+    x = rng.standard_normal((B, d_in))
+    t = rng.standard_normal((B, d_out))
+    loss, g = mlp.loss_and_grad(theta, x, t, d_in, d_h, d_out, skip)
+    h = 1e-6
+    fd = np.zeros(n)
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = h
+        fd[i] = (mlp.loss_and_grad(theta + e, x, t, d_in, d_h, d_out, skip)[0]
+                 - mlp.loss_and_grad(theta - e, x, t, d_in, d_h, d_out, skip)[0]) / (2 * h)
+    assert np.linalg.norm(g - fd) / np.linalg.norm(fd) < 1e-7
+    # the skip connection adds the input to the output and nothing else
+    y0, _ = mlp.forward(theta, x, d_in, d_h, d_out, False)
+    y1, _ = mlp.forward(theta, x, d_in, d_h, d_out, True)
+    assert np.array_equal(y1, y0 + x)
+
+
+def test_mlp_adam_decreases_loss_and_matches_closed_form():
+    """Adam's first step moves every parameter by lr * sign(g) (bias-corrected moments)."""
+    from oracle import mlp
+    d_in, d_h, d_out = 4, 3, 2
+    n = mlp.n_params(d_in, d_h, d_out)
+    theta = 0.3 * rng.standard_normal(n)
+    x, t = rng.standard_normal((9, d_in)), rng.standard_normal((9, d_out))
+    l0, g = mlp.loss_and_grad(theta, x, t, d_in, d_h, d_out)
+    th1, m, v = mlp.adam_step(theta, g, np.zeros(n), np.zeros(n), 1, 1e-3)
+    assert np.allclose(th1 - theta, -1e-3 * np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8), atol=1e-12)
+    th, m, v = theta, np.zeros(n), np.zeros(n)
+    for s in range(1, 200):
+        _, g = mlp.loss_and_grad(th, x, t, d_in, d_h, d_out)
+        th, m, v = mlp.adam_step(th, g, m, v, s, 1e-2)
+    assert mlp.loss_and_grad(th, x, t, d_in, d_h, d_out)[0] < 0.5 * l0
+
+
+def test_coarse_features_are_referenced_knot_solutions():
+    """Noise-free data: the coarse pass recovers the true gains on the knot channels, so the
+    features are the true gains referenced to antenna 0 (the phase gauge removed)."""
+    from oracle import mlp
+    P = synth.bandpass_di(8, 11, sigma=0.0, noise=False, dtype=torch.complex128, seed=12)
+    ivs = []
+    for k in range(P.n_int):
+        iv = P.interval(k)
+        ivs.append(dict(d=iv["d"][:, 0], m=iv["m"][:, 0, 0], p=iv["p"], q=iv["q"], flags=iv["flags"]))
+    f, res = mlp.coarse_features(ivs, 8, 4, tol=1e-13, max_iter=2000)
+    assert list(mlp.knots(11, 4)) == [1, 5, 9]
+    assert all(o["status"] & 1 for o in res)
+    g = P.g_true.numpy()[:, 0, :, 0]                  # [chan][ant]
+    want = g[[1, 5, 9]] * (np.conj(g[[1, 5, 9], 0]) / np.abs(g[[1, 5, 9], 0]))[:, None]
+    assert np.allclose(f[:, :3] + 1j * f[:, 3:], want.T, atol=1e-9)
+
+
+def test_bins_and_channels_round_trip():
+    """Knots of 14 channels in bins of 4 are 1, 5, 9, 12 (ragged last bin).  Gains whose
+    amplitude and phase are linear in channel (a delay) are reproduced exactly between the
+    outer knots and held constant beyond them; the target window averages only the channels
+    near each knot; a common per-channel phase cancels."""
+    from oracle import mlp
+    n_ant, bw, n_int = 5, 4, 14
+    ks = mlp.knots(n_int, bw)
+    assert list(ks) == [1, 5, 9, 12]
+    k = np.arange(n_int)[:, None]
+    amp = 1.0 + 0.02 * k * rng.uniform(-1, 1, n_ant)[None]
+    ph = rng.uniform(-np.pi, np.pi, n_ant)[None] + 0.4 * k * rng.uniform(-1, 1, n_ant)[None]
+    g = amp * np.exp(1j * ph)
+    r = g * (np.conj(g[:, :1]) / np.abs(g[:, :1]))
+    y = mlp.channels_to_bins(g, n_ant, bw, 0)
+    assert np.allclose(y[:, :4] + 1j * y[:, 4:], r[ks].T, atol=1e-14)
+    back = mlp.bins_to_channels(y, n_ant, bw, n_int)
+    assert np.allclose(back[1:13], r[1:13], atol=1e-12)
+    assert np.allclose(back[0], r[1]) and np.allclose(back[13], r[12])
+    vals = rng.standard_normal((4, n_ant)) + 1j * rng.standard_normal((4, n_ant))
+    vals[:, 0] = np.abs(vals[:, 0])
+    gb = np.repeat(vals, bw, axis=0)[:n_int]
+    yb = mlp.channels_to_bins(gb, n_ant, bw, 1)        # windows [0,2], [4,6], [8,10], [11,13]
+    zb = yb[:, :4] + 1j * yb[:, 4:]
+    assert np.allclose(zb[:, :3], vals[:3].T, atol=1e-14)
+    assert np.allclose(zb[:, 3], (vals[2] + 2 * vals[3]) / 3, atol=1e-14)
+    cp = np.exp(1j * rng.uniform(-np.pi, np.pi, n_int))[:, None]
+    assert np.allclose(mlp.channels_to_bins(g * cp, n_ant, bw, 2), mlp.channels_to_bins(g, n_ant, bw, 2),
+                       atol=1e-13)
