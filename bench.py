@@ -29,13 +29,20 @@ MFMA_FP32_PEAK_TFS = 157.3     # dense FP32 matrix peak of one MI355X
 MFMA_ISSUED_FLOP_PER_ROW = 3 * 2 * 16 * 16 * 4 / 4   # three 16x16x4 FP32 MFMAs per 4 samples
 
 
-def source_hash() -> str:
-    """sha256 of the library sources (kernels, host code, public header)."""
-    import glob
+KERNEL_SOURCES = {
+    "di": ("di_kernels.hip", "di_common.h"),
+    "dd": ("dd_kernels.hip",),
+}
+
+
+def source_hash(family: str) -> str:
+    """sha256 of what decides a kernel family's memory traffic: its kernel sources, the plan
+    and launch code, and the public header."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1502_06974_amd", "csrc", "*"))) + \
-        [os.path.join(ROOT, "include", "wcal.h")]
+    csrc = os.path.join(ROOT, "paper_1502_06974_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in KERNEL_SOURCES[family] + ("wcal_internal.h", "wcal_api.hip")]
+    files.append(os.path.join(ROOT, "include", "wcal.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
@@ -48,7 +55,8 @@ def measured_traffic(key: str):
         rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))[key]
     except (OSError, KeyError, ValueError):
         return None
-    return rec["traffic_bytes_per_launch"] if rec.get("src_sha") == source_hash() else None
+    family = key.split("_", 1)[0]
+    return rec["traffic_bytes_per_launch"] if rec.get("src_sha") == source_hash(family) else None
 
 
 def log(*a):
