@@ -588,6 +588,9 @@ __global__ void __launch_bounds__(TB) di_pass_kernel(DiArgs a, int it) {
     __shared__ int s_t;
     const int nw = blockDim.x / WAVE;
     const int n = it == 0 ? a.ntiles : a.ctr[qoff(a) + it];
+    // tiles are popped dynamically, so workgroups beyond the listed count have nothing to
+    // take (after convergence every workgroup leaves without touching the queue)
+    if ((int)blockIdx.x >= n) return;
     const int32_t* list = a.lists + (it & 1) * a.ntiles;
     float* myacc = acc + (threadIdx.x / WAVE) * na * NVP;
     for (;;) {
@@ -610,6 +613,164 @@ __global__ void __launch_bounds__(TB) di_pass_kernel(DiArgs a, int it) {
         for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
             float v = acc[i];
             for (int w = 1; w < nw; ++w) v += acc[w * na * NVP + i];
+            out[i] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ triangle pass
+// Scalar gains, baselines in the canonical order (all pairs p < q, p-major): the stored
+// rows of one sample form the upper triangle of an n_ant x n_ant matrix, and the folded
+// sums of Eq. JJ:di are its row sums (antenna p) and column sums (antenna q):
+//   A_p += |g_q|^2 sum|m|^2,   c_p += g_q sum conj(m) d,
+//   A_q += |g_p|^2 sum|m|^2,   c_q += g_p conj(sum conj(m) d).
+// A unit is a block of whole rows p (at most 64).  A wavefront walks each row in chunks of
+// 64 consecutive baselines (lane = q - p - 1 - 64 j), so it streams the triangle in storage
+// order and every cache line is consumed by one wavefront.  The row sum builds up in the
+// lanes over the row's chunks and is reduced once per row (row-shift DPP adds, then the four
+// row totals); lane (p - p0) keeps it until the unit ends.  Within a chunk the q are
+// distinct, so each lane adds its column terms to the wavefront's LDS slice directly; the
+// slice is private to the wavefront and updated in program order.  Every sum runs in a fixed
+// order, so the pass is bit-reproducible.
+
+// x from the lane n below in the same row of 16 lanes (0 for the first n lanes of a row)
+template <int N>
+__device__ __forceinline__ float dpp_row_shr(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + N, 0xf, 0xf, true));
+}
+
+// Sum over the 64 lanes, returned uniformly.  Call with every lane active.
+__device__ __forceinline__ float wave_total(float x) {
+    x += dpp_row_shr<1>(x);
+    x += dpp_row_shr<2>(x);
+    x += dpp_row_shr<4>(x);
+    x += dpp_row_shr<8>(x);   // lane 16 r + 15 holds the sum of row r
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 15));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 31));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 47));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+    return (r0 + r1) + (r2 + r3);
+}
+
+constexpr int TRI_U = 8;    // chunks in flight per lane
+
+// element i of a row segment that starts at `base` (a uniform pointer), via a 32-bit byte
+// offset so the load takes the scalar-base form
+template <typename T>
+__device__ __forceinline__ T load_at(const T* base, int i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)i * (uint32_t)sizeof(T));
+}
+
+// One unit of a tile (samples [s0, s1) of interval k) into this wavefront's slice
+// acc[na + 1][3]; G holds na + 1 gains.  Lanes past the end of a row load the row's last
+// element (no extra memory traffic), contribute zeros, and add them to the spare slot na.
+__device__ __forceinline__ void tri_unit(const DiArgs& a, const Tile& T, const TriUnit& U, const float2* G,
+                                         float* acc) {
+    const int na = a.n_ant;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t off = a.row_off[T.k];
+    const bool has_flags = a.flags != nullptr;
+    float ps0 = 0.f, ps1 = 0.f, ps2 = 0.f;    // this lane's share of the current row sum
+    float pr0 = 0.f, pr1 = 0.f, pr2 = 0.f;    // row sums of row p0 + lane
+    float m2 = 0.f, tr = 0.f, ti = 0.f;       // sum|m|^2, sum conj(m) d of the current entry
+    int p = U.p0, j = 0, s = T.s0;
+    while (p < U.p1) {
+        float2 d[TRI_U], m[TRI_U];
+        bool use[TRI_U], end_e[TRI_U], end_r[TRI_U];
+        int pu[TRI_U], qu[TRI_U];
+        int pp = p, jj = j, ss = s;
+#pragma unroll
+        for (int u = 0; u < TRI_U; ++u) {
+            const bool in = pp < U.p1;
+            const int pr = in ? pp : U.p1 - 1;          // a row that exists
+            const int len = na - 1 - pr;                 // baselines of row pr
+            const int c = 64 * jj + lane;                // position in the row
+            const bool valid = in && c < len;
+            const int cc = valid ? c : len - 1;
+            const int64_t base = off + (int64_t)ss * a.n_bl + (int64_t)pr * na - (int64_t)pr * (pr + 1) / 2;
+            d[u] = load_at(a.data + base, cc);
+            m[u] = load_at(a.model + base, cc);
+            use[u] = valid && !(has_flags && load_at(a.flags + base, cc) != 0);
+            pu[u] = pr;
+            qu[u] = valid ? pr + 1 + c : na;
+            end_e[u] = in && ss + 1 == T.s1;
+            end_r[u] = end_e[u] && 64 * (jj + 1) >= len;
+            if (in && ++ss == T.s1) {
+                ss = T.s0;
+                if (64 * (++jj) >= len) { jj = 0; ++pp; }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < TRI_U; ++u) {
+            if (use[u]) {
+                m2 += nrm(m[u]);
+                const float2 t = ccmul(m[u], d[u]);     // conj(m) d
+                tr += t.x;
+                ti += t.y;
+            }
+            if (end_e[u]) {                             // entry (pu, qu) complete: contract
+                const float2 gp = G[pu[u]];
+                const float2 gq = G[qu[u]];
+                const float2 sv = make_float2(tr, ti);
+                const float2 cp = cmul(gq, sv);
+                const float2 cq = cmulc(gp, sv);        // g_p conj(s)
+                ps0 += nrm(gq) * m2;
+                ps1 += cp.x;
+                ps2 += cp.y;
+                float* dq = acc + qu[u] * 3;
+                dq[0] += nrm(gp) * m2;
+                dq[1] += cq.x;
+                dq[2] += cq.y;
+                m2 = 0.f; tr = 0.f; ti = 0.f;
+            }
+            if (end_r[u]) {                             // row pu complete: reduce its sum
+                const float t0 = wave_total(ps0);
+                const float t1 = wave_total(ps1);
+                const float t2 = wave_total(ps2);
+                if (lane == pu[u] - U.p0) { pr0 = t0; pr1 = t1; pr2 = t2; }
+                ps0 = 0.f; ps1 = 0.f; ps2 = 0.f;
+            }
+        }
+        p = pp; j = jj; s = ss;
+    }
+    if (lane < U.p1 - U.p0) {
+        float* dst = acc + (U.p0 + lane) * 3;
+        dst[0] += pr0; dst[1] += pr1; dst[2] += pr2;
+    }
+}
+
+__global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit* __restrict__ units, int it) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NVP = Nv<1, 0>::v;
+    const int na = a.n_ant;
+    const int ns = (na + 1) * NVP;                  // slice: na antennas + the spare slot
+    float2* G = reinterpret_cast<float2*>(smem);    // na + 1 (the last is 0)
+    float* acc = reinterpret_cast<float*>(G + na + 1);
+    __shared__ int s_t;
+    const int nw = blockDim.x / WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
+    const int n = it == 0 ? a.ntiles : a.ctr[qoff(a) + it];
+    if ((int)blockIdx.x >= n) return;     // nothing to pop (see di_pass_kernel)
+    const int32_t* list = a.lists + (it & 1) * a.ntiles;
+    float* myacc = acc + w * ns;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[it], 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_t);
+        if (idx >= n) break;
+        const int t = it == 0 ? idx : list[idx];
+        const Tile T = a.tiles[t];
+        const float2* gk = a.gains + (int64_t)T.k * na;
+        for (int i = threadIdx.x; i <= na; i += blockDim.x) G[i] = i < na ? gk[i] : make_float2(0.f, 0.f);
+        for (int i = threadIdx.x; i < nw * ns; i += blockDim.x) acc[i] = 0.f;
+        __syncthreads();
+        for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
+        __syncthreads();
+        float* out = a.partial + (int64_t)t * na * NVP;
+        for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+            float v = acc[i];
+            for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * ns + i];
             out[i] = v;
         }
     }
@@ -828,6 +989,22 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
         prof_begin(plan, WCAL_K_SOLVE_STATS, s);
         hipLaunchKernelGGL(di_solve_stats_kernel<NC>, dim3(g2), dim3(TB), us, s, a);
         prof_end(plan, WCAL_K_SOLVE_STATS, s);
+    } else if (NC == 1 && plan->tri) {
+        // pass and update over the triangle tiles; the residual below keeps the row tiles
+        DiArgs at = a;
+        at.tiles = plan->d_ttiles;
+        at.tile_off = plan->d_ttile_off;
+        at.ntiles = plan->nttiles;
+        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TB / WAVE) * (na + 1) * 3 * sizeof(float);
+        const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_tri_pass_kernel), TB, ps, at.ntiles);
+        for (int it = 0; it < a.max_iter; ++it) {
+            prof_begin(plan, WCAL_K_PASS, s);
+            hipLaunchKernelGGL(di_tri_pass_kernel, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
+            prof_end(plan, WCAL_K_PASS, s);
+            prof_begin(plan, WCAL_K_UPDATE, s);
+            hipLaunchKernelGGL(di_update_kernel<1>, dim3(a.n_int), dim3(TB), us, s, at, it);
+            prof_end(plan, WCAL_K_UPDATE, s);
+        }
     } else {
         const size_t ps = pass_smem(na, NC);
         const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_pass_kernel<NC>), TB, ps, a.ntiles);

@@ -214,6 +214,73 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
             return fail(WCAL_ESHAPE, "too many tiles");
         }
     }
+    // triangle pass: scalar StefCal PASS solve with every pair p < q in p-major order
+    {
+        bool canonical = p.algo == WCAL_STEFCAL && p.n_corr == 1 && p.mode == WCAL_MODE_PASS &&
+                         (int64_t)p.n_bl == (int64_t)p.n_ant * (p.n_ant - 1) / 2;
+        for (int32_t a = 0, b = 0; canonical && a < p.n_ant; ++a)
+            for (int32_t c = a + 1; canonical && c < p.n_ant; ++c, ++b)
+                canonical = ant1_h[b] == a && ant2_h[b] == c;
+        const char* env = std::getenv("WCAL_TRI");
+        const int want = env ? atoi(env) : -1;   // 0: never, 1: whenever the order allows, unset: n_ant >= 64
+        plan->tri = canonical && (want == 1 || (want < 0 && p.n_ant >= 64));
+    }
+    std::vector<TriUnit> units;
+    std::vector<Tile> ttiles;
+    std::vector<int32_t> ttile_off(p.n_int + 1, 0);
+    if (plan->tri) {
+        // units: blocks of whole rows (at most 64) of about 8 chunks of 64 baselines (the
+        // cost of a row is its chunk count), then ordered largest first and dealt in snake
+        // order, so the round-robin share of each of the four wavefronts of a workgroup is
+        // even
+        const int32_t target = 8;
+        std::vector<TriUnit> raw;
+        for (int32_t r0 = 0; r0 < p.n_ant - 1;) {
+            int32_t r1 = r0, ent = 0, chunks = 0;
+            while (r1 < p.n_ant - 1 && r1 - r0 < 64) {
+                const int32_t len = p.n_ant - 1 - r1, ch = (len + 63) / 64;
+                if (r1 > r0 && chunks + ch > target) break;
+                ent += len;
+                chunks += ch;
+                ++r1;
+            }
+            raw.push_back(TriUnit{r0, r1, ent, chunks});
+            r0 = r1;
+        }
+        std::stable_sort(raw.begin(), raw.end(), [](const TriUnit& x, const TriUnit& y) { return x.chunks > y.chunks; });
+        const int nwv = 4;
+        std::vector<std::vector<TriUnit>> lanes(nwv);
+        for (size_t i = 0; i < raw.size(); ++i) {
+            const size_t r = i / nwv, c = i % nwv;
+            lanes[(r % 2 == 0) ? c : nwv - 1 - c].push_back(raw[i]);
+        }
+        for (size_t r = 0; r * nwv < raw.size(); ++r)
+            for (int c = 0; c < nwv; ++c)
+                if (r < lanes[c].size()) units.push_back(lanes[c][r]);
+        const int64_t tr = plan->tile_rows;
+        for (int32_t k = 0; k < p.n_int; ++k) {
+            const int32_t S = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tr / p.n_bl, ns32[k]));
+            for (int32_t s0 = 0; s0 < ns32[k]; s0 += S) {
+                const int32_t s1 = std::min(s0 + S, ns32[k]);
+                int32_t u0 = 0;
+                while (u0 < (int32_t)units.size()) {
+                    int64_t ent = 0;
+                    int32_t u1 = u0;
+                    while (u1 < (int32_t)units.size() && (u1 == u0 || (ent + units[u1].entries) * (s1 - s0) <= tr))
+                        ent += units[u1++].entries;
+                    ttiles.push_back(Tile{k, u0, u1, s0, s1});
+                    u0 = u1;
+                }
+            }
+            ttile_off[k + 1] = (int32_t)ttiles.size();
+            if (ttiles.size() > (size_t)INT32_MAX / 2) {
+                delete plan;
+                return fail(WCAL_ESHAPE, "too many tiles");
+            }
+        }
+        plan->nunits = (int32_t)units.size();
+        plan->nttiles = (int32_t)ttiles.size();
+    }
     // statistics tiles in decreasing-size order (longest first)
     std::stable_sort(stiles.begin(), stiles.end(), [](const Tile& x, const Tile& y) {
         return (int64_t)(x.b1 - x.b0) * (x.s1 - x.s0) > (int64_t)(y.b1 - y.b0) * (y.s1 - y.s0);
@@ -221,14 +288,21 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
     plan->ntiles = (int32_t)tiles.size();
     plan->nstiles = (int32_t)stiles.size();
     const int nvp = p.algo == WCAL_STEFCAL ? di_nvp(p.n_corr) : 0;
+    const int32_t ntmax = std::max(plan->ntiles, plan->nttiles);
     hipError_t e = hipSuccess;
+    if (plan->tri && ((e = upload(&plan->d_units, units.data(), units.size())) != hipSuccess ||
+                      (e = upload(&plan->d_ttiles, ttiles.data(), ttiles.size())) != hipSuccess ||
+                      (e = upload(&plan->d_ttile_off, ttile_off.data(), ttile_off.size())) != hipSuccess)) {
+        wcal_plan_destroy(plan);
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan units");
+    }
     if ((e = upload(&plan->d_tiles, tiles.data(), tiles.size())) != hipSuccess ||
         (e = upload(&plan->d_tile_off, tile_off.data(), tile_off.size())) != hipSuccess ||
         (e = upload(&plan->d_stiles, stiles.data(), stiles.size())) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_lists), 2 * sizeof(int32_t) * std::max(1, plan->ntiles))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_lists), 2 * sizeof(int32_t) * std::max(1, ntmax))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void**>(&plan->d_ctr), sizeof(int32_t) * (2 * (p.max_iter + 2) + 16))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void**>(&plan->d_partial),
-                       sizeof(float) * std::max<size_t>(1, (size_t)plan->ntiles * p.n_ant * nvp))) != hipSuccess ||
+                       sizeof(float) * std::max<size_t>(1, (size_t)ntmax * p.n_ant * nvp))) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void**>(&plan->d_active), sizeof(int32_t) * p.n_int)) != hipSuccess ||
         (e = hipMalloc(reinterpret_cast<void**>(&plan->d_chi_part), sizeof(double) * std::max(1, plan->ntiles))) != hipSuccess) {
         wcal_plan_destroy(plan);
@@ -283,7 +357,8 @@ void wcal_plan_destroy(wcal_plan* plan) {
                     (void*)plan->d_order, (void*)plan->d_queue, (void*)plan->d_stats, (void*)plan->d_tiles,
                     (void*)plan->d_tile_off, (void*)plan->d_stiles, (void*)plan->d_lists, (void*)plan->d_ctr,
                     (void*)plan->d_partial, (void*)plan->d_active, (void*)plan->d_chi_part,
-                    (void*)plan->d_ant_ptr, (void*)plan->d_ant_bl})
+                    (void*)plan->d_ant_ptr, (void*)plan->d_ant_bl, (void*)plan->d_units, (void*)plan->d_ttiles,
+                    (void*)plan->d_ttile_off})
         if (p) (void)hipFree(p);
     delete plan;
 }

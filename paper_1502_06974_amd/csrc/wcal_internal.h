@@ -17,6 +17,12 @@ struct Profiler;
 void prof_begin(const wcal_plan* plan, int cls, hipStream_t s);
 void prof_end(const wcal_plan* plan, int cls, hipStream_t s);
 
+// A unit of the triangle pass (baselines in the canonical order: all pairs p < q,
+// p-major, q increasing): the whole rows p in [p0, p1) of the triangle, at most 64.
+struct TriUnit {
+    int32_t p0, p1, entries, chunks;   // chunks: sum over rows of ceil(length / 64)
+};
+
 // ------------------------------------------------------------------ plan
 struct wcal_plan {
     wcal_problem prob;
@@ -53,6 +59,14 @@ struct wcal_plan {
     int block = 0;                // threads per workgroup (0 = largest compiled for the kernel)
     int wg_per_cu = 0;            // resident workgroups per CU (0 = occupancy limit)
     int tile_rows = 0;            // target rows per tile
+    // triangle pass (scalar StefCal, canonical baseline order): units and tiles whose
+    // b0/b1 are unit ranges; the PASS solve uses these tiles for its pass and update
+    bool tri = false;
+    TriUnit* d_units = nullptr;
+    int32_t nunits = 0;
+    Tile* d_ttiles = nullptr;
+    int32_t* d_ttile_off = nullptr;
+    int32_t nttiles = 0;
     Profiler* prof = nullptr;     // non-null while timing is enabled
 };
 

@@ -300,3 +300,106 @@ def test_small_tiles_split_intervals(tile_rows, monkeypatch):
         go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
         assert rel(g[k], go) <= 1e-5
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
+
+
+# ------------------------------------------------------------------ triangle pass
+# Scalar StefCal with every pair p < q in p-major order runs the triangle pass (by default
+# from 64 antennas; WCAL_TRI=1 forces it for any canonical table, 0 disables it).
+TRI_CASES = [(12, [1, 1, 3]), (64, [1, 3]), (100, [1, 2, 5, 1]), (130, [1, 2])]
+
+
+@pytest.mark.parametrize("n_ant,ns", TRI_CASES)
+def test_triangle_pass_lockstep(n_ant, ns, monkeypatch):
+    log(f"[triangle lockstep] n_ant={n_ant} ns={ns}")
+    monkeypatch.setenv("WCAL_TRI", "1")
+    P = make("scalar", n_ant, ns, flag_frac=0.1, seed=11)
+    plan = wcal.plan_for(P, tol=0.0, max_iter=6)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    g = out["gains"].cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=6)
+        go = glue.gains_from_oracle(o["g"], 1, 1)
+        assert rel(g[k], go) <= 1e-5, (k, rel(g[k], go))
+        assert int(out["n_iter"][k]) == 6 and int(out["status"][k]) == oc.MAXITER
+        assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
+
+
+def test_triangle_pass_split_tiles(monkeypatch):
+    """Tiles holding one unit each (a 700-row target) give the same updates."""
+    log("[triangle tiles]")
+    monkeypatch.setenv("WCAL_TRI", "1")
+    monkeypatch.setenv("WCAL_TILE_ROWS", "700")
+    P = make("scalar", 100, [1, 3, 8], flag_frac=0.05, seed=12)
+    plan = wcal.plan_for(P, tol=0.0, max_iter=5)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    g = out["gains"].cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=5)
+        assert rel(g[k], glue.gains_from_oracle(o["g"], 1, 1)) <= 1e-5
+
+
+def test_triangle_pass_matches_generic_and_is_reproducible(monkeypatch):
+    log("[triangle vs generic]")
+    P = make("scalar", 70, [1, 4, 2], flag_frac=0.1, seed=13)
+    outs = {}
+    for tri in ("0", "1"):
+        monkeypatch.setenv("WCAL_TRI", tri)
+        plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
+        outs[tri] = [plan.solve(P.data, P.model, P.flags, P.unit_gains()) for _ in range(2)]
+    torch.cuda.synchronize()
+    a, b = outs["0"][0]["gains"].cpu().numpy(), outs["1"][0]["gains"].cpu().numpy()
+    assert rel(b, a) <= 1e-5
+    assert np.all(outs["1"][0]["status"].cpu().numpy() & oc.CONVERGED)
+    for key in ("gains", "n_iter", "chi2"):
+        x, y = outs["1"][0][key].cpu(), outs["1"][1][key].cpu()
+        assert torch.equal(x.view(torch.uint8) if x.is_complex() else x,
+                           y.view(torch.uint8) if y.is_complex() else y), key
+
+
+def test_triangle_pass_flags_and_status(monkeypatch):
+    """Garbage under flags leaves every output bit-identical; a fully flagged antenna is
+    SINGULAR_ANT with its gain kept; NaN in an unflagged row stops the interval before any
+    update; status bits equal the oracle's."""
+    log("[triangle flags/status]")
+    monkeypatch.setenv("WCAL_TRI", "1")
+    P = make("scalar", 70, [2, 3, 1], flag_frac=0.15, seed=14)
+    plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
+    clean = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    d2, m2 = P.data.clone(), P.model.clone()
+    f = P.flags.bool()
+    d2[f] = float("nan")
+    m2[f] = 1e30
+    dirty = plan.solve(d2, m2, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    for key in ("gains", "residual", "n_iter", "status", "chi2"):
+        a, b = clean[key].cpu(), dirty[key].cpu()
+        assert torch.equal(a.view(torch.uint8) if a.is_complex() else a,
+                           b.view(torch.uint8) if b.is_complex() else b), key
+    flags = P.flags.clone()
+    a1, a2 = P.ant1.cpu().numpy(), P.ant2.cpu().numpy()
+    bad = torch.as_tensor(np.where((a1 == 5) | (a2 == 5))[0], device=DEV)
+    for s in range(2):
+        flags[int(P.row_off[0]) + s * P.n_bl + bad] = 1
+    data = P.data.clone()
+    r1 = int(P.row_off[1]) + int(torch.nonzero(P.flags[int(P.row_off[1]):int(P.row_off[2])] == 0)[0])
+    data[r1, 0] = float("nan")
+    g0 = P.unit_gains()
+    g0[:, 0, 5, 0] = 0.5 - 0.25j
+    out = plan.solve(data, P.model, flags, g0.clone())
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    g = out["gains"].cpu().numpy()
+    for k in range(P.n_int):
+        iv = P.interval(k)
+        d = iv["d"][:, 0].copy()
+        if k == 1:
+            d[r1 - int(P.row_off[1])] = np.nan
+        fl = flags[int(P.row_off[k]):int(P.row_off[k + 1])].cpu().numpy() != 0
+        o = oc.stefcal_scalar(d, iv["m"][:, 0, 0], iv["p"], iv["q"], fl, g0[k, 0, :, 0].cpu().numpy().astype(complex),
+                              tol=1e-6, max_iter=100)
+        assert st[k] == o["status"], (k, st[k], o["status"])
+    assert st[0] & oc.SINGULAR_ANT and st[0] & oc.CONVERGED
+    assert np.array_equal(g[0, 0, 5], g0[0, 0, 5].cpu().numpy())
+    assert st[1] == oc.NONFINITE and int(out["n_iter"][1]) == 0
