@@ -204,11 +204,11 @@ def main():
     if args.mode == "pass":
         # every update's pass streams D, M and flags of the interval once
         kcls = "pass"
-        kname = "dd_gram_kernel<false>" if dd else "di_pass_kernel<%d>" % P.n_corr
+        kname = plan.pass_kernel
         krows = float((rows_k * it).sum()) * args.steps
     else:
         kcls = "stats"
-        kname = "dd_gram_kernel<false>" if dd else "di_stats_kernel<%d>" % P.n_corr
+        kname = plan.pass_kernel
         krows = float(P.n_rows) * args.steps
     kbytes = krows * bpr
     kms, klaunch = prof[kcls]

@@ -129,6 +129,13 @@ void wcal_plan_destroy(wcal_plan* plan);
 /* Total rows (sum over intervals of n_bl * ns[k]) described by the plan. */
 int64_t wcal_plan_rows(const wcal_plan* plan);
 
+/* Name of the kernel that streams the visibilities in this plan's solve: the per-update
+ * pass (PASS mode) or the one-off statistics pass (STATS mode).  Scalar StefCal whose
+ * baselines are every pair p < q in p-major order (the canonical table) runs the triangle
+ * pass by default from 64 antennas (environment WCAL_TRI=0 disables it, 1 forces it for any
+ * canonical table).  Static string owned by the library; "" for NULL. */
+const char* wcal_plan_pass_kernel(const wcal_plan* plan);
+
 /* Solve every interval: iterate the algorithm's update from the gains held in `gains`
  * until the relative parameter change drops below tol or max_iter updates were applied,
  * then predict the residual R = D - sum_d G_p M G_q^H with the final gains.

@@ -48,6 +48,11 @@ __host__ __device__ inline int rec_cnt(int nd) { return 2 * ntri(nd) + 4 * nd + 
 struct DdState {
     float* rec;          // [n_int][n_bl][rec_floats]
     double* chi_bl;      // [n_int][n_bl] chi^2 per baseline (accumulate)
+    float2* gn;          // [n_int][nd][n_ant] candidate gains of the current update
+    double* ant_d;       // [n_int][n_ant] |g_new - g|^2 per antenna
+    double* ant_n;       // [n_int][n_ant] |g_new|^2 per antenna
+    int32_t* ant_f;      // [n_int][n_ant] 1: non-finite block, 2: singular block
+    int32_t* alist;      // [2][n_int] intervals still iterating, by update parity
     const int32_t* ant_ptr;  // [n_ant + 1] CSR of (baseline, side) per antenna
     const int32_t* ant_bl;   // [2 n_bl]: 2 b + side (side 0: antenna is ant1, 1: ant2)
     int32_t* active;     // [n_int]
@@ -177,6 +182,163 @@ __global__ void __launch_bounds__(DT) dd_gram_kernel(DdArgs a, DdState st, int o
         if (lane == 0) {
             reinterpret_cast<int*>(rec)[rec_cnt(nd)] = cnt;
             if constexpr (WITH_R) st.chi_bl[(int64_t)k * nbl + b] = chi;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ blocked Gram pass
+// The solve's Gram pass (no residual column).  A workgroup owns GB consecutive baselines of
+// one interval and walks its samples in chunks of GS: for each sample the model rows of the
+// GB baselines are one contiguous segment (GB * Nd complex), so the chunk is read with
+// consecutive addresses across the workgroup, staged in registers while the previous chunk
+// is consumed, and laid out in LDS as [sample][baseline][16 columns].  Wavefront w then
+// runs the MFMAs of baselines 4w .. 4w + 3 from LDS (lane l: column l % 16 of sample l / 16,
+// as in the per-baseline kernel above).
+constexpr int GB = 16;                 // baselines per workgroup task
+constexpr int GS = 8;                  // samples per chunk
+constexpr int GELEM = GS * GB * (NDMAX + 1);
+constexpr int GPT = (GELEM + DT - 1) / DT;   // staged elements per thread (Nd = NDMAX)
+
+// list: the intervals to process (n_list of them), or null for every interval in LPT order
+__global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+    __shared__ float2 abuf[GS][GB][16];
+    __shared__ uint8_t fbuf[GS][GB];
+    __shared__ int s_task;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int nd = a.n_dir, nbl = a.n_bl;
+    const int RS = rec_floats(nd);
+    const int kk = lane >> 4;
+    const int col = lane & 15;
+    const int nbb = (nbl + GB - 1) / GB;
+    const int nint = list ? *n_list : a.n_int;
+    const int64_t ntask = (int64_t)nint * nbb;
+    if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
+    const bool has_flags = a.flags != nullptr;
+    const int nmod = GS * GB * nd;              // model elements of a chunk
+    const int nel = nmod + GS * GB;             // + data elements
+    // static decode of this thread's staged elements: chunk-relative global offset (in
+    // model or data elements) and a packed code (LDS slot | sample << 12 | baseline << 16;
+    // -1 for no element)
+    int goff[GPT], code[GPT];
+#pragma unroll
+    for (int r = 0; r < GPT; ++r) {
+        const int i = threadIdx.x + DT * r;
+        goff[r] = 0;
+        code[r] = -1;
+        if (i < nmod) {
+            const int sm = i / (GB * nd), e = i % (GB * nd);
+            goff[r] = sm * nbl * nd + e;
+            code[r] = ((sm * GB + e / nd) * 16 + e % nd) | (sm << 12) | ((e / nd) << 16);
+        } else if (i < nel) {
+            const int j = i - nmod, sm = j / GB, bl = j % GB;
+            goff[r] = sm * nbl + bl;
+            code[r] = ((sm * GB + bl) * 16 + nd) | (sm << 12) | (bl << 16);
+        }
+    }
+    const int fs = threadIdx.x / GB, fb = threadIdx.x % GB;   // flag staged by this thread
+    const bool fown = threadIdx.x < GS * GB;
+    float2* lds = &abuf[0][0][0];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
+        __syncthreads();
+        const int task = __builtin_amdgcn_readfirstlane(s_task);
+        if (task >= ntask) break;
+        const int k = list ? list[task / nbb] : a.order[task / nbb];
+        const int b0 = (task % nbb) * GB;
+        const int64_t off = a.row_off[k];
+        const int ns = a.ns[k];
+        const int nch = (ns + GS - 1) / GS;
+        float2 stage[GPT];
+        uint8_t fstage = 1;
+        auto fetch = [&](int c) {
+            const int s0 = c * GS;
+            const int64_t row0 = off + (int64_t)s0 * nbl + b0;
+            const float2* mb = a.model + row0 * nd;
+            const float2* db = a.data + row0;
+#pragma unroll
+            for (int r = 0; r < GPT; ++r) {
+                const int cd = code[r];
+                const bool ok = cd >= 0 && s0 + ((cd >> 12) & 15) < ns && b0 + (cd >> 16) < nbl;
+                const int i = threadIdx.x + DT * r;
+                stage[r] = make_float2(0.f, 0.f);
+                if (ok) stage[r] = i < nmod ? load_at(mb, goff[r]) : load_at(db, goff[r]);
+            }
+            const bool fok = fown && s0 + fs < ns && b0 + fb < nbl;
+            fstage = 1;
+            if (fok) fstage = has_flags ? (uint8_t)(a.flags[row0 + (int64_t)fs * nbl + fb] != 0) : (uint8_t)0;
+        };
+        floatx4 crr[4], cri[4];
+        int cnt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cnt[j] = 0;
+        }
+        fetch(0);
+        for (int c = 0; c < nch; ++c) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < GPT; ++r)
+                if (code[r] >= 0) lds[code[r] & 4095] = stage[r];
+            if (fown) fbuf[fs][fb] = fstage;
+            __syncthreads();
+            if (c + 1 < nch) fetch(c + 1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int bl = 4 * w + j;
+#pragma unroll
+                for (int g = 0; g < GS / 4; ++g) {
+                    const int sl = 4 * g + kk;
+                    const bool use = !fbuf[sl][bl];
+                    float2 v = make_float2(0.f, 0.f);
+                    if (use && col <= nd) v = abuf[sl][bl][col];
+                    if (use && col == 0) ++cnt[j];
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
+                    cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
+                }
+            }
+        }
+        // epilogue: each wavefront writes the records of its four baselines through its own
+        // 2 x 256-float area of the (now free) staging buffer
+        __syncthreads();
+        float* tile = reinterpret_cast<float*>(lds) + w * 512;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int b = b0 + 4 * w + j;
+            int cj = cnt[j];
+#pragma unroll
+            for (int o = WAVE / 2; o > 0; o >>= 1) cj += __shfl_xor(cj, o, WAVE);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * (lane >> 4) + r;
+                tile[i * 16 + col] = crr[j][r];
+                tile[256 + i * 16 + col] = cri[j][r];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (b < nbl) {
+                float* rec = st.rec + ((int64_t)k * nbl + b) * RS;
+                for (int e = lane; e < 256; e += WAVE) {
+                    const int i = e >> 4, jj = e & 15;
+                    const float re = tile[i * 16 + jj];
+                    const float im = tile[256 + i * 16 + jj] - tile[256 + jj * 16 + i];
+                    if (i <= jj && jj < nd) {
+                        const int t = tri(i, jj, nd);
+                        rec[2 * t] = re;
+                        rec[2 * t + 1] = im;
+                    } else if (i < nd && jj == nd) {
+                        rec[rec_z(nd) + 2 * i] = re;
+                        rec[rec_z(nd) + 2 * i + 1] = im;
+                    } else if (i == nd && jj == nd) {
+                        rec[rec_d2(nd)] = re;
+                    }
+                }
+                if (lane == 0) reinterpret_cast<int*>(rec)[rec_cnt(nd)] = cj;
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
@@ -328,119 +490,168 @@ __device__ DdSmem dd_smem(unsigned char* smem, int nd, int na) {
     return s;
 }
 
-// One update of interval k: per batch of BA antennas form their blocks, solve each
-// (CohJones: Cholesky; AllJones: diagonal, residual form), apply the schedule into Gn.
-// Then the FP64 relative change decides.  Returns 1 when the interval stops.
-__device__ int dd_update_step(const DdArgs& a, const DdState& st, int k, int it, const DdSmem& S, double* red,
-                              int* s_flags, uint32_t& status) {
-    const int nd = a.n_dir, na = a.n_ant;
-    const int nx = ntri(nd);
-    if (threadIdx.x == 0) { s_flags[0] = 0; s_flags[1] = 0; }
-    const bool avg = avg_step(it, a.schedule);
-    double dsum = 0.0, nsum = 0.0;
-    for (int p0 = 0; p0 < na; p0 += BA) {
-        const int nb = min(BA, na - p0);
-        __syncthreads();
-        dd_blocks<false>(a, st, k, S.G, p0, nb, S.H, S.C, nullptr, nullptr);
-        __syncthreads();
-        if (threadIdx.x < nb) {
-            const int j = threadIdx.x, p = p0 + j;
-            double2* h = S.H + j * nx;
-            const double2* c = S.C + j * nd;
-            double2* x = S.X + j * NDMAX;
-            bool fin = true;
-            for (int i = 0; i < nx; ++i) fin = fin && isfinite(h[i].x) && isfinite(h[i].y);
-            for (int i = 0; i < nd; ++i) fin = fin && isfinite(c[i].x) && isfinite(c[i].y);
-            if (!fin) s_flags[0] = 1;
-            bool ok = true;
-            if (a.algo == WCAL_COHJONES) {
-                ok = fin && chol_solve(h, c, x, nd);
+// counters: [0] one-off Gram pops, [2 + 2 it] Gram pops of update it, [3 + 2 it] intervals
+// listed for update it (it >= 1)
+__host__ __device__ inline int dd_pop_slot(int it) { return 2 + 2 * it; }
+__host__ __device__ inline int dd_nlist_slot(int it) { return 3 + 2 * it; }
+
+// LDS bytes of the gains [nd][na] in dd_ant_kernel, rounded up to 16 for the FP64 blocks
+__host__ __device__ inline size_t ant_g_bytes(int nd, int na) { return ((size_t)nd * na * 8 + 15) / 16 * 16; }
+
+// One update, per antenna: one wavefront forms H_p and c_p of one antenna (lanes over the
+// Nd(Nd+1)/2 + Nd entries, each summed over the antenna's baselines in CSR order, FP64),
+// then its first lane solves (CohJones: Cholesky; AllJones: diagonal, residual form),
+// applies the schedule and writes the candidate gains and its share of the FP64
+// relative-change norms.  The interval's decision follows in dd_finish_kernel.
+__global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nd = a.n_dir, na = a.n_ant, nbl = a.n_bl;
+    const int nx = ntri(nd), per = nx + nd;
+    const int nw = DT / WAVE;
+    const int ngrp = (na + nw - 1) / nw;
+    const int k = blockIdx.x / ngrp;
+    if (!st.active[k]) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int p = (blockIdx.x % ngrp) * nw + w;
+    float2* G = reinterpret_cast<float2*>(smem);                              // [nd][na]
+    double2* H = reinterpret_cast<double2*>(smem + ant_g_bytes(nd, na)) + w * (per + NDMAX);  // this wavefront's block
+    double2* C = H + nx;
+    double2* X = C + nd;
+    const float2* gk = a.gains + (int64_t)k * nd * na;
+    for (int i = threadIdx.x; i < nd * na; i += blockDim.x) G[i] = gk[i];
+    __syncthreads();
+    if (p < na) {
+        const int RS = rec_floats(nd);
+        const float* recs = st.rec + (int64_t)k * nbl * RS;
+        const int t0 = st.ant_ptr[p], t1 = st.ant_ptr[p + 1];
+        for (int e = lane; e < per; e += WAVE) {
+            int ci = 0, cj = 0;
+            if (e < nx) {
+                int rem = e;
+                while (rem >= nd - ci) { rem -= nd - ci; ++ci; }
+                cj = ci + rem;
             } else {
-                // AllJones: g^d + (c_d - sum_e H[d][e] g^e) / H[d][d], per direction
-                for (int d = 0; d < nd; ++d) {
-                    const double hdd = hget(h, d, d, nd).x;
-                    const float2 gd = S.G[d * na + p];
-                    if (!(hdd > 0.0)) {
-                        ok = false;
-                        x[d] = make_double2(gd.x, gd.y);
-                        continue;
-                    }
-                    double2 jr = c[d];
-                    for (int e = 0; e < nd; ++e) {
-                        const float2 ge = S.G[e * na + p];
-                        const double2 pr = dmul(hget(h, d, e, nd), make_double2(ge.x, ge.y));
-                        jr.x -= pr.x; jr.y -= pr.y;
-                    }
-                    x[d] = make_double2(gd.x + jr.x / hdd, gd.y + jr.y / hdd);
+                ci = e - nx;
+            }
+            double2 acc = make_double2(0.0, 0.0);
+            for (int t = t0; t < t1; ++t) {
+                const int code = st.ant_bl[t];
+                const int b = code >> 1, side = code & 1;
+                const int o = side ? a.ant1[b] : a.ant2[b];     // the other antenna of the row
+                const float* rec = recs + (int64_t)b * RS;
+                const float2 goc = G[ci * na + o];
+                if (e < nx) {
+                    const float2 goe = G[cj * na + o];
+                    const double2 x = make_double2(rec[2 * e], side ? -rec[2 * e + 1] : rec[2 * e + 1]);
+                    const double2 wv = make_double2((double)goc.x * goe.x + (double)goc.y * goe.y,
+                                                    (double)goc.y * goe.x - (double)goc.x * goe.y);
+                    const double2 pr = dmul(wv, x);
+                    acc.x += pr.x; acc.y += pr.y;
+                } else {
+                    const float* z = rec + rec_z(nd) + 2 * ci;
+                    const double2 pr = dmul(make_double2(goc.x, goc.y), make_double2(z[0], side ? -z[1] : z[1]));
+                    acc.x += pr.x; acc.y += pr.y;
                 }
             }
-            if (!ok) s_flags[1] = 1;
-            for (int d = 0; d < nd; ++d) {
-                const float2 go = S.G[d * na + p];
-                double nr, ni;
-                if (a.algo == WCAL_COHJONES && !ok) { nr = go.x; ni = go.y; }
-                else { nr = x[d].x; ni = x[d].y; }
-                if (avg) { nr = 0.5 * (go.x + nr); ni = 0.5 * (go.y + ni); }
-                const float2 gn = make_float2((float)nr, (float)ni);
-                S.Gn[d * na + p] = gn;
-                const double dr = (double)gn.x - go.x, di = (double)gn.y - go.y;
-                dsum += dr * dr + di * di;
-                nsum += (double)gn.x * gn.x + (double)gn.y * gn.y;
-            }
+            if (e < nx) H[e] = acc;
+            else C[ci] = acc;
         }
     }
-    dsum = block_sum(dsum, red);
-    nsum = block_sum(nsum, red);
-    if (s_flags[0]) { status |= WCAL_NONFINITE; __syncthreads(); return 1; }
-    if (s_flags[1]) status |= WCAL_SINGULAR_ANT;
-    for (int i = threadIdx.x; i < nd * na; i += blockDim.x) S.G[i] = S.Gn[i];
     __syncthreads();
-    const double num = sqrt(dsum), den = sqrt(nsum);
-    const double rel = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : num / den;
-    if (rel < a.tol) { status |= WCAL_CONVERGED; return 1; }
-    return 0;
+    if (p < na && lane == 0) {
+        bool fin = true;
+        for (int i = 0; i < nx; ++i) fin = fin && isfinite(H[i].x) && isfinite(H[i].y);
+        for (int i = 0; i < nd; ++i) fin = fin && isfinite(C[i].x) && isfinite(C[i].y);
+        bool ok = true;
+        if (a.algo == WCAL_COHJONES) {
+            ok = fin && chol_solve(H, C, X, nd);
+        } else {
+            // AllJones: g^d + (c_d - sum_e H[d][e] g^e) / H[d][d], per direction
+            for (int d = 0; d < nd; ++d) {
+                const double hdd = hget(H, d, d, nd).x;
+                const float2 gd = G[d * na + p];
+                if (!(hdd > 0.0)) {
+                    ok = false;
+                    X[d] = make_double2(gd.x, gd.y);
+                    continue;
+                }
+                double2 jr = C[d];
+                for (int e = 0; e < nd; ++e) {
+                    const float2 ge = G[e * na + p];
+                    const double2 pr = dmul(hget(H, d, e, nd), make_double2(ge.x, ge.y));
+                    jr.x -= pr.x; jr.y -= pr.y;
+                }
+                X[d] = make_double2(gd.x + jr.x / hdd, gd.y + jr.y / hdd);
+            }
+        }
+        const bool avg = avg_step(it, a.schedule);
+        double dsum = 0.0, nsum = 0.0;
+        float2* gn = st.gn + (int64_t)k * nd * na;
+        for (int d = 0; d < nd; ++d) {
+            const float2 go = G[d * na + p];
+            double nr, ni;
+            if (a.algo == WCAL_COHJONES && !ok) { nr = go.x; ni = go.y; }
+            else { nr = X[d].x; ni = X[d].y; }
+            if (avg) { nr = 0.5 * (go.x + nr); ni = 0.5 * (go.y + ni); }
+            const float2 g = make_float2((float)nr, (float)ni);
+            gn[d * na + p] = g;
+            const double dr = (double)g.x - go.x, di = (double)g.y - go.y;
+            dsum += dr * dr + di * di;
+            nsum += (double)g.x * g.x + (double)g.y * g.y;
+        }
+        st.ant_d[(int64_t)k * na + p] = dsum;
+        st.ant_n[(int64_t)k * na + p] = nsum;
+        st.ant_f[(int64_t)k * na + p] = (fin ? 0 : 1) | (ok ? 0 : 2);
+    }
 }
 
-// Iterate updates [it0, it1) of every interval (one workgroup per interval popped from the
-// queue).  Per-interval state (status, n_iter, active) lives in global memory so PASS mode
-// can call this once per update.
-__global__ void __launch_bounds__(DT) dd_iterate_kernel(DdArgs a, DdState st, int it0, int it1) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int nd = a.n_dir, na = a.n_ant;
-    DdSmem S = dd_smem(smem, nd, na);
+// The interval's decision after dd_ant_kernel: norms summed over antennas in a fixed
+// order; a non-finite block stops the interval before this update (gains kept); otherwise
+// the candidate becomes the gains, singular antennas are reported, and the relative change
+// and the iteration cap decide whether it keeps iterating.
+__global__ void __launch_bounds__(DT) dd_finish_kernel(DdArgs a, DdState st, int it) {
     __shared__ double red[DT / WAVE];
-    __shared__ int s_flags[2];
-    __shared__ int s_k;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_k = atomicAdd(&st.ctr[1], 1);
-        __syncthreads();
-        const int idx = __builtin_amdgcn_readfirstlane(s_k);
-        if (idx >= a.n_int) break;
-        const int k = a.order[idx];
-        if (!st.active[k]) continue;
+    __shared__ int s_f;
+    const int k = blockIdx.x;
+    if (!st.active[k]) return;
+    const int nd = a.n_dir, na = a.n_ant;
+    if (threadIdx.x == 0) s_f = 0;
+    __syncthreads();
+    double dsum = 0.0, nsum = 0.0;
+    int f = 0;
+    for (int p = threadIdx.x; p < na; p += blockDim.x) {
+        dsum += st.ant_d[(int64_t)k * na + p];
+        nsum += st.ant_n[(int64_t)k * na + p];
+        f |= st.ant_f[(int64_t)k * na + p];
+    }
+    if (f) atomicOr(&s_f, f);
+    dsum = block_sum(dsum, red);
+    nsum = block_sum(nsum, red);
+    const int flags = s_f;
+    uint32_t status = 0;
+    bool finished = false;
+    if (flags & 1) {
+        status |= WCAL_NONFINITE;
+        finished = true;
+    } else {
+        if (flags & 2) status |= WCAL_SINGULAR_ANT;
+        const float2* gn = st.gn + (int64_t)k * nd * na;
         float2* gk = a.gains + (int64_t)k * nd * na;
-        for (int i = threadIdx.x; i < nd * na; i += blockDim.x) S.G[i] = gk[i];
-        __syncthreads();
-        uint32_t status = 0;
-        int n_it = a.n_iter[k];
-        bool finished = false;
-        for (int it = it0; it < it1; ++it) {
-            const int stop = dd_update_step(a, st, k, it, S, red, s_flags, status);
-            if (status & WCAL_NONFINITE) { finished = true; break; }
-            n_it = it + 1;
-            if (stop) { finished = true; break; }
-        }
-        if (!finished && it1 >= a.max_iter) {
-            status |= WCAL_MAXITER;
-            finished = true;
-        }
-        for (int i = threadIdx.x; i < nd * na; i += blockDim.x) gk[i] = S.G[i];
-        if (threadIdx.x == 0) {
-            a.status[k] |= status;
-            a.n_iter[k] = n_it;
-            if (finished) st.active[k] = 0;
-        }
+        for (int i = threadIdx.x; i < nd * na; i += blockDim.x) gk[i] = gn[i];
+        const double num = sqrt(dsum), den = sqrt(nsum);
+        const double rel = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : num / den;
+        if (rel < a.tol) { status |= WCAL_CONVERGED; finished = true; }
+    }
+    if (!finished && it + 1 >= a.max_iter) {
+        status |= WCAL_MAXITER;
+        finished = true;
+    }
+    if (threadIdx.x == 0) {
+        a.status[k] |= status;
+        if (!(status & WCAL_NONFINITE)) a.n_iter[k] = it + 1;
+        if (finished) st.active[k] = 0;
+        else st.alist[((it + 1) & 1) * a.n_int + atomicAdd(&st.ctr[dd_nlist_slot(it + 1)], 1)] = k;
     }
 }
 
@@ -552,7 +763,13 @@ DdState state_of(const wcal_plan* plan) {
     DdState st;
     const int nd = plan->prob.n_dir;
     st.rec = plan->d_stats;
-    st.chi_bl = reinterpret_cast<double*>(plan->d_stats + (size_t)plan->prob.n_int * plan->prob.n_bl * rec_floats(nd));
+    const size_t nrec = (size_t)plan->prob.n_int * plan->prob.n_bl;
+    st.chi_bl = reinterpret_cast<double*>(plan->d_stats + nrec * rec_floats(nd));
+    st.ant_d = st.chi_bl + nrec;
+    st.ant_n = st.ant_d + (size_t)plan->prob.n_int * plan->prob.n_ant;
+    st.gn = reinterpret_cast<float2*>(st.ant_n + (size_t)plan->prob.n_int * plan->prob.n_ant);
+    st.ant_f = reinterpret_cast<int32_t*>(st.gn + (size_t)plan->prob.n_int * nd * plan->prob.n_ant);
+    st.alist = st.ant_f + (size_t)plan->prob.n_int * plan->prob.n_ant;
     st.ant_ptr = plan->d_ant_ptr;
     st.ant_bl = plan->d_ant_bl;
     st.active = plan->d_active;
@@ -568,7 +785,9 @@ DdState state_of(const wcal_plan* plan) {
 
 size_t dd_stats_bytes(const wcal_problem& p) {
     const size_t n = (size_t)p.n_int * p.n_bl;
-    return n * rec_floats(p.n_dir) * sizeof(float) + n * sizeof(double);
+    const size_t na = (size_t)p.n_int * p.n_ant;
+    return n * rec_floats(p.n_dir) * sizeof(float) + n * sizeof(double) + 2 * na * sizeof(double) +
+           na * p.n_dir * sizeof(float2) + na * sizeof(int32_t) + 2 * (size_t)p.n_int * sizeof(int32_t);
 }
 
 size_t dd_smem_bytes(int nd, int na) { return dd_smem_size(nd, na); }
@@ -589,31 +808,34 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     DdState st = state_of(plan);
     const int nd = a.n_dir, na = a.n_ant;
     const int nctr = 2 * (a.max_iter + 2) + 4;
-    const size_t sm = dd_smem_bytes(nd, na);
-    const int64_t ntask = (int64_t)a.n_int * a.n_bl;
-    const int gg = grid_res(plan, reinterpret_cast<const void*>(dd_gram_kernel<false>), 0, (ntask + 3) / 4);
-    const int gi = grid_res(plan, reinterpret_cast<const void*>(dd_iterate_kernel), sm, a.n_int);
+    const int64_t nblk = (int64_t)a.n_int * ((a.n_bl + GB - 1) / GB);
+    const int gg = grid_res(plan, reinterpret_cast<const void*>(dd_gram_blk_kernel), 0, nblk);
+    const int ngrp = (na + DT / WAVE - 1) / (DT / WAVE);
+    const size_t asm_ = ant_g_bytes(nd, na) + (size_t)(DT / WAVE) * (ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
     hipLaunchKernelGGL(dd_init_kernel, dim3((std::max(a.n_int, nctr) + DT - 1) / DT), dim3(DT), 0, s, a, st, 1, nctr);
     prof_end(plan, WCAL_K_OTHER, s);
-    if (plan->prob.mode == WCAL_MODE_STATS) {
+    const bool stats = plan->prob.mode == WCAL_MODE_STATS;
+    if (stats) {
         prof_begin(plan, WCAL_K_STATS, s);
-        hipLaunchKernelGGL(dd_gram_kernel<false>, dim3(gg), dim3(DT), 0, s, a, st, 0);
+        hipLaunchKernelGGL(dd_gram_blk_kernel, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr,
+                           (const int32_t*)nullptr);
         prof_end(plan, WCAL_K_STATS, s);
-        prof_begin(plan, WCAL_K_SOLVE_STATS, s);
-        hipLaunchKernelGGL(dd_iterate_kernel, dim3(gi), dim3(DT), sm, s, a, st, 0, a.max_iter);
-        prof_end(plan, WCAL_K_SOLVE_STATS, s);
-    } else {
-        for (int it = 0; it < a.max_iter; ++it) {
-            DdState sti = st;
-            sti.ctr = st.ctr + 2 + 2 * it;     // fresh pop counters per update
+    }
+    for (int it = 0; it < a.max_iter; ++it) {
+        DdState sti = st;
+        sti.ctr = st.ctr + dd_pop_slot(it);      // Gram pops of this update at sti.ctr[0]
+        if (!stats) {
+            const int32_t* lst = it == 0 ? nullptr : st.alist + (it & 1) * a.n_int;
             prof_begin(plan, WCAL_K_PASS, s);
-            hipLaunchKernelGGL(dd_gram_kernel<false>, dim3(gg), dim3(DT), 0, s, a, sti, 1);
+            hipLaunchKernelGGL(dd_gram_blk_kernel, dim3(gg), dim3(DT), 0, s, a, sti, lst,
+                               (const int32_t*)(st.ctr + dd_nlist_slot(it)));
             prof_end(plan, WCAL_K_PASS, s);
-            prof_begin(plan, WCAL_K_UPDATE, s);
-            hipLaunchKernelGGL(dd_iterate_kernel, dim3(gi), dim3(DT), sm, s, a, sti, it, it + 1);
-            prof_end(plan, WCAL_K_UPDATE, s);
         }
+        prof_begin(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);
+        hipLaunchKernelGGL(dd_ant_kernel, dim3(a.n_int * ngrp), dim3(DT), asm_, s, a, st, it);
+        hipLaunchKernelGGL(dd_finish_kernel, dim3(a.n_int), dim3(DT), 0, s, a, st, it);
+        prof_end(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -117,6 +117,13 @@ __device__ __forceinline__ void seg_add_int(int key, int v, int* acc) {
     if (tail && key >= 0) atomicAdd(&acc[key], v);
 }
 
+// element i (0 <= i, i * sizeof(T) < 2^32) of an array that starts at `base`, a
+// wavefront-uniform pointer, via a 32-bit byte offset so the load takes the scalar-base form
+template <typename T>
+__device__ __forceinline__ T load_at(const T* base, int i) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)i * (uint32_t)sizeof(T));
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = WAVE / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, WAVE);

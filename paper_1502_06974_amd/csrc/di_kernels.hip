@@ -654,13 +654,6 @@ __device__ __forceinline__ float wave_total(float x) {
 
 constexpr int TRI_U = 8;    // chunks in flight per lane
 
-// element i of a row segment that starts at `base` (a uniform pointer), via a 32-bit byte
-// offset so the load takes the scalar-base form
-template <typename T>
-__device__ __forceinline__ T load_at(const T* base, int i) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)i * (uint32_t)sizeof(T));
-}
-
 // One unit of a tile (samples [s0, s1) of interval k) into this wavefront's slice
 // acc[na + 1][3]; G holds na + 1 gains.  Lanes past the end of a row load the row's last
 // element (no extra memory traffic), contribute zeros, and add them to the spare slot na.

@@ -365,6 +365,15 @@ void wcal_plan_destroy(wcal_plan* plan) {
 
 int64_t wcal_plan_rows(const wcal_plan* plan) { return plan ? plan->rows : -1; }
 
+const char* wcal_plan_pass_kernel(const wcal_plan* plan) {
+    if (!plan) return "";
+    const wcal_problem& p = plan->prob;
+    if (p.algo != WCAL_STEFCAL) return "dd_gram_blk_kernel";
+    if (p.mode == WCAL_MODE_STATS) return p.n_corr == 1 ? "di_stats_kernel<1>" : "di_stats_kernel<4>";
+    if (plan->tri) return "di_tri_pass_kernel";
+    return p.n_corr == 1 ? "di_pass_kernel<1>" : "di_pass_kernel<4>";
+}
+
 static void fill_tables_di(const wcal_plan* plan, DiArgs& a) {
     a.ant1 = plan->d_ant1;
     a.ant2 = plan->d_ant2;

@@ -27,7 +27,7 @@ _MODES = {"pass": MODE_PASS, "stats": MODE_STATS}
 
 # every symbol the header declares
 EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
-           "wcal_plan_rows", "wcal_solve", "wcal_accumulate", "wcal_residual",
+           "wcal_plan_rows", "wcal_plan_pass_kernel", "wcal_solve", "wcal_accumulate", "wcal_residual",
            "wcal_profile_enable", "wcal_profile_read", "wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains",
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
@@ -69,6 +69,8 @@ def lib() -> C.CDLL:
     L.wcal_plan_destroy.restype = None
     L.wcal_plan_rows.argtypes = [vp]
     L.wcal_plan_rows.restype = C.c_int64
+    L.wcal_plan_pass_kernel.argtypes = [vp]
+    L.wcal_plan_pass_kernel.restype = C.c_char_p
     L.wcal_solve.argtypes = [vp] * 9 + [vp]
     L.wcal_solve.restype = C.c_int
     L.wcal_accumulate.argtypes = [vp] * 12
@@ -131,6 +133,7 @@ class Plan:
         _check(L.wcal_plan_create(C.byref(self.prob), _ptr(a1), _ptr(a2), _ptr(nsv), device,
                                   C.byref(self._h)))
         self.rows = int(L.wcal_plan_rows(self._h))
+        self.pass_kernel = L.wcal_plan_pass_kernel(self._h).decode()
 
     def close(self):
         if self._h:
