@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-alt-mode", action="store_true",
                     help="skip timing the other solve mode")
     ap.add_argument("--out-json", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager wcal_solve calls instead of replays of a captured HIP graph")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(a known-size reference for hardware byte counters)")
@@ -180,18 +182,37 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    plan.profile(True)            # HIP events around every kernel launch of the timed steps
+    # timed steps (the headline time), each one solve replayed from a HIP graph capture of
+    # wcal_solve (or eager calls with --no-graph); then the same number of eager steps with
+    # HIP events on the launch stream around every kernel launch, for the per-kernel
+    # durations (an event pair costs a few microseconds per launch, kept out of the headline)
+    timed = step
+    if not args.no_graph:
+        graph = plan.solve_graph(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter,
+                                 status=status, chi2=chi2)
+
+        def timed():
+            gains.copy_(g0)
+            graph.launch()
+
+        timed()
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        timed()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    plan.profile(True)
     plan.profile_read()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    tp0 = time.perf_counter()
     for i in range(args.steps):
         step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_step_profiled = (time.perf_counter() - tp0) * 1e3 / args.steps
     prof = plan.profile_read()
     plan.profile(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
 
     rows_k = (P.row_off[1:] - P.row_off[:-1]).to(torch.float64)
     it = n_iter.cpu().to(torch.float64)
@@ -246,6 +267,8 @@ def main():
             "flag_frac": 0.0 if P.flags is None else round(float(P.flags.float().mean()), 4),
         },
         "solve_time_ms": ms_step,
+        "timed_as": "eager wcal_solve calls" if args.no_graph else "HIP graph replays of wcal_solve",
+        "solve_time_ms_with_kernel_events": ms_step_profiled,
         "mode": args.mode,
         "mean_iters": float(it.mean()),
         "converged_frac": conv,

@@ -145,12 +145,30 @@ const char* wcal_plan_pass_kernel(const wcal_plan* plan);
  *   status   out    [n_int] WCAL_* status bits
  *   chi2     out    [n_int] sum of |R|^2 over unflagged rows (FP64), or NULL
  * The whole batch runs on the device with no host synchronisation: in PASS mode each
- * update is a tiled pass over the rows of the intervals still iterating plus a
- * per-interval update launch; in STATS mode one statistics pass is followed by one
- * launch that iterates every interval; both end with a tiled residual pass. */
+ * update is a tiled pass over the rows of the intervals still iterating plus the update
+ * launches; in STATS mode one statistics pass is followed by updates on the statistics
+ * (StefCal: one launch that iterates every interval; CohJones / AllJones: per-update
+ * launches); both end with a tiled residual pass.  No call allocates, synchronises the
+ * host or records a memset node, so the call can be captured into a HIP graph. */
 int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
                int32_t* n_iter, uint32_t* status, double* chi2, void* stream);
+
+/* A wcal_solve captured into an instantiated HIP graph (stream capture of exactly the
+ * launches wcal_solve makes; on a NULL stream the capture uses a private stream).  Each
+ * wcal_graph_launch re-runs the solve on `stream` with the same pointers, reading the
+ * current contents of data, model, flags and gains (gains are updated in place, so reset
+ * them for a fresh start).  The plan must outlive the graph; launches of graphs or calls
+ * that share a plan must not overlap (they share its scratch).  Profiling must be off
+ * while capturing.  Errors: WCAL_EINVAL (NULL, profiling on), WCAL_EHIP (capture or
+ * instantiation failed). */
+typedef struct wcal_graph wcal_graph;
+int wcal_solve_graph(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
+                     const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
+                     int32_t* n_iter, uint32_t* status, double* chi2, void* stream,
+                     wcal_graph** out);
+int wcal_graph_launch(wcal_graph* graph, void* stream);
+void wcal_graph_destroy(wcal_graph* graph);   /* NULL is a no-op */
 
 /* One fused pass at fixed gains, no iteration: per interval and antenna the blocks of
  * the approximate J^H J that the algorithm inverts, the top half of J^H D and of J^H r,

@@ -455,6 +455,71 @@ int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, con
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve launch");
 }
 
+struct wcal_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int wcal_solve_graph(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
+                     wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
+                     void* stream, wcal_graph** out) {
+    g_err.clear();
+    if (!out) return fail(WCAL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plan) return fail(WCAL_EINVAL, "plan is NULL");
+    if (plan->prof) return fail(WCAL_EINVAL, "disable profiling before capturing a solve");
+    if (hipSetDevice(plan->device) != hipSuccess) return fail(WCAL_EHIP, "hipSetDevice failed");
+    // the legacy null stream cannot be captured: capture on a private stream instead
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipStream_t own = nullptr;
+    if (!s) {
+        if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
+            return fail(WCAL_EHIP, "hipStreamCreateWithFlags failed");
+        s = own;
+    }
+    auto done = [&](int rc) {
+        if (own) (void)hipStreamDestroy(own);
+        return rc;
+    };
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return done(fail(WCAL_EHIP, "hipStreamBeginCapture failed"));
+    const int rc = wcal_solve(plan, data, model, flags, gains, residual, n_iter, status, chi2, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (rc != WCAL_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return done(rc);
+    }
+    if (ec != hipSuccess || !graph) return done(hip_fail(ec, "hipStreamEndCapture"));
+    auto* g = new wcal_graph();
+    g->device = plan->device;
+    g->graph = graph;
+    const hipError_t ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        wcal_graph_destroy(g);
+        return done(hip_fail(ei, "hipGraphInstantiate"));
+    }
+    *out = g;
+    return done(WCAL_OK);
+}
+
+int wcal_graph_launch(wcal_graph* graph, void* stream) {
+    g_err.clear();
+    if (!graph) return fail(WCAL_EINVAL, "graph is NULL");
+    if (hipSetDevice(graph->device) != hipSuccess) return fail(WCAL_EHIP, "hipSetDevice failed");
+    const hipError_t e = hipGraphLaunch(graph->exec, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WCAL_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+void wcal_graph_destroy(wcal_graph* graph) {
+    if (!graph) return;
+    (void)hipSetDevice(graph->device);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
 int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
                     const wcal_c64* gains, wcal_c64* jhj, wcal_c64* jhd, wcal_c64* jhr, int32_t* count,
                     double* chi2, wcal_c64* residual, void* stream) {

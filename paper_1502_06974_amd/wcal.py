@@ -27,7 +27,8 @@ _MODES = {"pass": MODE_PASS, "stats": MODE_STATS}
 
 # every symbol the header declares
 EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
-           "wcal_plan_rows", "wcal_plan_pass_kernel", "wcal_solve", "wcal_accumulate", "wcal_residual",
+           "wcal_plan_rows", "wcal_plan_pass_kernel", "wcal_solve", "wcal_solve_graph", "wcal_graph_launch",
+           "wcal_graph_destroy", "wcal_accumulate", "wcal_residual",
            "wcal_profile_enable", "wcal_profile_read", "wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains",
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
@@ -73,6 +74,12 @@ def lib() -> C.CDLL:
     L.wcal_plan_pass_kernel.restype = C.c_char_p
     L.wcal_solve.argtypes = [vp] * 9 + [vp]
     L.wcal_solve.restype = C.c_int
+    L.wcal_solve_graph.argtypes = [vp] * 10 + [C.POINTER(C.c_void_p)]
+    L.wcal_solve_graph.restype = C.c_int
+    L.wcal_graph_launch.argtypes = [vp, vp]
+    L.wcal_graph_launch.restype = C.c_int
+    L.wcal_graph_destroy.argtypes = [vp]
+    L.wcal_graph_destroy.restype = None
     L.wcal_accumulate.argtypes = [vp] * 12
     L.wcal_accumulate.restype = C.c_int
     L.wcal_residual.argtypes = [vp] * 8
@@ -208,6 +215,31 @@ class Plan:
                                 self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
+    def solve_graph(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
+                    chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True) -> "Graph":
+        """wcal_solve_graph: the solve captured into a replayable HIP graph bound to these
+        tensors (kept alive by the returned object)."""
+        self._inputs(data, model, flags, gains)
+        dev = gains.device
+        if residual is None and want_residual:
+            residual = torch.empty_like(data)
+        if n_iter is None:
+            n_iter = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if chi2 is None and want_chi2:
+            chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
+        self._dev(residual, "residual", torch.complex64, (self.rows, self.n_corr))
+        self._dev(n_iter, "n_iter", torch.int32, (self.n_int,))
+        self._dev(status, "status", torch.int32, (self.n_int,))
+        self._dev(chi2, "chi2", torch.float64, (self.n_int,))
+        h = C.c_void_p()
+        _check(lib().wcal_solve_graph(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
+                                      _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2),
+                                      self._stream(stream), C.byref(h)))
+        return Graph(h, self, dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2,
+                                   data=data, model=model, flags=flags))
+
     def accumulate(self, data, model, flags, gains, residual=None, stream=None,
                    want_residual: bool = False):
         """wcal_accumulate: one fused pass at fixed gains."""
@@ -238,6 +270,28 @@ class Plan:
         _check(lib().wcal_residual(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
                                    _ptr(residual), _ptr(chi2), self._stream(stream)))
         return dict(residual=residual, chi2=chi2)
+
+
+class Graph:
+    """A captured solve (wraps wcal_graph); `outputs` holds the bound tensors."""
+
+    def __init__(self, h, plan: "Plan", tensors: dict):
+        self._h, self.plan, self.outputs = h, plan, tensors
+
+    def launch(self, stream=None):
+        _check(lib().wcal_graph_launch(self._h, self.plan._stream(stream)))
+        return self.outputs
+
+    def close(self):
+        if self._h:
+            lib().wcal_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _cur_stream(stream=None):
