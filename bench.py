@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--no-alt-mode", action="store_true",
                     help="skip timing the other solve mode")
     ap.add_argument("--out-json", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tiling")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager wcal_solve calls instead of replays of a captured HIP graph")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -159,6 +160,11 @@ def main():
     algo = "stefcal" if P.n_dir == 1 else "cohjones"
     plan = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=args.mode)
     g0 = P.unit_gains()
+    tuned = None
+    if not args.no_autotune:
+        # tiling chosen by the plan autotuner on this workload (before the timed region)
+        tuned = plan.autotune(P.data, P.model, P.flags, g0, n_updates=3)
+        log(f"[bench] autotune: {tuned}")
     gains = g0.clone()
     residual = torch.empty_like(P.data)
     n_iter = torch.empty(P.n_int, dtype=torch.int32, device=dev)
@@ -268,6 +274,7 @@ def main():
         },
         "solve_time_ms": ms_step,
         "timed_as": "eager wcal_solve calls" if args.no_graph else "HIP graph replays of wcal_solve",
+        "autotune": tuned,
         "solve_time_ms_with_kernel_events": ms_step_profiled,
         "mode": args.mode,
         "mean_iters": float(it.mean()),

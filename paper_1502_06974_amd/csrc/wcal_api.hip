@@ -120,6 +120,121 @@ const char* wcal_last_error(void) { return g_err.c_str(); }
 
 const char* wcal_version(void) { return "wcal 0.1 (gfx950)"; }
 
+// (Re)build the tiles of a plan for a target of `tile_rows` rows per tile, with or without
+// the triangle pass (used only where the plan allows it), and (re)allocate what depends on
+// the tile count.  Host-side; no kernel runs.
+static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
+    const wcal_problem& p = plan->prob;
+    const std::vector<int32_t>& ns32 = plan->h_ns;
+    for (void** q : {(void**)&plan->d_tiles, (void**)&plan->d_tile_off, (void**)&plan->d_stiles,
+                     (void**)&plan->d_lists, (void**)&plan->d_partial, (void**)&plan->d_chi_part,
+                     (void**)&plan->d_units, (void**)&plan->d_ttiles, (void**)&plan->d_ttile_off}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+    plan->tile_rows = (int)tile_rows;
+    plan->nunits = plan->nttiles = 0;
+    plan->tri = want_tri && plan->canonical && p.algo == WCAL_STEFCAL && p.n_corr == 1 && p.mode == WCAL_MODE_PASS;
+    // tiles: samples per tile S and baselines per tile (a multiple of the 256-lane
+    // workgroup) chosen for about tile_rows rows; interval k owns a contiguous tile range
+    const int TBL = 256;
+    auto round_up = [](int64_t x, int64_t m) { return (x + m - 1) / m * m; };
+    std::vector<Tile> tiles, stiles;
+    std::vector<int32_t> tile_off(p.n_int + 1, 0);
+    for (int32_t k = 0; k < p.n_int; ++k) {
+        const int64_t tr = tile_rows;
+        const int32_t S = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tr / p.n_bl, ns32[k]));
+        const int32_t bc = (int32_t)std::min<int64_t>(std::max<int64_t>(round_up((tr + S - 1) / S, TBL), TBL),
+                                                       round_up(p.n_bl, TBL));
+        for (int32_t s0 = 0; s0 < ns32[k]; s0 += S)
+            for (int32_t b0 = 0; b0 < p.n_bl; b0 += bc)
+                tiles.push_back(Tile{k, b0, std::min(b0 + bc, p.n_bl), s0, std::min(s0 + S, ns32[k])});
+        tile_off[k + 1] = (int32_t)tiles.size();
+        if (p.mode == WCAL_MODE_STATS) {
+            const int32_t bs = (int32_t)std::min<int64_t>(
+                std::max<int64_t>(round_up((tr + ns32[k] - 1) / ns32[k], TBL), TBL), round_up(p.n_bl, TBL));
+            for (int32_t b0 = 0; b0 < p.n_bl; b0 += bs)
+                stiles.push_back(Tile{k, b0, std::min(b0 + bs, p.n_bl), 0, ns32[k]});
+        }
+        if (tiles.size() > (size_t)INT32_MAX / 2) return fail(WCAL_ESHAPE, "too many tiles");
+    }
+    std::vector<TriUnit> units;
+    std::vector<Tile> ttiles;
+    std::vector<int32_t> ttile_off(p.n_int + 1, 0);
+    if (plan->tri) {
+        // units: blocks of whole rows (at most 64) of about 8 chunks of 64 baselines (the
+        // cost of a row is its chunk count), then ordered largest first and dealt in snake
+        // order, so the round-robin share of each of the four wavefronts of a workgroup is
+        // even
+        const int32_t target = 8;
+        std::vector<TriUnit> raw;
+        for (int32_t r0 = 0; r0 < p.n_ant - 1;) {
+            int32_t r1 = r0, ent = 0, chunks = 0;
+            while (r1 < p.n_ant - 1 && r1 - r0 < 64) {
+                const int32_t len = p.n_ant - 1 - r1, ch = (len + 63) / 64;
+                if (r1 > r0 && chunks + ch > target) break;
+                ent += len;
+                chunks += ch;
+                ++r1;
+            }
+            raw.push_back(TriUnit{r0, r1, ent, chunks});
+            r0 = r1;
+        }
+        std::stable_sort(raw.begin(), raw.end(), [](const TriUnit& x, const TriUnit& y) { return x.chunks > y.chunks; });
+        const int nwv = 4;
+        std::vector<std::vector<TriUnit>> lanes(nwv);
+        for (size_t i = 0; i < raw.size(); ++i) {
+            const size_t r = i / nwv, c = i % nwv;
+            lanes[(r % 2 == 0) ? c : nwv - 1 - c].push_back(raw[i]);
+        }
+        for (size_t r = 0; r * nwv < raw.size(); ++r)
+            for (int c = 0; c < nwv; ++c)
+                if (r < lanes[c].size()) units.push_back(lanes[c][r]);
+        const int64_t tr = tile_rows;
+        for (int32_t k = 0; k < p.n_int; ++k) {
+            const int32_t S = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tr / p.n_bl, ns32[k]));
+            for (int32_t s0 = 0; s0 < ns32[k]; s0 += S) {
+                const int32_t s1 = std::min(s0 + S, ns32[k]);
+                int32_t u0 = 0;
+                while (u0 < (int32_t)units.size()) {
+                    int64_t ent = 0;
+                    int32_t u1 = u0;
+                    while (u1 < (int32_t)units.size() && (u1 == u0 || (ent + units[u1].entries) * (s1 - s0) <= tr))
+                        ent += units[u1++].entries;
+                    ttiles.push_back(Tile{k, u0, u1, s0, s1});
+                    u0 = u1;
+                }
+            }
+            ttile_off[k + 1] = (int32_t)ttiles.size();
+            if (ttiles.size() > (size_t)INT32_MAX / 2) return fail(WCAL_ESHAPE, "too many tiles");
+        }
+        plan->nunits = (int32_t)units.size();
+        plan->nttiles = (int32_t)ttiles.size();
+    }
+    // statistics tiles in decreasing-size order (longest first)
+    std::stable_sort(stiles.begin(), stiles.end(), [](const Tile& x, const Tile& y) {
+        return (int64_t)(x.b1 - x.b0) * (x.s1 - x.s0) > (int64_t)(y.b1 - y.b0) * (y.s1 - y.s0);
+    });
+    plan->ntiles = (int32_t)tiles.size();
+    plan->nstiles = (int32_t)stiles.size();
+    const int nvp = p.algo == WCAL_STEFCAL ? di_nvp(p.n_corr) : 0;
+    const int32_t ntmax = std::max(plan->ntiles, plan->nttiles);
+    hipError_t e = hipSuccess;
+    if (plan->tri && ((e = upload(&plan->d_units, units.data(), units.size())) != hipSuccess ||
+                      (e = upload(&plan->d_ttiles, ttiles.data(), ttiles.size())) != hipSuccess ||
+                      (e = upload(&plan->d_ttile_off, ttile_off.data(), ttile_off.size())) != hipSuccess))
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan units");
+    if ((e = upload(&plan->d_tiles, tiles.data(), tiles.size())) != hipSuccess ||
+        (e = upload(&plan->d_tile_off, tile_off.data(), tile_off.size())) != hipSuccess ||
+        (e = upload(&plan->d_stiles, stiles.data(), stiles.size())) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_lists), 2 * sizeof(int32_t) * std::max(1, ntmax))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_partial),
+                       sizeof(float) * std::max<size_t>(1, (size_t)ntmax * p.n_ant * nvp))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_chi_part), sizeof(double) * std::max(1, plan->ntiles))) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tiles");
+    return WCAL_OK;
+}
+
 int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int32_t* ant2_h,
                      const int64_t* ns_h, int device, wcal_plan** out) {
     g_err.clear();
@@ -188,125 +303,25 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         delete plan;
         return fail(WCAL_ESHAPE, "n_ant too large for the per-interval LDS working set");
     }
-    // tiles: samples per tile S and baselines per tile (a multiple of the 256-lane
-    // workgroup) chosen for about tile_rows rows; interval k owns a contiguous tile range
-    const int TBL = 256;
-    auto round_up = [](int64_t x, int64_t m) { return (x + m - 1) / m * m; };
-    std::vector<Tile> tiles, stiles;
-    std::vector<int32_t> tile_off(p.n_int + 1, 0);
-    for (int32_t k = 0; k < p.n_int; ++k) {
-        const int64_t tr = plan->tile_rows;
-        const int32_t S = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tr / p.n_bl, ns32[k]));
-        const int32_t bc = (int32_t)std::min<int64_t>(std::max<int64_t>(round_up((tr + S - 1) / S, TBL), TBL),
-                                                       round_up(p.n_bl, TBL));
-        for (int32_t s0 = 0; s0 < ns32[k]; s0 += S)
-            for (int32_t b0 = 0; b0 < p.n_bl; b0 += bc)
-                tiles.push_back(Tile{k, b0, std::min(b0 + bc, p.n_bl), s0, std::min(s0 + S, ns32[k])});
-        tile_off[k + 1] = (int32_t)tiles.size();
-        if (p.mode == WCAL_MODE_STATS) {
-            const int32_t bs = (int32_t)std::min<int64_t>(
-                std::max<int64_t>(round_up((tr + ns32[k] - 1) / ns32[k], TBL), TBL), round_up(p.n_bl, TBL));
-            for (int32_t b0 = 0; b0 < p.n_bl; b0 += bs)
-                stiles.push_back(Tile{k, b0, std::min(b0 + bs, p.n_bl), 0, ns32[k]});
-        }
-        if (tiles.size() > (size_t)INT32_MAX / 2) {
-            delete plan;
-            return fail(WCAL_ESHAPE, "too many tiles");
-        }
-    }
-    // triangle pass: scalar StefCal PASS solve with every pair p < q in p-major order
+    plan->h_ns = ns32;
     {
-        bool canonical = p.algo == WCAL_STEFCAL && p.n_corr == 1 && p.mode == WCAL_MODE_PASS &&
-                         (int64_t)p.n_bl == (int64_t)p.n_ant * (p.n_ant - 1) / 2;
+        bool canonical = (int64_t)p.n_bl == (int64_t)p.n_ant * (p.n_ant - 1) / 2;
         for (int32_t a = 0, b = 0; canonical && a < p.n_ant; ++a)
             for (int32_t c = a + 1; canonical && c < p.n_ant; ++c, ++b)
                 canonical = ant1_h[b] == a && ant2_h[b] == c;
-        const char* env = std::getenv("WCAL_TRI");
-        const int want = env ? atoi(env) : -1;   // 0: never, 1: whenever the order allows, unset: n_ant >= 64
-        plan->tri = canonical && (want == 1 || (want < 0 && p.n_ant >= 64));
+        plan->canonical = canonical;
     }
-    std::vector<TriUnit> units;
-    std::vector<Tile> ttiles;
-    std::vector<int32_t> ttile_off(p.n_int + 1, 0);
-    if (plan->tri) {
-        // units: blocks of whole rows (at most 64) of about 8 chunks of 64 baselines (the
-        // cost of a row is its chunk count), then ordered largest first and dealt in snake
-        // order, so the round-robin share of each of the four wavefronts of a workgroup is
-        // even
-        const int32_t target = 8;
-        std::vector<TriUnit> raw;
-        for (int32_t r0 = 0; r0 < p.n_ant - 1;) {
-            int32_t r1 = r0, ent = 0, chunks = 0;
-            while (r1 < p.n_ant - 1 && r1 - r0 < 64) {
-                const int32_t len = p.n_ant - 1 - r1, ch = (len + 63) / 64;
-                if (r1 > r0 && chunks + ch > target) break;
-                ent += len;
-                chunks += ch;
-                ++r1;
-            }
-            raw.push_back(TriUnit{r0, r1, ent, chunks});
-            r0 = r1;
-        }
-        std::stable_sort(raw.begin(), raw.end(), [](const TriUnit& x, const TriUnit& y) { return x.chunks > y.chunks; });
-        const int nwv = 4;
-        std::vector<std::vector<TriUnit>> lanes(nwv);
-        for (size_t i = 0; i < raw.size(); ++i) {
-            const size_t r = i / nwv, c = i % nwv;
-            lanes[(r % 2 == 0) ? c : nwv - 1 - c].push_back(raw[i]);
-        }
-        for (size_t r = 0; r * nwv < raw.size(); ++r)
-            for (int c = 0; c < nwv; ++c)
-                if (r < lanes[c].size()) units.push_back(lanes[c][r]);
-        const int64_t tr = plan->tile_rows;
-        for (int32_t k = 0; k < p.n_int; ++k) {
-            const int32_t S = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tr / p.n_bl, ns32[k]));
-            for (int32_t s0 = 0; s0 < ns32[k]; s0 += S) {
-                const int32_t s1 = std::min(s0 + S, ns32[k]);
-                int32_t u0 = 0;
-                while (u0 < (int32_t)units.size()) {
-                    int64_t ent = 0;
-                    int32_t u1 = u0;
-                    while (u1 < (int32_t)units.size() && (u1 == u0 || (ent + units[u1].entries) * (s1 - s0) <= tr))
-                        ent += units[u1++].entries;
-                    ttiles.push_back(Tile{k, u0, u1, s0, s1});
-                    u0 = u1;
-                }
-            }
-            ttile_off[k + 1] = (int32_t)ttiles.size();
-            if (ttiles.size() > (size_t)INT32_MAX / 2) {
-                delete plan;
-                return fail(WCAL_ESHAPE, "too many tiles");
-            }
-        }
-        plan->nunits = (int32_t)units.size();
-        plan->nttiles = (int32_t)ttiles.size();
-    }
-    // statistics tiles in decreasing-size order (longest first)
-    std::stable_sort(stiles.begin(), stiles.end(), [](const Tile& x, const Tile& y) {
-        return (int64_t)(x.b1 - x.b0) * (x.s1 - x.s0) > (int64_t)(y.b1 - y.b0) * (y.s1 - y.s0);
-    });
-    plan->ntiles = (int32_t)tiles.size();
-    plan->nstiles = (int32_t)stiles.size();
-    const int nvp = p.algo == WCAL_STEFCAL ? di_nvp(p.n_corr) : 0;
-    const int32_t ntmax = std::max(plan->ntiles, plan->nttiles);
+    const char* env_tri = std::getenv("WCAL_TRI");
+    const int want_tri = env_tri ? atoi(env_tri) : -1;   // 0: never, 1: whenever allowed, unset: n_ant >= 64
     hipError_t e = hipSuccess;
-    if (plan->tri && ((e = upload(&plan->d_units, units.data(), units.size())) != hipSuccess ||
-                      (e = upload(&plan->d_ttiles, ttiles.data(), ttiles.size())) != hipSuccess ||
-                      (e = upload(&plan->d_ttile_off, ttile_off.data(), ttile_off.size())) != hipSuccess)) {
+    if (int rc = build_tiles(plan, plan->tile_rows, want_tri == 1 || (want_tri < 0 && p.n_ant >= 64))) {
         wcal_plan_destroy(plan);
-        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan units");
+        return rc;
     }
-    if ((e = upload(&plan->d_tiles, tiles.data(), tiles.size())) != hipSuccess ||
-        (e = upload(&plan->d_tile_off, tile_off.data(), tile_off.size())) != hipSuccess ||
-        (e = upload(&plan->d_stiles, stiles.data(), stiles.size())) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_lists), 2 * sizeof(int32_t) * std::max(1, ntmax))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_ctr), sizeof(int32_t) * (2 * (p.max_iter + 2) + 16))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_partial),
-                       sizeof(float) * std::max<size_t>(1, (size_t)ntmax * p.n_ant * nvp))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_active), sizeof(int32_t) * p.n_int)) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_chi_part), sizeof(double) * std::max(1, plan->ntiles))) != hipSuccess) {
+    if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_ctr), sizeof(int32_t) * (2 * (p.max_iter + 2) + 16))) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_active), sizeof(int32_t) * p.n_int)) != hipSuccess) {
         wcal_plan_destroy(plan);
-        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tiles");
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan state");
     }
     if (p.algo == WCAL_STEFCAL && p.mode == WCAL_MODE_STATS) {
         plan->stats_bytes = sizeof(float) * (size_t)p.n_int * p.n_bl * di_nstat(p.n_corr);
@@ -453,6 +468,89 @@ int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, con
         e = launch_dd_solve(plan, a, s);
     }
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve launch");
+}
+
+int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
+                       const wcal_c64* gains, int32_t n_updates, void* stream, int32_t* tile_rows_out,
+                       int32_t* tri_out) {
+    g_err.clear();
+    int rc = check_common(plan, data, model, gains);
+    if (rc) return rc;
+    if (n_updates < 1 || n_updates > plan->prob.max_iter)
+        return fail(WCAL_EINVAL, "n_updates must be in [1, max_iter]");
+    if (plan->prof) return fail(WCAL_EINVAL, "disable profiling before tuning");
+    wcal_problem& p = plan->prob;
+    auto report = [&]() {
+        if (tile_rows_out) *tile_rows_out = plan->tile_rows;
+        if (tri_out) *tri_out = plan->tri ? 1 : 0;
+        return WCAL_OK;
+    };
+    // CohJones / AllJones stream the rows in their own blocked Gram pass: nothing to tune
+    if (p.algo != WCAL_STEFCAL) return report();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t gbytes = (size_t)p.n_int * p.n_dir * p.n_ant * p.n_corr * sizeof(wcal_c64);
+    wcal_c64* g = nullptr;
+    int32_t* nit = nullptr;
+    uint32_t* st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (g) (void)hipFree(g);
+        if (nit) (void)hipFree(nit);
+        if (st) (void)hipFree(st);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(reinterpret_cast<void**>(&g), gbytes) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&nit), sizeof(int32_t) * p.n_int) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&st), sizeof(uint32_t) * p.n_int) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(WCAL_ENOMEM, "autotune scratch allocation failed");
+    }
+    // every candidate applies exactly n_updates updates (tol 0) from the given gains
+    const int saved_iter = p.max_iter;
+    const double saved_tol = p.tol;
+    p.max_iter = n_updates;
+    p.tol = 0.0;
+    const bool tri_ok = plan->canonical && p.n_corr == 1 && p.mode == WCAL_MODE_PASS;
+    const int64_t rows_cand[] = {16384, 32768, 65536, 131072, 262144};
+    int64_t best_rows = plan->tile_rows;
+    bool best_tri = plan->tri;
+    float best_ms = 1e30f;
+    int err = WCAL_OK;
+    for (int tri = 0; tri <= (tri_ok ? 1 : 0) && err == WCAL_OK; ++tri) {
+        for (int64_t tr : rows_cand) {
+            if ((err = build_tiles(plan, tr, tri != 0)) != WCAL_OK) break;
+            float ms = 1e30f;
+            for (int rep = 0; rep < 3 && err == WCAL_OK; ++rep) {
+                if (hipMemcpyAsync(g, gains, gbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                    hipEventRecord(e0, s) != hipSuccess) {
+                    err = fail(WCAL_EHIP, "autotune copy failed");
+                    break;
+                }
+                err = wcal_solve(plan, data, model, flags, g, nullptr, nit, st, nullptr, stream);
+                if (err != WCAL_OK) break;
+                float t = 0.f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+                    err = fail(WCAL_EHIP, "autotune timing failed");
+                    break;
+                }
+                if (rep > 0) ms = std::min(ms, t);      // the first run warms caches and code
+            }
+            if (err == WCAL_OK && ms < best_ms) {
+                best_ms = ms;
+                best_rows = tr;
+                best_tri = tri != 0;
+            }
+        }
+    }
+    p.max_iter = saved_iter;
+    p.tol = saved_tol;
+    cleanup();
+    if (err != WCAL_OK) return err;
+    if ((err = build_tiles(plan, best_rows, best_tri)) != WCAL_OK) return err;
+    return report();
 }
 
 struct wcal_graph {

@@ -2,8 +2,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "wcal.h"
 
@@ -30,6 +32,7 @@ struct wcal_plan {
     int n_cu = 0;
     int64_t rows = 0;
     int32_t max_ns = 0;
+    std::vector<int32_t> h_ns;    // samples per interval (host copy, for re-tiling)
     // device tables (plan-owned)
     int32_t* d_ant1 = nullptr;    // [n_bl]
     int32_t* d_ant2 = nullptr;    // [n_bl]
@@ -61,6 +64,7 @@ struct wcal_plan {
     int tile_rows = 0;            // target rows per tile
     // triangle pass (scalar StefCal, canonical baseline order): units and tiles whose
     // b0/b1 are unit ranges; the PASS solve uses these tiles for its pass and update
+    bool canonical = false;       // baselines are every pair p < q in p-major order
     bool tri = false;
     TriUnit* d_units = nullptr;
     int32_t nunits = 0;

@@ -27,7 +27,7 @@ _MODES = {"pass": MODE_PASS, "stats": MODE_STATS}
 
 # every symbol the header declares
 EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
-           "wcal_plan_rows", "wcal_plan_pass_kernel", "wcal_solve", "wcal_solve_graph", "wcal_graph_launch",
+           "wcal_plan_rows", "wcal_plan_pass_kernel", "wcal_plan_autotune", "wcal_solve", "wcal_solve_graph", "wcal_graph_launch",
            "wcal_graph_destroy", "wcal_accumulate", "wcal_residual",
            "wcal_profile_enable", "wcal_profile_read", "wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains",
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
@@ -70,6 +70,8 @@ def lib() -> C.CDLL:
     L.wcal_plan_destroy.restype = None
     L.wcal_plan_rows.argtypes = [vp]
     L.wcal_plan_rows.restype = C.c_int64
+    L.wcal_plan_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp, vp]
+    L.wcal_plan_autotune.restype = C.c_int
     L.wcal_plan_pass_kernel.argtypes = [vp]
     L.wcal_plan_pass_kernel.restype = C.c_char_p
     L.wcal_solve.argtypes = [vp] * 9 + [vp]
@@ -214,6 +216,15 @@ class Plan:
                                 _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2),
                                 self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
+
+    def autotune(self, data, model, flags, gains, n_updates: int = 3, stream=None) -> dict:
+        """wcal_plan_autotune: time the candidate tilings on these inputs and keep the fastest."""
+        self._inputs(data, model, flags, gains)
+        tr, tri = C.c_int32(0), C.c_int32(0)
+        _check(lib().wcal_plan_autotune(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains), n_updates,
+                                        self._stream(stream), C.byref(tr), C.byref(tri)))
+        self.pass_kernel = lib().wcal_plan_pass_kernel(self._h).decode()
+        return {"tile_rows": tr.value, "triangle": bool(tri.value), "pass_kernel": self.pass_kernel}
 
     def solve_graph(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
                     chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True) -> "Graph":
