@@ -89,6 +89,12 @@ typedef struct { float re, im; } wcal_c64;
 #define WCAL_MODE_PASS  0
 #define WCAL_MODE_STATS 1
 
+/* Precision of the CohJones / AllJones Gram pass (the per-sample products): FP32 MFMA
+ * (default), or BF16 MFMA with FP32 accumulation (inputs rounded to BF16; the per-antenna
+ * solve stays FP64).  StefCal accepts only WCAL_PREC_FP32. */
+#define WCAL_PREC_FP32       0
+#define WCAL_PREC_BF16_GRAM  1
+
 /* singular-block threshold: a 2x2 block with det Z <= EPS * Z00 * Z11 or an Nd x Nd
  * Cholesky pivot <= EPS * H_jj is treated as not invertible. */
 #define WCAL_EPS_PIVOT 1e-5
@@ -104,6 +110,7 @@ typedef struct {
     int32_t max_iter;  /* maximum number of updates (>= 1)           */
     double  tol;       /* relative parameter-change tolerance (>= 0) */
     int32_t mode;      /* WCAL_MODE_PASS | WCAL_MODE_STATS                 */
+    int32_t precision; /* WCAL_PREC_FP32 (0) | WCAL_PREC_BF16_GRAM          */
 } wcal_problem;
 
 typedef struct wcal_plan wcal_plan;

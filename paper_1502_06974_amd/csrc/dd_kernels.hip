@@ -194,13 +194,28 @@ __global__ void __launch_bounds__(DT) dd_gram_kernel(DdArgs a, DdState st, int o
 // is consumed, and laid out in LDS as [sample][baseline][16 columns].  Wavefront w then
 // runs the MFMAs of baselines 4w .. 4w + 3 from LDS (lane l: column l % 16 of sample l / 16,
 // as in the per-baseline kernel above).
+// BF16 variant (plan precision WCAL_PREC_BF16_GRAM): the products are taken by
+// v_mfma_f32_16x16x16_bf16 (16 samples per MFMA: lane l holds 4 consecutive samples of
+// column l % 16, starting at sample 4 (l / 16)), the staged FP32 values rounded to BF16
+// (nearest, ties to even) and accumulated in FP32.
 constexpr int GB = 16;                 // baselines per workgroup task
-constexpr int GS = 8;                  // samples per chunk
-constexpr int GELEM = GS * GB * (NDMAX + 1);
-constexpr int GPT = (GELEM + DT - 1) / DT;   // staged elements per thread (Nd = NDMAX)
+template <bool BF> struct GramShape {
+    static constexpr int gs = BF ? 16 : 8;                             // samples per chunk
+    static constexpr int gpt = (gs * GB * (NDMAX + 1) + DT - 1) / DT;  // staged elements per thread
+};
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest, ties to even (infinities and NaN stay non-finite)
+__device__ __forceinline__ short bf16_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
 
 // list: the intervals to process (n_list of them), or null for every interval in LPT order
+template <bool BF>
 __global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+    constexpr int GS = GramShape<BF>::gs;
+    constexpr int GPT = GramShape<BF>::gpt;
     __shared__ float2 abuf[GS][GB][16];
     __shared__ uint8_t fbuf[GS][GB];
     __shared__ int s_task;
@@ -289,16 +304,33 @@ __global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, c
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int bl = 4 * w + j;
+                if constexpr (BF) {
+                    shortx4 re, im;
 #pragma unroll
-                for (int g = 0; g < GS / 4; ++g) {
-                    const int sl = 4 * g + kk;
-                    const bool use = !fbuf[sl][bl];
-                    float2 v = make_float2(0.f, 0.f);
-                    if (use && col <= nd) v = abuf[sl][bl][col];
-                    if (use && col == 0) ++cnt[j];
-                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
-                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
-                    cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
+                    for (int i = 0; i < 4; ++i) {
+                        const int sl = 4 * kk + i;
+                        const bool use = !fbuf[sl][bl];
+                        float2 v = make_float2(0.f, 0.f);
+                        if (use && col <= nd) v = abuf[sl][bl][col];
+                        if (use && col == 0) ++cnt[j];
+                        re[i] = bf16_bits(v.x);
+                        im[i] = bf16_bits(v.y);
+                    }
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(re, re, crr[j], 0, 0, 0);
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(im, im, crr[j], 0, 0, 0);
+                    cri[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(re, im, cri[j], 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int g = 0; g < GS / 4; ++g) {
+                        const int sl = 4 * g + kk;
+                        const bool use = !fbuf[sl][bl];
+                        float2 v = make_float2(0.f, 0.f);
+                        if (use && col <= nd) v = abuf[sl][bl][col];
+                        if (use && col == 0) ++cnt[j];
+                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
+                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
+                        cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -809,7 +841,10 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const int nd = a.n_dir, na = a.n_ant;
     const int nctr = 2 * (a.max_iter + 2) + 4;
     const int64_t nblk = (int64_t)a.n_int * ((a.n_bl + GB - 1) / GB);
-    const int gg = grid_res(plan, reinterpret_cast<const void*>(dd_gram_blk_kernel), 0, nblk);
+    const bool bf = plan->prob.precision == WCAL_PREC_BF16_GRAM;
+    const void* gram_fn = bf ? reinterpret_cast<const void*>(dd_gram_blk_kernel<true>)
+                             : reinterpret_cast<const void*>(dd_gram_blk_kernel<false>);
+    const int gg = grid_res(plan, gram_fn, 0, nblk);
     const int ngrp = (na + DT / WAVE - 1) / (DT / WAVE);
     const size_t asm_ = ant_g_bytes(nd, na) + (size_t)(DT / WAVE) * (ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
@@ -818,8 +853,12 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const bool stats = plan->prob.mode == WCAL_MODE_STATS;
     if (stats) {
         prof_begin(plan, WCAL_K_STATS, s);
-        hipLaunchKernelGGL(dd_gram_blk_kernel, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr,
-                           (const int32_t*)nullptr);
+        if (bf)
+            hipLaunchKernelGGL(dd_gram_blk_kernel<true>, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr);
+        else
+            hipLaunchKernelGGL(dd_gram_blk_kernel<false>, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr);
         prof_end(plan, WCAL_K_STATS, s);
     }
     for (int it = 0; it < a.max_iter; ++it) {
@@ -828,8 +867,9 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
         if (!stats) {
             const int32_t* lst = it == 0 ? nullptr : st.alist + (it & 1) * a.n_int;
             prof_begin(plan, WCAL_K_PASS, s);
-            hipLaunchKernelGGL(dd_gram_blk_kernel, dim3(gg), dim3(DT), 0, s, a, sti, lst,
-                               (const int32_t*)(st.ctr + dd_nlist_slot(it)));
+            const int32_t* nl = st.ctr + dd_nlist_slot(it);
+            if (bf) hipLaunchKernelGGL(dd_gram_blk_kernel<true>, dim3(gg), dim3(DT), 0, s, a, sti, lst, nl);
+            else hipLaunchKernelGGL(dd_gram_blk_kernel<false>, dim3(gg), dim3(DT), 0, s, a, sti, lst, nl);
             prof_end(plan, WCAL_K_PASS, s);
         }
         prof_begin(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);

@@ -247,6 +247,10 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
     if (!(p.tol >= 0.0)) return fail(WCAL_EINVAL, "tol must be >= 0");
     if (p.schedule < WCAL_AVG_FIRST || p.schedule > WCAL_GN_ONLY) return fail(WCAL_EINVAL, "unknown schedule");
     if (p.mode != WCAL_MODE_PASS && p.mode != WCAL_MODE_STATS) return fail(WCAL_EINVAL, "unknown mode");
+    if (p.precision != WCAL_PREC_FP32 && p.precision != WCAL_PREC_BF16_GRAM)
+        return fail(WCAL_EINVAL, "unknown precision");
+    if (p.precision != WCAL_PREC_FP32 && p.algo == WCAL_STEFCAL)
+        return fail(WCAL_EINVAL, "the BF16 Gram is for CohJones / AllJones");
     if (p.max_iter > 100000) return fail(WCAL_ESHAPE, "max_iter > 100000");
     if (p.algo == WCAL_STEFCAL) {
         if (p.n_dir != 1) return fail(WCAL_EINVAL, "StefCal needs n_dir == 1 (use CohJones/AllJones)");

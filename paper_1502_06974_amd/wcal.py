@@ -24,6 +24,8 @@ _ALGOS = {"stefcal": STEFCAL, "cohjones": COHJONES, "alljones": ALLJONES}
 _SCHED = {"avg_first": AVG_FIRST, "gn_first": GN_FIRST, "gn_only": GN_ONLY}
 MODE_PASS, MODE_STATS = 0, 1
 _MODES = {"pass": MODE_PASS, "stats": MODE_STATS}
+PREC_FP32, PREC_BF16_GRAM = 0, 1
+_PRECS = {"fp32": PREC_FP32, "bf16": PREC_BF16_GRAM}
 
 # every symbol the header declares
 EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
@@ -46,7 +48,7 @@ class Problem(C.Structure):
     _fields_ = [("n_ant", C.c_int32), ("n_bl", C.c_int32), ("n_dir", C.c_int32),
                 ("n_corr", C.c_int32), ("n_int", C.c_int32), ("algo", C.c_int32),
                 ("schedule", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
-                ("mode", C.c_int32)]
+                ("mode", C.c_int32), ("precision", C.c_int32)]
 
 
 _lib = None
@@ -128,13 +130,13 @@ class Plan:
 
     def __init__(self, n_ant: int, ant1, ant2, ns, n_dir: int = 1, n_corr: int = 1,
                  algo: str = "stefcal", schedule: str = "avg_first", max_iter: int = 100,
-                 tol: float = 1e-6, device: int = 0, mode: str = "pass"):
+                 tol: float = 1e-6, device: int = 0, mode: str = "pass", precision: str = "fp32"):
         L = lib()
         a1 = torch.as_tensor(ant1, dtype=torch.int32).cpu().contiguous()
         a2 = torch.as_tensor(ant2, dtype=torch.int32).cpu().contiguous()
         nsv = torch.as_tensor(ns, dtype=torch.int64).cpu().contiguous()
         self.prob = Problem(n_ant, a1.numel(), n_dir, n_corr, nsv.numel(), _ALGOS[algo],
-                            _SCHED[schedule], max_iter, tol, _MODES[mode])
+                            _SCHED[schedule], max_iter, tol, _MODES[mode], _PRECS[precision])
         self.n_ant, self.n_bl, self.n_dir, self.n_corr, self.n_int = n_ant, a1.numel(), n_dir, n_corr, nsv.numel()
         self.device = device
         self.ant1, self.ant2, self.ns = a1, a2, nsv

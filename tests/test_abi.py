@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def _create(n_ant, a1, a2, ns, **kw):
     p = wcal.Problem(n_ant, len(a1), kw.get("n_dir", 1), kw.get("n_corr", 1), len(ns),
                      kw.get("algo", 0), kw.get("schedule", 0), kw.get("max_iter", 10), kw.get("tol", 1e-6),
-                     kw.get("mode", 0))
+                     kw.get("mode", 0), kw.get("precision", 0))
     a1 = np.asarray(a1, np.int32)
     a2 = np.asarray(a2, np.int32)
     ns = np.asarray(ns, np.int64)
@@ -53,6 +53,8 @@ def _create(n_ant, a1, a2, ns, **kw):
     ([0, 0, 1], [1, 2, 2], [2], {"tol": -1.0}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"schedule": 7}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"mode": 5}, wcal.EINVAL),
+    ([0, 0, 1], [1, 2, 2], [2], {"precision": 1}, wcal.EINVAL),         # BF16 Gram with StefCal
+    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_dir": 2, "precision": 7}, wcal.EINVAL),
 ])
 def test_plan_validation_errors(a1, a2, ns, kw, code):
     rc, h = _create(3, a1, a2, ns, **kw)
