@@ -21,6 +21,8 @@
 // applies the schedule and the FP64 relative-change test.  In STATS mode the Gram pass
 // runs once and one launch iterates every interval; in PASS mode the Gram pass is
 // repeated before every update.  A tiled residual pass ends the solve.
+#include <cstdlib>
+
 #include "di_common.h"
 
 using namespace wcal_dev;
@@ -194,15 +196,9 @@ __global__ void __launch_bounds__(DT) dd_gram_kernel(DdArgs a, DdState st, int o
 // is consumed, and laid out in LDS as [sample][baseline][16 columns].  Wavefront w then
 // runs the MFMAs of baselines 4w .. 4w + 3 from LDS (lane l: column l % 16 of sample l / 16,
 // as in the per-baseline kernel above).
-// BF16 variant (plan precision WCAL_PREC_BF16_GRAM): the products are taken by
-// v_mfma_f32_16x16x16_bf16 (16 samples per MFMA: lane l holds 4 consecutive samples of
-// column l % 16, starting at sample 4 (l / 16)), the staged FP32 values rounded to BF16
-// (nearest, ties to even) and accumulated in FP32.
 constexpr int GB = 16;                 // baselines per workgroup task
-template <bool BF> struct GramShape {
-    static constexpr int gs = BF ? 16 : 8;                             // samples per chunk
-    static constexpr int gpt = (gs * GB * (NDMAX + 1) + DT - 1) / DT;  // staged elements per thread
-};
+constexpr int GS = 8;                  // samples per chunk (register-staged FP32 kernel)
+constexpr int GPT = (GS * GB * (NDMAX + 1) + DT - 1) / DT;   // staged elements per thread
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16 bits, round to nearest, ties to even (infinities and NaN stay non-finite)
@@ -212,10 +208,7 @@ __device__ __forceinline__ short bf16_bits(float f) {
 }
 
 // list: the intervals to process (n_list of them), or null for every interval in LPT order
-template <bool BF>
 __global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
-    constexpr int GS = GramShape<BF>::gs;
-    constexpr int GPT = GramShape<BF>::gpt;
     __shared__ float2 abuf[GS][GB][16];
     __shared__ uint8_t fbuf[GS][GB];
     __shared__ int s_task;
@@ -304,33 +297,16 @@ __global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, c
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int bl = 4 * w + j;
-                if constexpr (BF) {
-                    shortx4 re, im;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int sl = 4 * kk + i;
-                        const bool use = !fbuf[sl][bl];
-                        float2 v = make_float2(0.f, 0.f);
-                        if (use && col <= nd) v = abuf[sl][bl][col];
-                        if (use && col == 0) ++cnt[j];
-                        re[i] = bf16_bits(v.x);
-                        im[i] = bf16_bits(v.y);
-                    }
-                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(re, re, crr[j], 0, 0, 0);
-                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(im, im, crr[j], 0, 0, 0);
-                    cri[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(re, im, cri[j], 0, 0, 0);
-                } else {
-#pragma unroll
-                    for (int g = 0; g < GS / 4; ++g) {
-                        const int sl = 4 * g + kk;
-                        const bool use = !fbuf[sl][bl];
-                        float2 v = make_float2(0.f, 0.f);
-                        if (use && col <= nd) v = abuf[sl][bl][col];
-                        if (use && col == 0) ++cnt[j];
-                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
-                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
-                        cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
-                    }
+                for (int g = 0; g < GS / 4; ++g) {
+                    const int sl = 4 * g + kk;
+                    const bool use = !fbuf[sl][bl];
+                    float2 v = make_float2(0.f, 0.f);
+                    if (use && col <= nd) v = abuf[sl][bl][col];
+                    if (use && col == 0) ++cnt[j];
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
+                    cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
                 }
             }
         }
@@ -338,6 +314,143 @@ __global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, c
         // 2 x 256-float area of the (now free) staging buffer
         __syncthreads();
         float* tile = reinterpret_cast<float*>(lds) + w * 512;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int b = b0 + 4 * w + j;
+            int cj = cnt[j];
+#pragma unroll
+            for (int o = WAVE / 2; o > 0; o >>= 1) cj += __shfl_xor(cj, o, WAVE);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * (lane >> 4) + r;
+                tile[i * 16 + col] = crr[j][r];
+                tile[256 + i * 16 + col] = cri[j][r];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (b < nbl) {
+                float* rec = st.rec + ((int64_t)k * nbl + b) * RS;
+                for (int e = lane; e < 256; e += WAVE) {
+                    const int i = e >> 4, jj = e & 15;
+                    const float re = tile[i * 16 + jj];
+                    const float im = tile[256 + i * 16 + jj] - tile[256 + jj * 16 + i];
+                    if (i <= jj && jj < nd) {
+                        const int t = tri(i, jj, nd);
+                        rec[2 * t] = re;
+                        rec[2 * t + 1] = im;
+                    } else if (i < nd && jj == nd) {
+                        rec[rec_z(nd) + 2 * i] = re;
+                        rec[rec_z(nd) + 2 * i + 1] = im;
+                    } else if (i == nd && jj == nd) {
+                        rec[rec_d2(nd)] = re;
+                    }
+                }
+                if (lane == 0) reinterpret_cast<int*>(rec)[rec_cnt(nd)] = cj;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// BF16 Gram pass (plan precision WCAL_PREC_BF16_GRAM): the products are taken by
+// v_mfma_f32_16x16x16_bf16, 16 samples per MFMA (lane l holds 4 consecutive samples of
+// column l % 16, starting at sample 4 (l / 16)), from values rounded to BF16 (nearest, ties
+// to even), accumulated in FP32.  With the MFMA work this small the pass is a stream: the
+// model rows are copied straight from HBM into LDS (global_load_lds), with no register
+// staging, so more workgroups fit per CU and hide each other's copy phases.  Same work split
+// as dd_gram_blk_kernel, chunks of GSD = 16 samples.  The model rows of a chunk land in LDS
+// in their HBM order, [sample][baseline][Nd], as pieces of PIECE bytes: 16 when Nd is even
+// and the model array is 16-byte aligned (every sample's segment is then 16-byte aligned),
+// else 4.  Data and flags (9 B per row) go through registers.  (With FP32 MFMAs the copy
+// and the products do not overlap inside a workgroup and the register-staged kernel is
+// faster; a double-buffered copy serialises, because the compiler waits for every
+// outstanding copy before any LDS read.)
+constexpr int GSD = 16;
+
+template <int PIECE>
+__global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+    __shared__ __align__(16) float2 mbuf[GSD * GB * NDMAX];
+    __shared__ float2 dbuf[GSD][GB];
+    __shared__ uint8_t fbuf[GSD][GB];
+    __shared__ int s_task;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int nd = a.n_dir, nbl = a.n_bl;
+    const int RS = rec_floats(nd);
+    const int kk = lane >> 4;
+    const int col = lane & 15;
+    const int nbb = (nbl + GB - 1) / GB;
+    const int nint = list ? *n_list : a.n_int;
+    const int64_t ntask = (int64_t)nint * nbb;
+    if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
+    const bool has_flags = a.flags != nullptr;
+    const int seg_bytes = GB * nd * 8;          // one sample's model segment
+    const int pps = seg_bytes / PIECE;          // pieces per sample
+    const int npc = GSD * pps;                  // pieces per chunk
+    const int ds = threadIdx.x / GB, db = threadIdx.x % GB;   // data / flag element of this thread
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
+        __syncthreads();
+        const int task = __builtin_amdgcn_readfirstlane(s_task);
+        if (task >= ntask) break;
+        const int k = list ? list[task / nbb] : a.order[task / nbb];
+        const int b0 = (task % nbb) * GB;
+        const int64_t off = a.row_off[k];
+        const int ns = a.ns[k];
+        const int nch = (ns + GSD - 1) / GSD;
+        floatx4 crr[4], cri[4];
+        int cnt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cnt[j] = 0;
+        }
+        for (int c = 0; c < nch; ++c) {
+            const int s0 = c * GSD;
+            // model: pieces p = p0 + lane of the chunk, p0 uniform per wavefront; piece p lands
+            // at byte p * PIECE of mbuf
+            for (int p0 = w * WAVE; p0 < npc; p0 += DT) {
+                const int p = p0 + lane;
+                const int sm = p / pps, jb = (p - sm * pps) * PIECE;
+                const bool ok = p < npc && s0 + sm < ns && b0 + jb / (8 * nd) < nbl;
+                if (ok) {
+                    const char* src = reinterpret_cast<const char*>(a.model + (off + (int64_t)(s0 + sm) * nbl + b0) * nd) + jb;
+                    auto dst = (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(mbuf) + p0 * PIECE);
+                    if constexpr (PIECE == 16) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+                    else __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+                }
+            }
+            {
+                const bool ok = s0 + ds < ns && b0 + db < nbl;
+                const int64_t row = off + (int64_t)(s0 + ds) * nbl + b0 + db;
+                dbuf[ds][db] = ok ? a.data[row] : make_float2(0.f, 0.f);
+                fbuf[ds][db] = ok ? (has_flags ? (uint8_t)(a.flags[row] != 0) : (uint8_t)0) : (uint8_t)1;
+            }
+            __syncthreads();     // the model pieces have landed (the barrier waits for them)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int bl = 4 * w + j;
+                shortx4 re, im;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int sl = 4 * kk + i;
+                    const bool use = !fbuf[sl][bl];
+                    float2 v = make_float2(0.f, 0.f);
+                    if (use && col < nd) v = mbuf[(sl * GB + bl) * nd + col];
+                    else if (use && col == nd) v = dbuf[sl][bl];
+                    if (use && col == 0) ++cnt[j];
+                    re[i] = bf16_bits(v.x);
+                    im[i] = bf16_bits(v.y);
+                }
+                crr[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(re, re, crr[j], 0, 0, 0);
+                crr[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(im, im, crr[j], 0, 0, 0);
+                cri[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(re, im, cri[j], 0, 0, 0);
+            }
+            __syncthreads();     // every wavefront is done with this chunk before the next lands
+        }
+        // epilogue through each wavefront's own 2 x 256 floats of mbuf (free now)
+        float* tile = reinterpret_cast<float*>(mbuf) + w * 512;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int b = b0 + 4 * w + j;
@@ -842,9 +955,10 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const int nctr = 2 * (a.max_iter + 2) + 4;
     const int64_t nblk = (int64_t)a.n_int * ((a.n_bl + GB - 1) / GB);
     const bool bf = plan->prob.precision == WCAL_PREC_BF16_GRAM;
-    const void* gram_fn = bf ? reinterpret_cast<const void*>(dd_gram_blk_kernel<true>)
-                             : reinterpret_cast<const void*>(dd_gram_blk_kernel<false>);
-    const int gg = grid_res(plan, gram_fn, 0, nblk);
+    const bool p16 = nd % 2 == 0 && reinterpret_cast<uintptr_t>(a.model) % 16 == 0;
+    typedef void (*GramFn)(DdArgs, DdState, const int32_t*, const int32_t*);
+    GramFn gram = !bf ? dd_gram_blk_kernel : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
+    const int gg = grid_res(plan, reinterpret_cast<const void*>(gram), 0, nblk);
     const int ngrp = (na + DT / WAVE - 1) / (DT / WAVE);
     const size_t asm_ = ant_g_bytes(nd, na) + (size_t)(DT / WAVE) * (ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
@@ -853,12 +967,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const bool stats = plan->prob.mode == WCAL_MODE_STATS;
     if (stats) {
         prof_begin(plan, WCAL_K_STATS, s);
-        if (bf)
-            hipLaunchKernelGGL(dd_gram_blk_kernel<true>, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr,
-                               (const int32_t*)nullptr);
-        else
-            hipLaunchKernelGGL(dd_gram_blk_kernel<false>, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr,
-                               (const int32_t*)nullptr);
+        hipLaunchKernelGGL(gram, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr, (const int32_t*)nullptr);
         prof_end(plan, WCAL_K_STATS, s);
     }
     for (int it = 0; it < a.max_iter; ++it) {
@@ -868,8 +977,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
             const int32_t* lst = it == 0 ? nullptr : st.alist + (it & 1) * a.n_int;
             prof_begin(plan, WCAL_K_PASS, s);
             const int32_t* nl = st.ctr + dd_nlist_slot(it);
-            if (bf) hipLaunchKernelGGL(dd_gram_blk_kernel<true>, dim3(gg), dim3(DT), 0, s, a, sti, lst, nl);
-            else hipLaunchKernelGGL(dd_gram_blk_kernel<false>, dim3(gg), dim3(DT), 0, s, a, sti, lst, nl);
+            hipLaunchKernelGGL(gram, dim3(gg), dim3(DT), 0, s, a, sti, lst, nl);
             prof_end(plan, WCAL_K_PASS, s);
         }
         prof_begin(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);

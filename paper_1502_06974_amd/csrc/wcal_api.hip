@@ -387,7 +387,7 @@ int64_t wcal_plan_rows(const wcal_plan* plan) { return plan ? plan->rows : -1; }
 const char* wcal_plan_pass_kernel(const wcal_plan* plan) {
     if (!plan) return "";
     const wcal_problem& p = plan->prob;
-    if (p.algo != WCAL_STEFCAL) return "dd_gram_blk_kernel";
+    if (p.algo != WCAL_STEFCAL) return p.precision == WCAL_PREC_BF16_GRAM ? "dd_gram_dma_kernel" : "dd_gram_blk_kernel";
     if (p.mode == WCAL_MODE_STATS) return p.n_corr == 1 ? "di_stats_kernel<1>" : "di_stats_kernel<4>";
     if (plan->tri) return "di_tri_pass_kernel";
     return p.n_corr == 1 ? "di_pass_kernel<1>" : "di_pass_kernel<4>";
