@@ -732,6 +732,13 @@ __device__ __forceinline__ void tri_unit(const DiArgs& a, const Tile& T, const T
     }
 }
 
+template <int NC>
+__device__ void finish_interval(const DiArgs& a, int it, int k, int t0, int t1, const float* acc, float2* G,
+                                float2* Gn, double* red, int* s_flags, int* s_pos);
+
+// FUSED: every interval is one tile, so the workgroup that sums a tile holds its interval's
+// complete sums and applies the update itself (no partials, no update launch).
+template <bool FUSED>
 __global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit* __restrict__ units, int it) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NVP = Nv<1, 0>::v;
@@ -739,6 +746,10 @@ __global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit
     const int ns = (na + 1) * NVP;                  // slice: na antennas + the spare slot
     float2* G = reinterpret_cast<float2*>(smem);    // na + 1 (the last is 0)
     float* acc = reinterpret_cast<float*>(G + na + 1);
+    float2* Gn = reinterpret_cast<float2*>(acc + (TB / WAVE) * ns);   // FUSED: candidate gains
+    __shared__ double red[TB / WAVE];
+    __shared__ int s_flags[2];
+    __shared__ int s_pos;
     __shared__ int s_t;
     const int nw = blockDim.x / WAVE;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
@@ -760,12 +771,55 @@ __global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit
         __syncthreads();
         for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
         __syncthreads();
-        float* out = a.partial + (int64_t)t * na * NVP;
-        for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
-            float v = acc[i];
-            for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * ns + i];
-            out[i] = v;
+        if constexpr (FUSED) {
+            // fold the wavefront slices into the first, in wavefront order
+            for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                float v = acc[i];
+                for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * ns + i];
+                acc[i] = v;
+            }
+            __syncthreads();
+            finish_interval<1>(a, it, T.k, t, t + 1, acc, G, Gn, red, s_flags, &s_pos);
+        } else {
+            float* out = a.partial + (int64_t)t * na * NVP;
+            for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                float v = acc[i];
+                for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * ns + i];
+                out[i] = v;
+            }
         }
+    }
+}
+
+// Update `it` of interval k from its folded sums acc[na][NVP] (LDS): solve, schedule and
+// convergence (update_step), write the gains, the status, the update count and the
+// activity, and list the interval's tiles [t0, t1) for the next update if it keeps
+// iterating.  Every thread of the workgroup must call this.
+template <int NC>
+__device__ void finish_interval(const DiArgs& a, int it, int k, int t0, int t1, const float* acc, float2* G,
+                                float2* Gn, double* red, int* s_flags, int* s_pos) {
+    const int na = a.n_ant;
+    float2* gk = a.gains + (int64_t)k * na * NC;
+    uint32_t status = 0;
+    const int stop = update_step<NC>(a, it, acc, G, Gn, red, s_flags, status);
+    bool finished = stop != 0;
+    if (!(status & WCAL_NONFINITE)) {
+        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) gk[i] = G[i];
+    }
+    if (!finished && it + 1 >= a.max_iter) {
+        status |= WCAL_MAXITER;
+        finished = true;
+    }
+    if (threadIdx.x == 0) {
+        a.status[k] |= status;
+        if (!(status & WCAL_NONFINITE)) a.n_iter[k] = it + 1;
+        if (finished) a.active[k] = 0;
+        else *s_pos = atomicAdd(&a.ctr[qoff(a) + it + 1], t1 - t0);
+    }
+    if (!finished) {
+        __syncthreads();
+        int32_t* next = a.lists + ((it + 1) & 1) * a.ntiles;
+        for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) next[*s_pos + i] = t0 + i;
     }
 }
 
@@ -791,27 +845,7 @@ __global__ void __launch_bounds__(TB) di_update_kernel(DiArgs a, int it) {
         acc[i] = v;
     }
     __syncthreads();
-    uint32_t status = 0;
-    const int stop = update_step<NC>(a, it, acc, G, Gn, red, s_flags, status);
-    bool finished = stop != 0;
-    if (!(status & WCAL_NONFINITE)) {
-        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) gk[i] = G[i];
-    }
-    if (!finished && it + 1 >= a.max_iter) {
-        status |= WCAL_MAXITER;
-        finished = true;
-    }
-    if (threadIdx.x == 0) {
-        a.status[k] |= status;
-        if (!(status & WCAL_NONFINITE)) a.n_iter[k] = it + 1;
-        if (finished) a.active[k] = 0;
-        else s_pos = atomicAdd(&a.ctr[qoff(a) + it + 1], t1 - t0);
-    }
-    if (!finished) {
-        __syncthreads();
-        int32_t* next = a.lists + ((it + 1) & 1) * a.ntiles;
-        for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) next[s_pos + i] = t0 + i;
-    }
+    finish_interval<NC>(a, it, k, t0, t1, acc, G, Gn, red, s_flags, &s_pos);
 }
 
 template <int NC>
@@ -988,15 +1022,24 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
         at.tiles = plan->d_ttiles;
         at.tile_off = plan->d_ttile_off;
         at.ntiles = plan->nttiles;
-        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TB / WAVE) * (na + 1) * 3 * sizeof(float);
-        const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_tri_pass_kernel), TB, ps, at.ntiles);
+        const bool fused = plan->nttiles == a.n_int;    // one tile per interval
+        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TB / WAVE) * (na + 1) * 3 * sizeof(float) +
+                          (fused ? (size_t)na * sizeof(float2) : 0);
+        const void* fn = fused ? reinterpret_cast<const void*>(di_tri_pass_kernel<true>)
+                               : reinterpret_cast<const void*>(di_tri_pass_kernel<false>);
+        const int gp = grid_resident(plan, fn, TB, ps, at.ntiles);
         for (int it = 0; it < a.max_iter; ++it) {
             prof_begin(plan, WCAL_K_PASS, s);
-            hipLaunchKernelGGL(di_tri_pass_kernel, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
+            if (fused)
+                hipLaunchKernelGGL(di_tri_pass_kernel<true>, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
+            else
+                hipLaunchKernelGGL(di_tri_pass_kernel<false>, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
             prof_end(plan, WCAL_K_PASS, s);
-            prof_begin(plan, WCAL_K_UPDATE, s);
-            hipLaunchKernelGGL(di_update_kernel<1>, dim3(a.n_int), dim3(TB), us, s, at, it);
-            prof_end(plan, WCAL_K_UPDATE, s);
+            if (!fused) {
+                prof_begin(plan, WCAL_K_UPDATE, s);
+                hipLaunchKernelGGL(di_update_kernel<1>, dim3(a.n_int), dim3(TB), us, s, at, it);
+                prof_end(plan, WCAL_K_UPDATE, s);
+            }
         }
     } else {
         const size_t ps = pass_smem(na, NC);
