@@ -322,7 +322,7 @@ def main():
         else:
             # BF16 MFMA issues 16x faster: the pass is bound by HBM
             out["roofline_mfma"] = mfma
-    if not args.no_alt_mode:
+    if not args.no_alt_mode and args.precision == "fp32":     # the BF16 Gram runs in PASS mode only
         alt = "stats" if args.mode == "pass" else "pass"
         plan_alt = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=alt,
                                  precision=args.precision)

@@ -85,13 +85,17 @@ typedef struct { float re, im; } wcal_c64;
  * PASS  -- every update streams all samples of the interval (per-sample J^H J / J^H D pass);
  * STATS -- the gain-independent per-baseline sums over samples are formed in one pass and
  *          every update contracts them with the current gains (cost independent of the
- *          number of samples per interval). */
+ *          number of samples per interval).  A StefCal plan whose intervals all hold one
+ *          sample runs the PASS solve in this mode: one sample's statistics are no smaller
+ *          than the sample. */
 #define WCAL_MODE_PASS  0
 #define WCAL_MODE_STATS 1
 
 /* Precision of the CohJones / AllJones Gram pass (the per-sample products): FP32 MFMA
  * (default), or BF16 MFMA with FP32 accumulation (inputs rounded to BF16; the per-antenna
- * solve stays FP64).  StefCal accepts only WCAL_PREC_FP32. */
+ * solve stays FP64).  The BF16 Gram also forms the residual in FP32 and the update takes
+ * the residual form g + H^-1 J^H r (Eq. ghat:approx), so the fixed point does not carry the
+ * rounding of H; it needs PASS mode and Nd <= 13.  StefCal accepts only WCAL_PREC_FP32. */
 #define WCAL_PREC_FP32       0
 #define WCAL_PREC_BF16_GRAM  1
 

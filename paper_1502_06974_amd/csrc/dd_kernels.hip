@@ -206,6 +206,23 @@ __device__ __forceinline__ short bf16_bits(float f) {
     const uint32_t u = __float_as_uint(f);
     return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
+__device__ __forceinline__ float bf16_value(short b) { return __uint_as_float((uint32_t)(uint16_t)b << 16); }
+
+// x from the lane given by a DPP control within the same row of 16 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp16(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+// Sum over each row of 16 lanes, left in every lane of the row: butterfly over the lane
+// partners i^1, i^2 (quad permutations), i^7 (half-row mirror) and i^15 (row mirror), whose
+// masks span the 16 lanes.  Call with every lane active.
+__device__ __forceinline__ float2 row16_sum(float2 v) {
+    v.x += dpp16<0xB1>(v.x);  v.y += dpp16<0xB1>(v.y);     // quad_perm [1, 0, 3, 2]
+    v.x += dpp16<0x4E>(v.x);  v.y += dpp16<0x4E>(v.y);     // quad_perm [2, 3, 0, 1]
+    v.x += dpp16<0x141>(v.x); v.y += dpp16<0x141>(v.y);    // row_half_mirror
+    v.x += dpp16<0x140>(v.x); v.y += dpp16<0x140>(v.y);    // row_mirror
+    return v;
+}
 
 // list: the intervals to process (n_list of them), or null for every interval in LPT order
 __global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
@@ -360,7 +377,13 @@ __global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, c
 // as dd_gram_blk_kernel, chunks of GSD = 16 samples.  The model rows of a chunk land in LDS
 // in their HBM order, [sample][baseline][Nd], as pieces of PIECE bytes: 16 when Nd is even
 // and the model array is 16-byte aligned (every sample's segment is then 16-byte aligned),
-// else 4.  Data and flags (9 B per row) go through registers.  (With FP32 MFMAs the copy
+// else 4.  Data and flags (9 B per row) go through registers.  Columns Nd + 1 and Nd + 2
+// carry the residual r = d - sum_c g^c_p m^c conj(g^c_q), formed in FP32 from the current
+// gains and split into its BF16 rounding and the remainder (so M^H r keeps ~16 bits of r),
+// and the update takes the residual form g + H^-1 J^H r: its fixed point is that of the
+// exact sums up to the fixed rounding of M, although H comes from BF16 products.  A single
+// BF16 column for r would make J^H r jump with the rounding of r as the gains move, and
+// the iteration would chatter above the tolerance instead of converging.  Needs Nd <= 13.  (With FP32 MFMAs the copy
 // and the products do not overlap inside a workgroup and the register-staged kernel is
 // faster; a double-buffered copy serialises, because the compiler waits for every
 // outstanding copy before any LDS read.)
@@ -400,11 +423,16 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
         const int nch = (ns + GSD - 1) / GSD;
         floatx4 crr[4], cri[4];
         int cnt[4];
+        float2 wgt[4];           // g^c_p conj(g^c_q) of this lane's column for its 4 baselines
+        const float2* gk = a.gains + (int64_t)k * nd * a.n_ant;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cnt[j] = 0;
+            const int b = b0 + 4 * w + j;
+            wgt[j] = make_float2(0.f, 0.f);
+            if (b < nbl && col < nd) wgt[j] = cmulc(gk[col * a.n_ant + a.ant1[b]], gk[col * a.n_ant + a.ant2[b]]);
         }
         for (int c = 0; c < nch; ++c) {
             const int s0 = c * GSD;
@@ -440,6 +468,17 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
                     if (use && col < nd) v = mbuf[(sl * GB + bl) * nd + col];
                     else if (use && col == nd) v = dbuf[sl][bl];
                     if (use && col == 0) ++cnt[j];
+                    // residual r = d - sum_c g^c_p m^c conj(g^c_q) in FP32: lane col < nd holds
+                    // -g m conj(g) of its direction, lane nd holds d, and one butterfly over
+                    // the 16 lanes of the sample leaves r in each of them
+                    float2 t = col == nd ? v : cmul(wgt[j], v);
+                    if (col < nd) { t.x = -t.x; t.y = -t.y; }
+                    t = row16_sum(t);
+                    const float2 r = use ? t : make_float2(0.f, 0.f);
+                    // r in two BF16 columns: nd + 1 the rounded value, nd + 2 what rounding left
+                    if (col == nd + 1) v = r;
+                    if (col == nd + 2)
+                        v = make_float2(r.x - bf16_value(bf16_bits(r.x)), r.y - bf16_value(bf16_bits(r.y)));
                     re[i] = bf16_bits(v.x);
                     im[i] = bf16_bits(v.y);
                 }
@@ -477,6 +516,10 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
                     } else if (i < nd && jj == nd) {
                         rec[rec_z(nd) + 2 * i] = re;
                         rec[rec_z(nd) + 2 * i + 1] = im;
+                    } else if (i < nd && jj == nd + 1) {
+                        // J^H r from the two residual columns
+                        rec[rec_w(nd) + 2 * i] = re + tile[i * 16 + jj + 1];
+                        rec[rec_w(nd) + 2 * i + 1] = im + tile[256 + i * 16 + jj + 1] - tile[256 + (jj + 1) * 16 + i];
                     } else if (i == nd && jj == nd) {
                         rec[rec_d2(nd)] = re;
                     }
@@ -656,6 +699,7 @@ __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it
     const int ngrp = (na + nw - 1) / nw;
     const int k = blockIdx.x / ngrp;
     if (!st.active[k]) return;
+    const bool resid = a.precision == WCAL_PREC_BF16_GRAM;   // J^H r in C, residual-form update
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int p = (blockIdx.x % ngrp) * nw + w;
@@ -694,7 +738,8 @@ __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it
                     const double2 pr = dmul(wv, x);
                     acc.x += pr.x; acc.y += pr.y;
                 } else {
-                    const float* z = rec + rec_z(nd) + 2 * ci;
+                    // c_p (data form) or, with the BF16 Gram, J^H r (residual form)
+                    const float* z = rec + (resid ? rec_w(nd) : rec_z(nd)) + 2 * ci;
                     const double2 pr = dmul(make_double2(goc.x, goc.y), make_double2(z[0], side ? -z[1] : z[1]));
                     acc.x += pr.x; acc.y += pr.y;
                 }
@@ -709,7 +754,15 @@ __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it
         for (int i = 0; i < nx; ++i) fin = fin && isfinite(H[i].x) && isfinite(H[i].y);
         for (int i = 0; i < nd; ++i) fin = fin && isfinite(C[i].x) && isfinite(C[i].y);
         bool ok = true;
-        if (a.algo == WCAL_COHJONES) {
+        if (a.algo == WCAL_COHJONES && resid) {
+            // g + H^-1 J^H r
+            ok = fin && chol_solve(H, C, X, nd);
+            if (ok)
+                for (int d = 0; d < nd; ++d) {
+                    const float2 gd = G[d * na + p];
+                    X[d] = make_double2(gd.x + X[d].x, gd.y + X[d].y);
+                }
+        } else if (a.algo == WCAL_COHJONES) {
             ok = fin && chol_solve(H, C, X, nd);
         } else {
             // AllJones: g^d + (c_d - sum_e H[d][e] g^e) / H[d][d], per direction
@@ -721,12 +774,13 @@ __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it
                     X[d] = make_double2(gd.x, gd.y);
                     continue;
                 }
-                double2 jr = C[d];
-                for (int e = 0; e < nd; ++e) {
-                    const float2 ge = G[e * na + p];
-                    const double2 pr = dmul(hget(H, d, e, nd), make_double2(ge.x, ge.y));
-                    jr.x -= pr.x; jr.y -= pr.y;
-                }
+                double2 jr = C[d];          // with the BF16 Gram C already holds J^H r
+                if (!resid)
+                    for (int e = 0; e < nd; ++e) {
+                        const float2 ge = G[e * na + p];
+                        const double2 pr = dmul(hget(H, d, e, nd), make_double2(ge.x, ge.y));
+                        jr.x -= pr.x; jr.y -= pr.y;
+                    }
                 X[d] = make_double2(gd.x + jr.x / hdd, gd.y + jr.y / hdd);
             }
         }

@@ -1005,7 +1005,7 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
                        0, s, a);
     prof_end(plan, WCAL_K_OTHER, s);
     const size_t us = update_smem(na, NC);
-    if (plan->prob.mode == WCAL_MODE_STATS) {
+    if (di_stats_solve(plan)) {
         const int g1 = grid_resident(plan, reinterpret_cast<const void*>(di_stats_kernel<NC>), TB, 0, plan->nstiles);
         prof_begin(plan, WCAL_K_STATS, s);
         hipLaunchKernelGGL(di_stats_kernel<NC>, dim3(g1), dim3(TB), 0, s, a, (const Tile*)plan->d_stiles,

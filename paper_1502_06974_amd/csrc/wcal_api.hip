@@ -134,7 +134,7 @@ static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
     }
     plan->tile_rows = (int)tile_rows;
     plan->nunits = plan->nttiles = 0;
-    plan->tri = want_tri && plan->canonical && p.algo == WCAL_STEFCAL && p.n_corr == 1 && p.mode == WCAL_MODE_PASS;
+    plan->tri = want_tri && plan->canonical && p.algo == WCAL_STEFCAL && p.n_corr == 1 && !di_stats_solve(plan);
     // tiles: samples per tile S and baselines per tile (a multiple of the 256-lane
     // workgroup) chosen for about tile_rows rows; interval k owns a contiguous tile range
     const int TBL = 256;
@@ -251,6 +251,10 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         return fail(WCAL_EINVAL, "unknown precision");
     if (p.precision != WCAL_PREC_FP32 && p.algo == WCAL_STEFCAL)
         return fail(WCAL_EINVAL, "the BF16 Gram is for CohJones / AllJones");
+    if (p.precision != WCAL_PREC_FP32 && p.mode != WCAL_MODE_PASS)
+        return fail(WCAL_EINVAL, "the BF16 Gram needs PASS mode (its residual column follows the gains)");
+    if (p.precision != WCAL_PREC_FP32 && p.n_dir > 13)
+        return fail(WCAL_ESHAPE, "the BF16 Gram holds at most 13 directions (16 columns: Nd, d, r twice)");
     if (p.max_iter > 100000) return fail(WCAL_ESHAPE, "max_iter > 100000");
     if (p.algo == WCAL_STEFCAL) {
         if (p.n_dir != 1) return fail(WCAL_EINVAL, "StefCal needs n_dir == 1 (use CohJones/AllJones)");
@@ -327,7 +331,7 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         wcal_plan_destroy(plan);
         return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan state");
     }
-    if (p.algo == WCAL_STEFCAL && p.mode == WCAL_MODE_STATS) {
+    if (p.algo == WCAL_STEFCAL && di_stats_solve(plan)) {
         plan->stats_bytes = sizeof(float) * (size_t)p.n_int * p.n_bl * di_nstat(p.n_corr);
         if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
             wcal_plan_destroy(plan);
@@ -388,7 +392,7 @@ const char* wcal_plan_pass_kernel(const wcal_plan* plan) {
     if (!plan) return "";
     const wcal_problem& p = plan->prob;
     if (p.algo != WCAL_STEFCAL) return p.precision == WCAL_PREC_BF16_GRAM ? "dd_gram_dma_kernel" : "dd_gram_blk_kernel";
-    if (p.mode == WCAL_MODE_STATS) return p.n_corr == 1 ? "di_stats_kernel<1>" : "di_stats_kernel<4>";
+    if (di_stats_solve(plan)) return p.n_corr == 1 ? "di_stats_kernel<1>" : "di_stats_kernel<4>";
     if (plan->tri) return "di_tri_pass_kernel";
     return p.n_corr == 1 ? "di_pass_kernel<1>" : "di_pass_kernel<4>";
 }
@@ -433,6 +437,7 @@ static void fill_tables_dd(const wcal_plan* plan, DdArgs& a) {
     a.schedule = plan->prob.schedule;
     a.algo = plan->prob.algo;
     a.tol = plan->prob.tol;
+    a.precision = plan->prob.precision;
 }
 
 int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
@@ -516,7 +521,7 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
     const double saved_tol = p.tol;
     p.max_iter = n_updates;
     p.tol = 0.0;
-    const bool tri_ok = plan->canonical && p.n_corr == 1 && p.mode == WCAL_MODE_PASS;
+    const bool tri_ok = plan->canonical && p.n_corr == 1 && !di_stats_solve(plan);
     const int64_t rows_cand[] = {16384, 32768, 65536, 131072, 262144};
     int64_t best_rows = plan->tile_rows;
     bool best_tri = plan->tri;

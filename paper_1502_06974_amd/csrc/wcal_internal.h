@@ -135,9 +135,15 @@ struct DdArgs {
     const int32_t* ns;
     const int32_t* order;
     int32_t* queue;
-    int32_t n_ant, n_bl, n_int, n_dir, max_iter, schedule, algo;
+    int32_t n_ant, n_bl, n_int, n_dir, max_iter, schedule, algo, precision;
     double tol;
 };
+
+// StefCal runs the statistics solve in WCAL_MODE_STATS unless every interval holds one
+// sample (the statistics of one sample are no smaller than the sample: the PASS solve runs)
+inline bool di_stats_solve(const wcal_plan* plan) {
+    return plan->prob.mode == WCAL_MODE_STATS && plan->max_ns > 1;
+}
 
 // launchers (return a hipError_t)
 hipError_t launch_di_solve(const wcal_plan* plan, const DiArgs& a, hipStream_t s);

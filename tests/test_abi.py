@@ -55,6 +55,7 @@ def _create(n_ant, a1, a2, ns, **kw):
     ([0, 0, 1], [1, 2, 2], [2], {"mode": 5}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"precision": 1}, wcal.EINVAL),         # BF16 Gram with StefCal
     ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_dir": 2, "precision": 7}, wcal.EINVAL),
+    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_dir": 2, "precision": 1, "mode": 1}, wcal.EINVAL),  # BF16 + STATS
 ])
 def test_plan_validation_errors(a1, a2, ns, kw, code):
     rc, h = _create(3, a1, a2, ns, **kw)

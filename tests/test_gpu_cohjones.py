@@ -212,30 +212,30 @@ def test_cohjones_na64_nd10_full_size(mode):
 
 
 # ------------------------------------------------------------------ BF16 Gram
-@pytest.mark.parametrize("mode", MODES)
-def test_bf16_gram_error_against_oracle(mode):
-    """BF16 products with FP32 accumulation in the Gram pass: the converged gains of the
-    64-antenna, 10-direction problem (2 x 8 samples) against the FP64 oracle's, and the
-    FP32 path on the same problem for comparison."""
-    log(f"[bf16 gram] mode={mode}")
+@pytest.mark.parametrize("algo", ["cohjones", "alljones"])
+def test_bf16_gram_error_against_oracle(algo):
+    """BF16 products with FP32 accumulation in the Gram pass, with the FP32 residual column
+    and the residual-form update: the converged gains of the 64-antenna, 10-direction problem
+    (2 x 8 samples) against the FP64 oracle's, beside the FP32 path on the same problem."""
+    log(f"[bf16 gram] algo={algo}")
     P = synth.workload("cohjones_na64", device=DEV, n_time=2, n_chan=8, n_int=1)
     o = glue.solve(P, 0, P.unit_gains()[0].cpu().numpy(), algo="cohjones", tol=1e-10, max_iter=3000)
     go = glue.gains_from_oracle(o["g"], 1, P.n_dir)[:, :, 0]
     errs = {}
     for prec in ("fp32", "bf16"):
-        plan = wcal.plan_for(P, algo="cohjones", tol=1e-6, max_iter=300, mode=mode, precision=prec)
+        plan = wcal.plan_for(P, algo=algo, tol=1e-6, max_iter=500, precision=prec)
         out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
         torch.cuda.synchronize()
-        assert int(out["status"][0]) & oc.CONVERGED
+        assert int(out["status"][0]) & oc.CONVERGED, (prec, int(out["status"][0]))
         g = out["gains"][0, :, :, 0].cpu().numpy()
         errs[prec] = rel(glue.align(g, go, P.n_dir), go)
-    log(f"  gain error vs FP64 oracle: fp32 {errs['fp32']:.2e}, bf16 {errs['bf16']:.2e}")
+        log(f"  {prec}: gain error vs FP64 oracle {errs[prec]:.2e}, updates {int(out['n_iter'][0])}")
     assert errs["fp32"] <= 1e-5
-    assert errs["bf16"] <= 6e-3      # measured 2.1e-3 on MI355X
+    assert errs["bf16"] <= 1e-4
 
 
 def test_bf16_gram_full_size_noise_free_recovery():
-    """Full size (30 x 64 samples): BF16 Gram recovery error of noise-free gains (stated)."""
+    """Full size (30 x 64 samples): recovery of noise-free gains with the BF16 Gram."""
     log("[bf16 gram full]")
     Q = synth.workload("cohjones_na64", device=DEV, n_int=1, noise=False)
     gt = Q.g_true[0, :, :, 0].cpu().numpy()
@@ -246,4 +246,10 @@ def test_bf16_gram_full_size_noise_free_recovery():
         g = out["gains"][0, :, :, 0].cpu().numpy()
         e = rel(glue.align(g, gt, Q.n_dir), gt)
         log(f"  {prec}: recovery error {e:.2e}, iters {int(out['n_iter'][0])}, status {int(out['status'][0])}")
-        assert e <= (1e-5 if prec == "fp32" else 6e-4)   # bf16 measured 1.9e-4 on MI355X
+        assert e <= 1e-5 if prec == "fp32" else 1e-4
+
+
+def test_bf16_gram_needs_pass_mode():
+    P = synth.workload("cohjones_na64", device=DEV, n_time=1, n_chan=4, n_int=1)
+    with pytest.raises(wcal.WcalError):
+        wcal.plan_for(P, algo="cohjones", mode="stats", precision="bf16")
