@@ -168,7 +168,7 @@ def main():
     tuned = None
     if not args.no_autotune:
         # tiling chosen by the plan autotuner on this workload (before the timed region)
-        tuned = plan.autotune(P.data, P.model, P.flags, g0, n_updates=3)
+        tuned = plan.autotune(P.data, P.model, P.flags, g0, n_updates=0)    # whole solves to tol
         log(f"[bench] autotune: {tuned}")
     gains = g0.clone()
     residual = torch.empty_like(P.data)

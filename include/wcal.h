@@ -148,15 +148,16 @@ int64_t wcal_plan_rows(const wcal_plan* plan);
 const char* wcal_plan_pass_kernel(const wcal_plan* plan);
 
 /* Autotuner: pick the plan's tiling from measurements on the caller's data.  For StefCal
- * it times, with HIP events on `stream`, n_updates updates (tol 0, no residual) from
- * `gains` for each target of {16384, 32768, 65536, 131072, 262144} rows per tile and, where
+ * it times, with HIP events on `stream`, n_updates updates (tol 0; or, with n_updates = 0,
+ * the plan's own solve to its tolerance; no residual either way) from `gains` for each
+ * target of {8192, 16384, 32768, 65536, 131072, 262144} rows per tile and, where
  * the baseline table is canonical (scalar, PASS mode), with and without the triangle pass;
  * it keeps the fastest (best of two timed runs after a warm-up run).  `gains` is only read
  * (a scratch copy is iterated).  CohJones / AllJones stream their rows in the blocked Gram
  * pass, which has no tiling to choose; the call returns at once.  Outputs: the chosen
  * rows per tile and 1 if the triangle pass is used (either pointer may be NULL).  The call
  * allocates scratch, synchronises the host and rebuilds the plan's tiles: call it between
- * solves, not under graph capture.  Errors: WCAL_EINVAL (n_updates outside [1, max_iter],
+ * solves, not under graph capture.  Errors: WCAL_EINVAL (n_updates outside [0, max_iter],
  * profiling on), WCAL_ENOMEM, WCAL_EHIP. */
 int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                        const uint8_t* flags, const wcal_c64* gains, int32_t n_updates,

@@ -485,8 +485,8 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
     g_err.clear();
     int rc = check_common(plan, data, model, gains);
     if (rc) return rc;
-    if (n_updates < 1 || n_updates > plan->prob.max_iter)
-        return fail(WCAL_EINVAL, "n_updates must be in [1, max_iter]");
+    if (n_updates < 0 || n_updates > plan->prob.max_iter)
+        return fail(WCAL_EINVAL, "n_updates must be in [0, max_iter]");
     if (plan->prof) return fail(WCAL_EINVAL, "disable profiling before tuning");
     wcal_problem& p = plan->prob;
     auto report = [&]() {
@@ -516,13 +516,17 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
         cleanup();
         return fail(WCAL_ENOMEM, "autotune scratch allocation failed");
     }
-    // every candidate applies exactly n_updates updates (tol 0) from the given gains
+    // every candidate applies exactly n_updates updates (tol 0) from the given gains, or with
+    // n_updates = 0 runs the plan's own solve (to its tolerance, so the tail of the last
+    // intervals still iterating is timed too)
     const int saved_iter = p.max_iter;
     const double saved_tol = p.tol;
-    p.max_iter = n_updates;
-    p.tol = 0.0;
+    if (n_updates > 0) {
+        p.max_iter = n_updates;
+        p.tol = 0.0;
+    }
     const bool tri_ok = plan->canonical && p.n_corr == 1 && !di_stats_solve(plan);
-    const int64_t rows_cand[] = {16384, 32768, 65536, 131072, 262144};
+    const int64_t rows_cand[] = {8192, 16384, 32768, 65536, 131072, 262144};
     int64_t best_rows = plan->tile_rows;
     bool best_tri = plan->tri;
     float best_ms = 1e30f;

@@ -219,8 +219,9 @@ class Plan:
                                 self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
-    def autotune(self, data, model, flags, gains, n_updates: int = 3, stream=None) -> dict:
-        """wcal_plan_autotune: time the candidate tilings on these inputs and keep the fastest."""
+    def autotune(self, data, model, flags, gains, n_updates: int = 0, stream=None) -> dict:
+        """wcal_plan_autotune: time the candidate tilings on these inputs (n_updates updates,
+        or whole solves to the plan's tolerance with 0) and keep the fastest."""
         self._inputs(data, model, flags, gains)
         tr, tri = C.c_int32(0), C.c_int32(0)
         _check(lib().wcal_plan_autotune(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains), n_updates,

@@ -13,7 +13,7 @@ from paper_1502_06974_amd import synth, wcal
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
-CANDIDATES = {16384, 32768, 65536, 131072, 262144}
+CANDIDATES = {8192, 16384, 32768, 65536, 131072, 262144}
 
 
 def log(*a):
@@ -31,17 +31,18 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("n_updates", [3, 0])
 @pytest.mark.parametrize("mode", ["pass", "stats"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_autotune_picks_a_candidate_and_keeps_the_solution(case, mode):
-    log(f"[autotune] case={case} mode={mode}")
+def test_autotune_picks_a_candidate_and_keeps_the_solution(case, mode, n_updates):
+    log(f"[autotune] case={case} mode={mode} n_updates={n_updates}")
     P = CASES[case]()
     ref_plan = wcal.plan_for(P, tol=1e-6, max_iter=200, mode=mode)
     ref = ref_plan.solve(P.data, P.model, P.flags, P.unit_gains())
     plan = wcal.plan_for(P, tol=1e-6, max_iter=200, mode=mode)
     g0 = P.unit_gains()
     before = g0.clone()
-    choice = plan.autotune(P.data, P.model, P.flags, g0, n_updates=3)
+    choice = plan.autotune(P.data, P.model, P.flags, g0, n_updates=n_updates)
     torch.cuda.synchronize()
     log(f"  chose {choice}")
     assert choice["tile_rows"] in CANDIDATES
@@ -65,3 +66,5 @@ def test_autotune_dd_and_bad_arguments():
     plan_q = wcal.plan_for(Q, max_iter=5)
     with pytest.raises(wcal.WcalError):
         plan_q.autotune(Q.data, Q.model, Q.flags, Q.unit_gains(), n_updates=6)
+    with pytest.raises(wcal.WcalError):
+        plan_q.autotune(Q.data, Q.model, Q.flags, Q.unit_gains(), n_updates=-1)
