@@ -686,31 +686,32 @@ __host__ __device__ inline int dd_nlist_slot(int it) { return 3 + 2 * it; }
 // LDS bytes of the gains [nd][na] in dd_ant_kernel, rounded up to 16 for the FP64 blocks
 __host__ __device__ inline size_t ant_g_bytes(int nd, int na) { return ((size_t)nd * na * 8 + 15) / 16 * 16; }
 
-// One update, per antenna: one wavefront forms H_p and c_p of one antenna (lanes over the
-// Nd(Nd+1)/2 + Nd entries, each summed over the antenna's baselines in CSR order, FP64),
-// then its first lane solves (CohJones: Cholesky; AllJones: diagonal, residual form),
-// applies the schedule and writes the candidate gains and its share of the FP64
+// One update, per antenna: one workgroup forms H_p and c_p of one antenna.  Lanes run over
+// the Nd(Nd+1)/2 + Nd entries; the four wavefronts take every fourth of the antenna's
+// baselines (in CSR order, 8 records in flight per lane) and their FP64 sums are folded in
+// wavefront order.  Then one lane solves (CohJones: Cholesky; AllJones: diagonal, residual
+// form), applies the schedule and writes the candidate gains and its share of the FP64
 // relative-change norms.  The interval's decision follows in dd_finish_kernel.
 __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nd = a.n_dir, na = a.n_ant, nbl = a.n_bl;
     const int nx = ntri(nd), per = nx + nd;
     const int nw = DT / WAVE;
-    const int ngrp = (na + nw - 1) / nw;
-    const int k = blockIdx.x / ngrp;
+    const int k = blockIdx.x / na;
     if (!st.active[k]) return;
     const bool resid = a.precision == WCAL_PREC_BF16_GRAM;   // J^H r in C, residual-form update
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int p = (blockIdx.x % ngrp) * nw + w;
+    const int p = blockIdx.x % na;
     float2* G = reinterpret_cast<float2*>(smem);                              // [nd][na]
-    double2* H = reinterpret_cast<double2*>(smem + ant_g_bytes(nd, na)) + w * (per + NDMAX);  // this wavefront's block
+    double2* part = reinterpret_cast<double2*>(smem + ant_g_bytes(nd, na));   // [nw][2 WAVE]
+    double2* H = part + nw * 2 * WAVE;                                         // [nx] then C [nd], X [NDMAX]
     double2* C = H + nx;
     double2* X = C + nd;
     const float2* gk = a.gains + (int64_t)k * nd * na;
     for (int i = threadIdx.x; i < nd * na; i += blockDim.x) G[i] = gk[i];
     __syncthreads();
-    if (p < na) {
+    {
         const int RS = rec_floats(nd);
         const float* recs = st.rec + (int64_t)k * nbl * RS;
         const int t0 = st.ant_ptr[p], t1 = st.ant_ptr[p + 1];
@@ -724,32 +725,58 @@ __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it
                 ci = e - nx;
             }
             double2 acc = make_double2(0.0, 0.0);
-            for (int t = t0; t < t1; ++t) {
-                const int code = st.ant_bl[t];
-                const int b = code >> 1, side = code & 1;
-                const int o = side ? a.ant1[b] : a.ant2[b];     // the other antenna of the row
-                const float* rec = recs + (int64_t)b * RS;
-                const float2 goc = G[ci * na + o];
-                if (e < nx) {
-                    const float2 goe = G[cj * na + o];
-                    const double2 x = make_double2(rec[2 * e], side ? -rec[2 * e + 1] : rec[2 * e + 1]);
-                    const double2 wv = make_double2((double)goc.x * goe.x + (double)goc.y * goe.y,
-                                                    (double)goc.y * goe.x - (double)goc.x * goe.y);
-                    const double2 pr = dmul(wv, x);
-                    acc.x += pr.x; acc.y += pr.y;
-                } else {
-                    // c_p (data form) or, with the BF16 Gram, J^H r (residual form)
-                    const float* z = rec + (resid ? rec_w(nd) : rec_z(nd)) + 2 * ci;
-                    const double2 pr = dmul(make_double2(goc.x, goc.y), make_double2(z[0], side ? -z[1] : z[1]));
+            // the record entry this lane sums: X[e] (block) or, for c_p, Z[ci] (data form) or
+            // W[ci] (J^H r, residual form with the BF16 Gram)
+            const int roff = e < nx ? 2 * e : (resid ? rec_w(nd) : rec_z(nd)) + 2 * ci;
+            constexpr int TU = 8;      // baselines whose records are in flight together
+            for (int t = t0 + w; t < t1; t += TU * nw) {
+                int code[TU], oth[TU];
+                float2 x[TU];
+#pragma unroll
+                for (int u = 0; u < TU; ++u) {
+                    const int tt = t + u * nw;
+                    code[u] = tt < t1 ? st.ant_bl[tt] : 0;
+                    const int b = code[u] >> 1;
+                    oth[u] = (code[u] & 1) ? a.ant1[b] : a.ant2[b];     // the other antenna of the row
+                    x[u] = make_float2(0.f, 0.f);
+                    if (tt < t1) {
+                        const float* rec = recs + (int64_t)b * RS + roff;
+                        x[u] = make_float2(rec[0], rec[1]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < TU; ++u) {
+                    if (t + u * nw >= t1) break;
+                    const int side = code[u] & 1, o = oth[u];
+                    const double2 xv = make_double2(x[u].x, side ? -x[u].y : x[u].y);
+                    const float2 goc = G[ci * na + o];
+                    double2 wv;
+                    if (e < nx) {
+                        const float2 goe = G[cj * na + o];
+                        wv = make_double2((double)goc.x * goe.x + (double)goc.y * goe.y,
+                                          (double)goc.y * goe.x - (double)goc.x * goe.y);   // g^ci conj(g^cj)
+                    } else {
+                        wv = make_double2(goc.x, goc.y);
+                    }
+                    const double2 pr = dmul(wv, xv);
                     acc.x += pr.x; acc.y += pr.y;
                 }
             }
-            if (e < nx) H[e] = acc;
-            else C[ci] = acc;
+            part[w * 2 * WAVE + e] = acc;
         }
     }
     __syncthreads();
-    if (p < na && lane == 0) {
+    for (int e = threadIdx.x; e < per; e += blockDim.x) {
+        double2 v = part[e];
+        for (int w2 = 1; w2 < nw; ++w2) {
+            const double2 u = part[w2 * 2 * WAVE + e];
+            v.x += u.x; v.y += u.y;
+        }
+        if (e < nx) H[e] = v;
+        else C[e - nx] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         bool fin = true;
         for (int i = 0; i < nx; ++i) fin = fin && isfinite(H[i].x) && isfinite(H[i].y);
         for (int i = 0; i < nd; ++i) fin = fin && isfinite(C[i].x) && isfinite(C[i].y);
@@ -1013,8 +1040,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     typedef void (*GramFn)(DdArgs, DdState, const int32_t*, const int32_t*);
     GramFn gram = !bf ? dd_gram_blk_kernel : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
     const int gg = grid_res(plan, reinterpret_cast<const void*>(gram), 0, nblk);
-    const int ngrp = (na + DT / WAVE - 1) / (DT / WAVE);
-    const size_t asm_ = ant_g_bytes(nd, na) + (size_t)(DT / WAVE) * (ntri(nd) + nd + NDMAX) * 16;
+    const size_t asm_ = ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
     hipLaunchKernelGGL(dd_init_kernel, dim3((std::max(a.n_int, nctr) + DT - 1) / DT), dim3(DT), 0, s, a, st, 1, nctr);
     prof_end(plan, WCAL_K_OTHER, s);
@@ -1035,7 +1061,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
             prof_end(plan, WCAL_K_PASS, s);
         }
         prof_begin(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);
-        hipLaunchKernelGGL(dd_ant_kernel, dim3(a.n_int * ngrp), dim3(DT), asm_, s, a, st, it);
+        hipLaunchKernelGGL(dd_ant_kernel, dim3(a.n_int * na), dim3(DT), asm_, s, a, st, it);
         hipLaunchKernelGGL(dd_finish_kernel, dim3(a.n_int), dim3(DT), 0, s, a, st, it);
         prof_end(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);
     }
