@@ -225,7 +225,7 @@ __device__ __forceinline__ float2 row16_sum(float2 v) {
 }
 
 // list: the intervals to process (n_list of them), or null for every interval in LPT order
-__global__ void __launch_bounds__(DT) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8))) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
     __shared__ float2 abuf[GS][GB][16];
     __shared__ uint8_t fbuf[GS][GB];
     __shared__ int s_task;
