@@ -266,8 +266,10 @@ constexpr int TB = 256;   // workgroup size of every tiled kernel
 // sum vec(D) vec(M)^H.  vec index e = 2 i + k for entry (i, k) of a 2x2 matrix.
 template <int NC> struct Ns { static constexpr int v = NC == 1 ? 3 : 48; };
 
-// Rows in flight per lane in the tiled passes.
-template <int NC> struct UT { static constexpr int v = NC == 1 ? 8 : 4; };
+// Rows in flight per lane: in the statistics pass (2x2 at two rows fits 160 VGPRs, three
+// waves per SIMD, and measures faster than four rows at two waves) and in the residual pass.
+template <int NC> struct UT { static constexpr int v = NC == 1 ? 8 : 2; };
+template <int NC> struct UR { static constexpr int v = NC == 1 ? 8 : 4; };
 
 template <int NC>
 __device__ __forceinline__ void stat_add(float (&st)[Ns<NC>::v], const Vis<NC>& v) {
@@ -452,7 +454,7 @@ __device__ __forceinline__ void tile_walk(const DiArgs& a, const Tile& T, Flush 
 // Residual rows of a tile with the gains in LDS; returns this lane's chi^2 share.
 template <int NC>
 __device__ double tile_residual(const DiArgs& a, const Tile& T, const float2* G) {
-    constexpr int U = UT<NC>::v;
+    constexpr int U = UR<NC>::v;
     const int BS = blockDim.x;
     const int R = (T.b1 - T.b0 + BS - 1) / BS;
     const int S = T.s1 - T.s0;
