@@ -8,6 +8,7 @@ compound row index [pqs] of Sect. 2.3:
   scalar : d [R], m [R], gains g [Na]
   2x2    : D [R, 2, 2], M [R, 2, 2], gains G [Na, 2, 2]        (Sect. 4)
   DD     : d [R], m [R, Nd], gains g [Nd, Na]                  (Sect. 2.5)
+  2x2 DD : D [R, 2, 2], M [R, Nd, 2, 2], gains G [Nd, Na, 2, 2] (Sect. 4.4)
 flags [R] bool: a flagged row is weight 0 (Sect. 2.4), removed from every sum
 by selection, so non-finite values under a flag have no effect.
 
@@ -268,6 +269,99 @@ def residual_dd(d, m, p, q, flags, g):
     return r, float(np.sum(np.abs(r[k]) ** 2))
 
 
+# ------------------------------------------------------------------ polarized DD
+def accumulate_dd_2x2(D, M, p, q, flags, G):
+    """Polarized direction-dependent blocks (Sect. 4.4): with Y^d_pq = M^d_pq G^{dH}_q
+    stacked over directions into Ys_pq [2Nd, 2] (row 2d + k = row k of Y^d), the
+    operator-diagonal block of Eq. JHJ:DD:pol for antenna p acts as G_p -> G_p H_p with
+        H_p = sum Ys Ys^H           [2Nd, 2Nd], block (c, e) = sum Y^c Y^{eH},
+    and the top half of J^H D (Eq. JHR:DD:pol with D in place of R) is
+        N_p = sum D Ys^H            [2, 2Nd],   block e = sum D Y^{eH}
+    (least-squares order of the update, as for the 2x2 DI case).  J^H r uses
+    R = D - sum_d G^d_p M^d G^{dH}_q.  The folded row qp has Y^d_qp = M^{dH} G^{dH}_p
+    and D_qp = D^H.  D [R, 2, 2], M [R, Nd, 2, 2], G [Nd, Na, 2, 2]."""
+    nd, na = G.shape[:2]
+    k = _keep(flags, D.shape[0])
+    D, M, p, q = D[k], M[k], p[k], q[k]
+    Gp = np.swapaxes(G[:, p], 0, 1)             # [R, Nd, 2, 2]
+    Gq = np.swapaxes(G[:, q], 0, 1)
+    Y_pq = (M @ _H(Gq)).reshape(-1, 2 * nd, 2)
+    Y_qp = (_H(M) @ _H(Gp)).reshape(-1, 2 * nd, 2)
+    R = D - np.sum(Gp @ M @ _H(Gq), axis=1)
+    Hm = np.zeros((na, 2 * nd, 2 * nd), dtype=np.complex128)
+    N = np.zeros((na, 2, 2 * nd), dtype=np.complex128)
+    jhr = np.zeros((na, 2, 2 * nd), dtype=np.complex128)
+    _scatter(Hm, p, Y_pq @ _H(Y_pq))
+    _scatter(Hm, q, Y_qp @ _H(Y_qp))
+    _scatter(N, p, D @ _H(Y_pq))
+    _scatter(N, q, _H(D) @ _H(Y_qp))
+    _scatter(jhr, p, R @ _H(Y_pq))
+    _scatter(jhr, q, _H(R) @ _H(Y_qp))
+    count = np.bincount(p, minlength=na) + np.bincount(q, minlength=na)
+    return dict(H=Hm, N=N, jhr=jhr, count=count)
+
+
+def _rows_to_dirs(X, nd):
+    """[2, 2Nd] row block -> [Nd, 2, 2] per-direction 2x2 matrices."""
+    return np.swapaxes(X.reshape(2, nd, 2), 0, 1)
+
+
+def gn_cohjones_2x2(acc, G, eps=EPS_PIVOT, form="data"):
+    """Polarized CohJones GN value per antenna (Sect. 4.4, separable by antenna only):
+    the stacked gains [G^0 .. G^{Nd-1}] (2 x 2Nd) solve G H_p = N_p, i.e. each row x of
+    the gains solves H_p x^H = (row of N_p)^H, by Cholesky.  form="residual" gives
+    G + (J^H r) H_p^-1 (Eq. ghat:approx).  Singular antennas keep their gains."""
+    nd, na = G.shape[:2]
+    Gh = G.copy()
+    sing = np.zeros(na, dtype=bool)
+    for a in range(na):
+        rhs = acc["N"][a] if form == "data" else acc["jhr"][a]
+        rows = []
+        for i in range(2):
+            x = cholesky_solve(acc["H"][a], np.conj(rhs[i]), eps)
+            if x is None:
+                break
+            rows.append(np.conj(x))
+        if len(rows) < 2:
+            sing[a] = True
+            continue
+        step = _rows_to_dirs(np.stack(rows), nd)
+        Gh[:, a] = step if form == "data" else G[:, a] + step
+    return Gh, sing
+
+
+def gn_alljones_2x2(acc, G, eps=EPS_PIVOT):
+    """Polarized AllJones GN value (Eq. update:DD:diag:pol, least-squares order; residual
+    form): G^d_p + (sum R Y^{dH}) (sum Y^d Y^{dH})^-1 per antenna and direction, the
+    2x2 inverse by the adjugate.  A singular 2x2 block keeps its gain."""
+    nd, na = G.shape[:2]
+    Gh = G.copy()
+    sing = np.zeros((nd, na), dtype=bool)
+    for a in range(na):
+        J = _rows_to_dirs(acc["jhr"][a], nd)
+        for d in range(nd):
+            Z = acc["H"][a, 2 * d:2 * d + 2, 2 * d:2 * d + 2]
+            z00, z11 = Z[0, 0].real, Z[1, 1].real
+            det = (Z[0, 0] * Z[1, 1] - Z[0, 1] * Z[1, 0]).real
+            if not (z00 > 0) or not (det > eps * z00 * z11):
+                sing[d, a] = True
+                continue
+            Zinv = np.array([[Z[1, 1], -Z[0, 1]], [-Z[1, 0], Z[0, 0]]]) / det
+            Gh[d, a] = G[d, a] + J[d] @ Zinv
+    return Gh, sing
+
+
+def residual_dd_2x2(D, M, p, q, flags, G):
+    """R = D - sum_d G^d_p M^d G^{dH}_q (the polarized DD measurement equation of
+    Sect. 4.4); flagged rows 0; chi^2 = sum ||R||_F^2 over unflagged rows."""
+    k = _keep(flags, D.shape[0])
+    R = np.zeros_like(D, dtype=np.complex128)
+    Gp = np.swapaxes(G[:, p[k]], 0, 1)
+    Gq = np.swapaxes(G[:, q[k]], 0, 1)
+    R[k] = D[k] - np.sum(Gp @ M[k] @ _H(Gq), axis=1)
+    return R, float(np.sum(np.abs(R[k]) ** 2))
+
+
 # ------------------------------------------------------------------ iteration driver
 def _solve(accumulate, gn, residual, finite, sing_to_ant, d, m, p, q, flags, g0,
            tol, max_iter, schedule):
@@ -334,6 +428,24 @@ def alljones(d, m, p, q, flags, g0, tol=1e-6, max_iter=200, schedule=AVG_FIRST):
     fin = lambda a: np.all(np.isfinite(a["H"])) and np.all(np.isfinite(a["jhr"]))
     return _solve(accumulate_dd, gn_alljones, residual_dd, fin, None,
                   d, m, p, q, flags, g0, tol, max_iter, schedule)
+
+
+def cohjones_2x2(D, M, p, q, flags, G0, tol=1e-6, max_iter=100, schedule=AVG_FIRST,
+                 form="data"):
+    """Polarized CohJones: per-antenna 2Nd x 2Nd blocks (the 4Nd x 4Nd operator block of
+    Eq. JHJ:DD:pol acts on both rows of the gains alike) inverted exactly."""
+    fin = lambda a: np.all(np.isfinite(a["H"])) and np.all(np.isfinite(a["N"]))
+    gn = lambda acc, g: gn_cohjones_2x2(acc, g, form=form)
+    return _solve(accumulate_dd_2x2, gn, residual_dd_2x2, fin, None,
+                  D, M, p, q, flags, G0, tol, max_iter, schedule)
+
+
+def alljones_2x2(D, M, p, q, flags, G0, tol=1e-6, max_iter=200, schedule=AVG_FIRST):
+    """Polarized AllJones: separable by antenna and direction, residual form
+    (Eq. update:DD:diag:pol)."""
+    fin = lambda a: np.all(np.isfinite(a["H"])) and np.all(np.isfinite(a["jhr"]))
+    return _solve(accumulate_dd_2x2, gn_alljones_2x2, residual_dd_2x2, fin, None,
+                  D, M, p, q, flags, G0, tol, max_iter, schedule)
 
 
 # ------------------------------------------------------------------ gauge

@@ -48,6 +48,14 @@ def model_2x2(gflat, M, p, q, na):
     return vec(V).reshape(-1)
 
 
+def model_dd_2x2(gflat, M, p, q, nd, na):
+    """vec(sum_d G^d_p M^d_pq G^{dH}_q) for stored rows, stacked (polarized DD, Sect. 4.4);
+    gflat = [vec G^d_a] antenna major, direction minor (index (a * nd + d) * 4 + e)."""
+    G = unvec(gflat.reshape(na, nd, 4))                  # [na, nd, 2, 2]
+    V = np.sum(G[p] @ M @ np.conj(np.swapaxes(G[q], -1, -2)), axis=1)
+    return vec(V).reshape(-1)
+
+
 # ------------------------------------------------------------------ Jacobians
 def wirtinger_jacobian(f, z, h=0.05):
     """(J_k, J_k*) = (dv/dz, dv/dconj z) at z by real-coordinate central differences."""

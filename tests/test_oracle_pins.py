@@ -271,6 +271,57 @@ def test_p2_p4_pol_blocks():
         assert np.allclose(JHD[4 * a:4 * a + 4], oj.vec(acc["N"][a]), atol=1e-12)
 
 
+def _pol_dd(na, nd, ns, sigma, lead=0.3):
+    p, q = np.triu_indices(na, 1)
+    p, q = np.tile(p, ns), np.tile(q, ns)
+    G = np.eye(2) + lead * cn(nd, na, 2, 2)
+    M = cn(p.size, nd, 2, 2)
+    Gp, Gq = np.swapaxes(G[:, p], 0, 1), np.swapaxes(G[:, q], 0, 1)
+    D = np.sum(Gp @ M @ np.conj(np.swapaxes(Gq, -1, -2)), axis=1) + sigma * cn(p.size, 2, 2)
+    return D, M, p, q, G
+
+
+def _unit_pol(nd, na):
+    return np.tile(np.eye(2, dtype=complex), (nd, na, 1, 1))
+
+
+def test_p2_p4_pol_dd_blocks():
+    """Eq. JHJ:DD:pol: in antenna-major order the top-left quadrant of J^H J is
+    block-diagonal over antennas, and antenna a's 4Nd x 4Nd block has 4x4 operator blocks
+    (c, e) = R_{sum Y^e Y^{cH}}, the right-multiply operator (Eq. RA4x4) of block (e, c)
+    of the oracle's H_a; J^H D and J^H r (Eq. JHR:DD:pol) hold vec(sum D Y^{cH}) and
+    vec(sum R Y^{cH}).  J comes from numerical Wirtinger derivatives of the model."""
+    na, nd, ns = 4, 2, 2
+    p, q = np.triu_indices(na, 1)
+    p, q = np.tile(p, ns), np.tile(q, ns)
+    G, M, D = cn(nd, na, 2, 2), cn(p.size, nd, 2, 2), cn(p.size, 2, 2)
+    z = oj.vec(np.swapaxes(G, 0, 1)).reshape(-1)
+    f = lambda zz: oj.model_dd_2x2(zz, M, p, q, nd, na)
+    J = oj.full_jacobian(*oj.wirtinger_jacobian(f, z))
+    JHJ = J.conj().T @ J
+    acc = oc.accumulate_dd_2x2(D, M, p, q, None, G)
+    n = 4 * nd
+    for a in range(na):
+        for b in range(na):
+            blk = JHJ[a * n:(a + 1) * n, b * n:(b + 1) * n]
+            if a != b:
+                assert np.abs(blk).max() < 1e-12
+                continue
+            for c in range(nd):
+                for e in range(nd):
+                    want = oj.RA4(acc["H"][a][2 * e:2 * e + 2, 2 * c:2 * c + 2])
+                    assert np.allclose(blk[4 * c:4 * c + 4, 4 * e:4 * e + 4], want, atol=1e-12)
+    Dv = oj.vec(D).reshape(-1)
+    r = Dv - f(z)
+    for vecs, key in ((Dv, "N"), (r, "jhr")):
+        JH = J.conj().T @ np.concatenate([vecs, np.conj(vecs)])
+        for a in range(na):
+            for c in range(nd):
+                got = JH[(a * nd + c) * 4:(a * nd + c) * 4 + 4]
+                assert np.allclose(got, oj.vec(acc[key][a][:, 2 * c:2 * c + 2]), atol=1e-12)
+    assert np.array_equal(acc["count"], np.bincount(p, minlength=na) + np.bincount(q, minlength=na))
+
+
 # ------------------------------------------------------------------ P3 conjugate symmetry
 def test_p3_conjugate_symmetry():
     """Eq. JHR:DI1: bottom half of J^H r is conj(top); the GN step has conj symmetry."""
@@ -362,6 +413,34 @@ def test_p6_cohjones_and_pol_equal_full_gn():
     assert oc.rel_err(oc.align_phase(st["g"], Gn), Gn) < 1e-9
 
 
+def test_p5_noise_free_pol_dd():
+    """Noise-free polarized DD data: CohJones and AllJones reach the true gains up to one
+    phase per direction (generic models leave no other gauge)."""
+    na, nd = 7, 2
+    D, M, p, q, Gt = _pol_dd(na, nd, 4, 0.0)
+    for fn in (oc.cohjones_2x2, oc.alljones_2x2):
+        out = fn(D, M, p, q, None, _unit_pol(nd, na), tol=1e-14, max_iter=3000)
+        assert out["status"] & oc.CONVERGED, (fn.__name__, out["status"])
+        assert oc.rel_err(oc.align_phase_per_direction(out["g"], Gt), Gt) < 1e-10, fn.__name__
+        assert out["chi2"] < 1e-20
+
+
+def test_p6_pol_dd_equals_full_gn():
+    """Both polarized DD updates have the least-squares minimum as fixed point: CohJones
+    meets Eq. ghat:precise and AllJones is in residual form.  Full complex GN with the
+    numerical Jacobian reaches the same gains."""
+    na, nd = 5, 2
+    D, M, p, q, _ = _pol_dd(na, nd, 3, 0.05)
+    f = lambda z: oj.model_dd_2x2(z, M, p, q, nd, na)
+    z0 = oj.vec(np.swapaxes(_unit_pol(nd, na), 0, 1)).reshape(-1)
+    z = oj.gn_full(f, oj.vec(D).reshape(-1), z0, n_iter=100)
+    Gn = np.swapaxes(oj.unvec(z.reshape(na, nd, 4)), 0, 1)
+    for fn in (oc.cohjones_2x2, oc.alljones_2x2):
+        out = fn(D, M, p, q, None, _unit_pol(nd, na), tol=1e-14, max_iter=5000)
+        assert out["status"] & oc.CONVERGED, fn.__name__
+        assert oc.rel_err(oc.align_phase_per_direction(out["g"], Gn), Gn) < 1e-9, fn.__name__
+
+
 # ------------------------------------------------------------------ P8 chi^2 statistics
 def test_p8_chi2():
     P = synth.scalar_di(27, [240], sigma=0.01, dtype=torch.complex128, seed=6)
@@ -427,6 +506,68 @@ def test_p9_orientation_swap():
     a = oc.stefcal_2x2(D, M, p, q, None, G0, tol=0, max_iter=7)
     b = oc.stefcal_2x2(D2, M2, p2, q2, None, G0, tol=0, max_iter=7)
     assert np.allclose(a["g"], b["g"], rtol=1e-12)
+
+
+def test_p9_pol_dd_nd1_is_pol_stefcal():
+    """One direction reduces polarized CohJones and AllJones to polarized StefCal
+    (same iterates: H_p = Z_p, N_p = sum D Y^H, and the residual form equals the data form
+    in exact arithmetic)."""
+    na = 6
+    D, M, p, q, _ = _pol_dd(na, 1, 3, 0.1)
+    G0 = np.tile(np.eye(2, dtype=complex), (na, 1, 1))
+    a = oc.stefcal_2x2(D, M[:, 0], p, q, None, G0, tol=0, max_iter=10)
+    for fn in (oc.cohjones_2x2, oc.alljones_2x2):
+        b = fn(D, M, p, q, None, G0[None], tol=0, max_iter=10)
+        assert np.allclose(a["g"], b["g"][0], rtol=1e-11, atol=1e-12), fn.__name__
+
+
+def test_p9_diagonal_pol_dd_is_two_scalar_dd():
+    """Diagonal gains and diagonal models decouple polarized DD into two scalar DD
+    problems (xx and yy): polarized CohJones / AllJones equal scalar CohJones / AllJones
+    on each, update by update."""
+    na, nd, ns = 5, 2, 3
+    p, q = np.triu_indices(na, 1)
+    p, q = np.tile(p, ns), np.tile(q, ns)
+    mx, my = cn(p.size, nd), cn(p.size, nd)
+    gx, gy = cn(nd, na) + 2, cn(nd, na) + 2
+    dx = np.sum(gx[:, p].T * mx * np.conj(gx[:, q]).T, axis=1) + 0.1 * cn(p.size)
+    dy = np.sum(gy[:, p].T * my * np.conj(gy[:, q]).T, axis=1) + 0.1 * cn(p.size)
+    M = np.zeros((p.size, nd, 2, 2), complex)
+    M[:, :, 0, 0], M[:, :, 1, 1] = mx, my
+    D = np.zeros((p.size, 2, 2), complex)
+    D[:, 0, 0], D[:, 1, 1] = dx, dy
+    for pol, sc in ((oc.cohjones_2x2, oc.cohjones), (oc.alljones_2x2, oc.alljones)):
+        o = pol(D, M, p, q, None, _unit_pol(nd, na), tol=0, max_iter=8)
+        a = sc(dx, mx, p, q, None, np.ones((nd, na), complex), tol=0, max_iter=8)
+        b = sc(dy, my, p, q, None, np.ones((nd, na), complex), tol=0, max_iter=8)
+        assert np.allclose(o["g"][:, :, 0, 0], a["g"], rtol=1e-11), pol.__name__
+        assert np.allclose(o["g"][:, :, 1, 1], b["g"], rtol=1e-11), pol.__name__
+        assert np.allclose(o["g"][:, :, 0, 1], 0) and np.allclose(o["g"][:, :, 1, 0], 0)
+
+
+def test_p9_pol_dd_orientation_swap_and_flags():
+    """A row stored as (q, p) with D^H and M^{dH} is the same equation; flagged rows with
+    garbage equal deleted rows (P13), for both polarized DD updates."""
+    na, nd = 6, 2
+    D, M, p, q, _ = _pol_dd(na, nd, 2, 0.1)
+    sw = rng.random(p.size) < 0.5
+    H = lambda X: np.conj(np.swapaxes(X, -1, -2))
+    D2 = np.where(sw[:, None, None], H(D), D)
+    M2 = np.where(sw[:, None, None, None], H(M), M)
+    p2, q2 = np.where(sw, q, p), np.where(sw, p, q)
+    fl = rng.random(p.size) < 0.2
+    Df, Mf = D.copy(), M.copy()
+    Df[fl] = np.nan
+    Mf[fl] = 1e30
+    for fn in (oc.cohjones_2x2, oc.alljones_2x2):
+        a = fn(D, M, p, q, None, _unit_pol(nd, na), tol=0, max_iter=7)
+        b = fn(D2, M2, p2, q2, None, _unit_pol(nd, na), tol=0, max_iter=7)
+        assert np.allclose(a["g"], b["g"], rtol=1e-11), fn.__name__
+        c = fn(Df, Mf, p, q, fl, _unit_pol(nd, na), tol=0, max_iter=7)
+        k = ~fl
+        e = fn(D[k], M[k], p[k], q[k], None, _unit_pol(nd, na), tol=0, max_iter=7)
+        assert np.array_equal(c["g"], e["g"]), fn.__name__
+        assert np.all(c["residual"][fl] == 0) and c["chi2"] == e["chi2"]
 
 
 # ------------------------------------------------------------------ P11 GN alone oscillates
