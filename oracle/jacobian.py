@@ -192,4 +192,6 @@ def lm_full(f, d, z0, n_iter=200, lam0=1.0, K=10.0, tol=1e-14):
                 break
         else:
             lam *= K
+            if lam > 1e30:      # steps no longer change z: no further progress possible
+                break
     return z

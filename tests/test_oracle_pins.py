@@ -6,6 +6,7 @@ of the measurement equation, optima from full Gauss-Newton / LM, and the
 rest from closed forms, invariants, special cases and brute force.
 """
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -17,6 +18,15 @@ from paper_1502_06974_amd import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 rng = np.random.default_rng(1502)
+
+
+@pytest.fixture(autouse=True)
+def _per_test_rng(request):
+    """Seed the shared generator from the test's name, so that each pin sees the same
+    inputs whatever tests run before it."""
+    global rng
+    rng = np.random.default_rng(zlib.crc32(request.node.name.encode()))
+    yield
 
 
 def cn(*shape):
@@ -383,7 +393,9 @@ def test_p6_p7_stefcal_equals_full_gn_and_lm():
     gn = oj.gn_full(f, d, np.ones(6, complex))
     lm = oj.lm_full(f, d, np.ones(6, complex))
     assert oc.rel_err(oc.align_phase(st["g"], gn), gn) < 1e-10
-    assert oc.rel_err(oc.align_phase(lm, gn), gn) < 1e-10
+    # LM keeps a step only when chi^2 drops; chi^2 is flat to second order at the minimum,
+    # so in double precision that test places the minimiser to ~sqrt(eps) = 1.5e-8
+    assert oc.rel_err(oc.align_phase(lm, gn), gn) < 1e-8
     Jk, _ = oj.wirtinger_jacobian(folded(f), st["g"])
     r = d - f(st["g"])
     grad = Jk.conj().T @ np.concatenate([r, np.conj(r)])
