@@ -10,58 +10,86 @@ SCHED = {0: oc.AVG_FIRST, 1: oc.GN_FIRST, 2: oc.GN_ONLY, "avg_first": oc.AVG_FIR
          "gn_first": oc.GN_FIRST, "gn_only": oc.GN_ONLY}
 
 
-def split(iv, n_corr, n_dir):
+def _dd(n_dir, algo):
+    return n_dir > 1 or algo in ("cohjones", "alljones")
+
+
+def split(iv, n_corr, n_dir, algo=None):
     """Interval dict -> (d, m) in the oracle's per-kind shapes."""
-    if n_dir == 1 and n_corr == 1:
-        return iv["d"][:, 0], iv["m"][:, 0, 0]
     if n_corr == 4:
-        return iv["d"].reshape(-1, 2, 2), iv["m"][:, 0].reshape(-1, 2, 2)
+        D = iv["d"].reshape(-1, 2, 2)
+        if _dd(n_dir, algo):
+            return D, iv["m"].reshape(-1, n_dir, 2, 2)
+        return D, iv["m"][:, 0].reshape(-1, 2, 2)
+    if n_dir == 1 and not _dd(n_dir, algo):
+        return iv["d"][:, 0], iv["m"][:, 0, 0]
     return iv["d"][:, 0], iv["m"][:, :, 0]
 
 
-def gains_to_oracle(g, n_corr, n_dir):
+def gains_to_oracle(g, n_corr, n_dir, algo=None):
     """[n_dir][n_ant][n_corr] complex -> oracle layout."""
     g = np.asarray(g, dtype=np.complex128)
-    if n_dir == 1 and n_corr == 1:
-        return g[0, :, 0].copy()
     if n_corr == 4:
+        if _dd(n_dir, algo):
+            return g.reshape(n_dir, -1, 2, 2).copy()
         return g[0].reshape(-1, 2, 2).copy()
+    if n_dir == 1 and not _dd(n_dir, algo):
+        return g[0, :, 0].copy()
     return g[:, :, 0].copy()
 
 
-def gains_from_oracle(g, n_corr, n_dir):
-    if n_dir == 1 and n_corr == 1:
-        return g[None, :, None]
+def gains_from_oracle(g, n_corr, n_dir, algo=None):
     if n_corr == 4:
+        if _dd(n_dir, algo):
+            return g.reshape(n_dir, -1, 4)
         return g.reshape(1, -1, 4)
+    if n_dir == 1 and not _dd(n_dir, algo):
+        return g[None, :, None]
     return g[:, :, None]
 
 
 def solve(problem, k, g0, algo="stefcal", tol=1e-6, max_iter=100, schedule="avg_first", flags=True):
     iv = problem.interval(k)
-    d, m = split(iv, problem.n_corr, problem.n_dir)
+    nc, nd = problem.n_corr, problem.n_dir
+    d, m = split(iv, nc, nd, algo)
     fl = iv["flags"] if flags else None
-    g0o = gains_to_oracle(g0, problem.n_corr, problem.n_dir)
+    g0o = gains_to_oracle(g0, nc, nd, algo)
     s = SCHED[schedule]
     if algo == "stefcal":
-        fn = oc.stefcal_scalar if problem.n_corr == 1 else oc.stefcal_2x2
+        fn = oc.stefcal_scalar if nc == 1 else oc.stefcal_2x2
     elif algo == "cohjones":
-        fn = oc.cohjones
+        fn = oc.cohjones if nc == 1 else oc.cohjones_2x2
     else:
-        fn = oc.alljones
+        fn = oc.alljones if nc == 1 else oc.alljones_2x2
     return fn(d, m, iv["p"], iv["q"], fl, g0o, tol=tol, max_iter=max_iter, schedule=s)
 
 
-def accumulate(problem, k, g, flags=True):
+def accumulate(problem, k, g, flags=True, algo=None):
     iv = problem.interval(k)
-    d, m = split(iv, problem.n_corr, problem.n_dir)
+    nc, nd = problem.n_corr, problem.n_dir
+    d, m = split(iv, nc, nd, algo)
     fl = iv["flags"] if flags else None
-    go = gains_to_oracle(g, problem.n_corr, problem.n_dir)
-    if problem.n_dir > 1:
-        return oc.accumulate_dd(d, m, iv["p"], iv["q"], fl, go)
-    if problem.n_corr == 1:
+    go = gains_to_oracle(g, nc, nd, algo)
+    if _dd(nd, algo):
+        fn = oc.accumulate_dd if nc == 1 else oc.accumulate_dd_2x2
+        return fn(d, m, iv["p"], iv["q"], fl, go)
+    if nc == 1:
         return oc.accumulate_scalar(d, m, iv["p"], iv["q"], fl, go)
     return oc.accumulate_2x2(d, m, iv["p"], iv["q"], fl, go)
+
+
+def residual(problem, k, g, flags=True, algo=None):
+    """R and chi^2 of interval k at gains g ([n_dir][n_ant][n_corr])."""
+    iv = problem.interval(k)
+    nc, nd = problem.n_corr, problem.n_dir
+    d, m = split(iv, nc, nd, algo)
+    fl = iv["flags"] if flags else None
+    go = gains_to_oracle(g, nc, nd, algo)
+    if _dd(nd, algo):
+        fn = oc.residual_dd if nc == 1 else oc.residual_dd_2x2
+    else:
+        fn = oc.residual_scalar if nc == 1 else oc.residual_2x2
+    return fn(d, m, iv["p"], iv["q"], fl, go)
 
 
 def align(g, ref, n_dir):

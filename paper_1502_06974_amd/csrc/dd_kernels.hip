@@ -23,20 +23,14 @@
 // repeated before every update.  A tiled residual pass ends the solve.
 #include <cstdlib>
 
-#include "di_common.h"
+#include "dd_common.h"
 
 using namespace wcal_dev;
 
 namespace {
 
-constexpr int DT = 256;          // workgroup size
 constexpr int NDMAX = 14;        // Nd + 2 augmented columns fit one 16-wide MFMA tile
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-__host__ __device__ inline int ntri(int nd) { return nd * (nd + 1) / 2; }
-// packed index of (i, j), i <= j < nd, row-major upper triangle
-__host__ __device__ inline int tri(int i, int j, int nd) { return i * nd - i * (i - 1) / 2 + (j - i); }
 // floats per baseline record: X (upper, complex), Z, W (complex), sum |d|^2, count
 __host__ __device__ inline int rec_floats(int nd) {
     const int n = 2 * ntri(nd) + 4 * nd + 2;
@@ -46,28 +40,6 @@ __host__ __device__ inline int rec_z(int nd) { return 2 * ntri(nd); }
 __host__ __device__ inline int rec_w(int nd) { return 2 * ntri(nd) + 2 * nd; }
 __host__ __device__ inline int rec_d2(int nd) { return 2 * ntri(nd) + 4 * nd; }
 __host__ __device__ inline int rec_cnt(int nd) { return 2 * ntri(nd) + 4 * nd + 1; }
-
-struct DdState {
-    float* rec;          // [n_int][n_bl][rec_floats]
-    double* chi_bl;      // [n_int][n_bl] chi^2 per baseline (accumulate)
-    float2* gn;          // [n_int][nd][n_ant] candidate gains of the current update
-    double* ant_d;       // [n_int][n_ant] |g_new - g|^2 per antenna
-    double* ant_n;       // [n_int][n_ant] |g_new|^2 per antenna
-    int32_t* ant_f;      // [n_int][n_ant] 1: non-finite block, 2: singular block
-    int32_t* alist;      // [2][n_int] intervals still iterating, by update parity
-    const int32_t* ant_ptr;  // [n_ant + 1] CSR of (baseline, side) per antenna
-    const int32_t* ant_bl;   // [2 n_bl]: 2 b + side (side 0: antenna is ant1, 1: ant2)
-    int32_t* active;     // [n_int]
-    int32_t* ctr;        // work counters
-    const Tile* tiles;
-    const int32_t* tile_off;
-    int32_t ntiles;
-    double* chi_part;    // [ntiles]
-};
-
-__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
 
 // ------------------------------------------------------------------ Gram pass
 // WITH_R: add the residual column (fixed gains), write R and chi^2 per baseline.
@@ -678,10 +650,6 @@ __device__ DdSmem dd_smem(unsigned char* smem, int nd, int na) {
     return s;
 }
 
-// counters: [0] one-off Gram pops, [2 + 2 it] Gram pops of update it, [3 + 2 it] intervals
-// listed for update it (it >= 1)
-__host__ __device__ inline int dd_pop_slot(int it) { return 2 + 2 * it; }
-__host__ __device__ inline int dd_nlist_slot(int it) { return 3 + 2 * it; }
 
 // LDS bytes of the gains [nd][na] in dd_ant_kernel, rounded up to 16 for the FP64 blocks
 __host__ __device__ inline size_t ant_g_bytes(int nd, int na) { return ((size_t)nd * na * 8 + 15) / 16 * 16; }
@@ -832,55 +800,6 @@ __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it
     }
 }
 
-// The interval's decision after dd_ant_kernel: norms summed over antennas in a fixed
-// order; a non-finite block stops the interval before this update (gains kept); otherwise
-// the candidate becomes the gains, singular antennas are reported, and the relative change
-// and the iteration cap decide whether it keeps iterating.
-__global__ void __launch_bounds__(DT) dd_finish_kernel(DdArgs a, DdState st, int it) {
-    __shared__ double red[DT / WAVE];
-    __shared__ int s_f;
-    const int k = blockIdx.x;
-    if (!st.active[k]) return;
-    const int nd = a.n_dir, na = a.n_ant;
-    if (threadIdx.x == 0) s_f = 0;
-    __syncthreads();
-    double dsum = 0.0, nsum = 0.0;
-    int f = 0;
-    for (int p = threadIdx.x; p < na; p += blockDim.x) {
-        dsum += st.ant_d[(int64_t)k * na + p];
-        nsum += st.ant_n[(int64_t)k * na + p];
-        f |= st.ant_f[(int64_t)k * na + p];
-    }
-    if (f) atomicOr(&s_f, f);
-    dsum = block_sum(dsum, red);
-    nsum = block_sum(nsum, red);
-    const int flags = s_f;
-    uint32_t status = 0;
-    bool finished = false;
-    if (flags & 1) {
-        status |= WCAL_NONFINITE;
-        finished = true;
-    } else {
-        if (flags & 2) status |= WCAL_SINGULAR_ANT;
-        const float2* gn = st.gn + (int64_t)k * nd * na;
-        float2* gk = a.gains + (int64_t)k * nd * na;
-        for (int i = threadIdx.x; i < nd * na; i += blockDim.x) gk[i] = gn[i];
-        const double num = sqrt(dsum), den = sqrt(nsum);
-        const double rel = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : num / den;
-        if (rel < a.tol) { status |= WCAL_CONVERGED; finished = true; }
-    }
-    if (!finished && it + 1 >= a.max_iter) {
-        status |= WCAL_MAXITER;
-        finished = true;
-    }
-    if (threadIdx.x == 0) {
-        a.status[k] |= status;
-        if (!(status & WCAL_NONFINITE)) a.n_iter[k] = it + 1;
-        if (finished) st.active[k] = 0;
-        else st.alist[((it + 1) & 1) * a.n_int + atomicAdd(&st.ctr[dd_nlist_slot(it + 1)], 1)] = k;
-    }
-}
-
 // Blocks at fixed gains for the accumulate entry point.
 __global__ void __launch_bounds__(DT) dd_reduce_kernel(DdArgs a, DdState st) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -912,16 +831,6 @@ __global__ void __launch_bounds__(DT) dd_reduce_kernel(DdArgs a, DdState st) {
         for (int b = 0; b < a.n_bl; ++b) c += st.chi_bl[(int64_t)k * a.n_bl + b];
         a.chi2[k] = c;
     }
-}
-
-__global__ void __launch_bounds__(DT) dd_init_kernel(DdArgs a, DdState st, int init_state, int nctr) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (init_state && i < a.n_int) {
-        a.status[i] = 0;
-        a.n_iter[i] = 0;
-        st.active[i] = 1;
-    }
-    if (i < nctr) st.ctr[i] = 0;
 }
 
 // Residual rows of one tile: lane <-> baseline, weights g^c_p conj(g^c_q) per round.
@@ -968,53 +877,9 @@ __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int 
     }
 }
 
-__global__ void __launch_bounds__(DT) dd_chi2_kernel(DdArgs a, DdState st) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n_int || !a.chi2) return;
-    double c = 0.0;
-    for (int t = st.tile_off[k]; t < st.tile_off[k + 1]; ++t) c += st.chi_part[t];
-    a.chi2[k] = c;
-}
-
-int grid_res(const wcal_plan* plan, const void* fn, size_t smem, int64_t work) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, DT, smem) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    int64_t g = (int64_t)per_cu * plan->n_cu;
-    if (g > work) g = work;
-    return (int)(g < 1 ? 1 : g);
-}
-
-DdState state_of(const wcal_plan* plan) {
-    DdState st;
-    const int nd = plan->prob.n_dir;
-    st.rec = plan->d_stats;
-    const size_t nrec = (size_t)plan->prob.n_int * plan->prob.n_bl;
-    st.chi_bl = reinterpret_cast<double*>(plan->d_stats + nrec * rec_floats(nd));
-    st.ant_d = st.chi_bl + nrec;
-    st.ant_n = st.ant_d + (size_t)plan->prob.n_int * plan->prob.n_ant;
-    st.gn = reinterpret_cast<float2*>(st.ant_n + (size_t)plan->prob.n_int * plan->prob.n_ant);
-    st.ant_f = reinterpret_cast<int32_t*>(st.gn + (size_t)plan->prob.n_int * nd * plan->prob.n_ant);
-    st.alist = st.ant_f + (size_t)plan->prob.n_int * plan->prob.n_ant;
-    st.ant_ptr = plan->d_ant_ptr;
-    st.ant_bl = plan->d_ant_bl;
-    st.active = plan->d_active;
-    st.ctr = plan->d_ctr;
-    st.tiles = plan->d_tiles;
-    st.tile_off = plan->d_tile_off;
-    st.ntiles = plan->ntiles;
-    st.chi_part = plan->d_chi_part;
-    return st;
-}
-
 }  // namespace
 
-size_t dd_stats_bytes(const wcal_problem& p) {
-    const size_t n = (size_t)p.n_int * p.n_bl;
-    const size_t na = (size_t)p.n_int * p.n_ant;
-    return n * rec_floats(p.n_dir) * sizeof(float) + n * sizeof(double) + 2 * na * sizeof(double) +
-           na * p.n_dir * sizeof(float2) + na * sizeof(int32_t) + 2 * (size_t)p.n_int * sizeof(int32_t);
-}
+size_t dd_stats_bytes(const wcal_problem& p) { return dd_state_bytes(p, rec_floats(p.n_dir)); }
 
 size_t dd_smem_bytes(int nd, int na) { return dd_smem_size(nd, na); }
 
@@ -1022,7 +887,7 @@ int dd_max_dir() { return NDMAX; }
 
 static void launch_residual_tiles(const wcal_plan* plan, const DdArgs& a, const DdState& st, hipStream_t s,
                                   int slot) {
-    const int g = grid_res(plan, reinterpret_cast<const void*>(dd_resid_kernel), 0, st.ntiles);
+    const int g = dd_grid(plan, reinterpret_cast<const void*>(dd_resid_kernel), 0, st.ntiles);
     prof_begin(plan, WCAL_K_RESID, s);
     hipLaunchKernelGGL(dd_resid_kernel, dim3(g), dim3(DT), 0, s, a, st, slot);
     prof_end(plan, WCAL_K_RESID, s);
@@ -1031,7 +896,7 @@ static void launch_residual_tiles(const wcal_plan* plan, const DdArgs& a, const 
 
 hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t s) {
     DdArgs a = a0;
-    DdState st = state_of(plan);
+    DdState st = dd_state_of(plan, rec_floats(plan->prob.n_dir));
     const int nd = a.n_dir, na = a.n_ant;
     const int nctr = 2 * (a.max_iter + 2) + 4;
     const int64_t nblk = (int64_t)a.n_int * ((a.n_bl + GB - 1) / GB);
@@ -1039,7 +904,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const bool p16 = nd % 2 == 0 && reinterpret_cast<uintptr_t>(a.model) % 16 == 0;
     typedef void (*GramFn)(DdArgs, DdState, const int32_t*, const int32_t*);
     GramFn gram = !bf ? dd_gram_blk_kernel : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
-    const int gg = grid_res(plan, reinterpret_cast<const void*>(gram), 0, nblk);
+    const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), 0, nblk);
     const size_t asm_ = ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
     hipLaunchKernelGGL(dd_init_kernel, dim3((std::max(a.n_int, nctr) + DT - 1) / DT), dim3(DT), 0, s, a, st, 1, nctr);
@@ -1075,19 +940,19 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
 }
 
 hipError_t launch_dd_accumulate(const wcal_plan* plan, const DdArgs& a, hipStream_t s) {
-    DdState st = state_of(plan);
+    DdState st = dd_state_of(plan, rec_floats(plan->prob.n_dir));
     const int nd = a.n_dir, na = a.n_ant;
     const int nctr = 4;
     hipLaunchKernelGGL(dd_init_kernel, dim3(1), dim3(DT), 0, s, a, st, 0, nctr);
     const int64_t ntask = (int64_t)a.n_int * a.n_bl;
-    const int gg = grid_res(plan, reinterpret_cast<const void*>(dd_gram_kernel<true>), 0, (ntask + 3) / 4);
+    const int gg = dd_grid(plan, reinterpret_cast<const void*>(dd_gram_kernel<true>), 0, (ntask + 3) / 4);
     hipLaunchKernelGGL(dd_gram_kernel<true>, dim3(gg), dim3(DT), 0, s, a, st, 0);
     hipLaunchKernelGGL(dd_reduce_kernel, dim3(a.n_int), dim3(DT), dd_smem_bytes(nd, na), s, a, st);
     return hipGetLastError();
 }
 
 hipError_t launch_dd_residual(const wcal_plan* plan, const DdArgs& a, hipStream_t s) {
-    DdState st = state_of(plan);
+    DdState st = dd_state_of(plan, rec_floats(plan->prob.n_dir));
     hipLaunchKernelGGL(dd_init_kernel, dim3(1), dim3(DT), 0, s, a, st, 0, 4);
     launch_residual_tiles(plan, a, st, s, 3);
     return hipGetLastError();

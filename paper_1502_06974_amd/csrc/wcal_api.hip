@@ -259,8 +259,10 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
     if (p.algo == WCAL_STEFCAL) {
         if (p.n_dir != 1) return fail(WCAL_EINVAL, "StefCal needs n_dir == 1 (use CohJones/AllJones)");
     } else if (p.algo == WCAL_COHJONES || p.algo == WCAL_ALLJONES) {
-        if (p.n_corr != 1) return fail(WCAL_EINVAL, "CohJones/AllJones are implemented for n_corr == 1");
-        if (p.n_dir > dd_max_dir()) return fail(WCAL_ESHAPE, "n_dir above the supported maximum");
+        if (p.n_corr == 4 && p.precision != WCAL_PREC_FP32)
+            return fail(WCAL_EINVAL, "2x2 CohJones/AllJones take the FP32 Gram only");
+        if (p.n_dir > (p.n_corr == 4 ? ddp_max_dir() : dd_max_dir()))
+            return fail(WCAL_ESHAPE, "n_dir above the supported maximum");
     } else {
         return fail(WCAL_EINVAL, "unknown algorithm");
     }
@@ -298,7 +300,8 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
     }
     plan->n_cu = prop.multiProcessorCount;
     plan->max_smem = prop.sharedMemPerBlock;
-    if (p.algo != WCAL_STEFCAL && dd_smem_bytes(p.n_dir, p.n_ant) > plan->max_smem) {
+    if (p.algo != WCAL_STEFCAL &&
+        (p.n_corr == 4 ? ddp_smem_bytes(p.n_dir, p.n_ant) : dd_smem_bytes(p.n_dir, p.n_ant)) > plan->max_smem) {
         delete plan;
         return fail(WCAL_ESHAPE, "n_ant * n_dir too large for the per-interval LDS working set");
     }
@@ -348,7 +351,7 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tables");
     }
     if (p.algo != WCAL_STEFCAL) {
-        plan->stats_bytes = dd_stats_bytes(p);
+        plan->stats_bytes = p.n_corr == 4 ? ddp_stats_bytes(p) : dd_stats_bytes(p);
         if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
             wcal_plan_destroy(plan);
             return fail(WCAL_ENOMEM, "Gram record allocation failed");
@@ -391,6 +394,7 @@ int64_t wcal_plan_rows(const wcal_plan* plan) { return plan ? plan->rows : -1; }
 const char* wcal_plan_pass_kernel(const wcal_plan* plan) {
     if (!plan) return "";
     const wcal_problem& p = plan->prob;
+    if (p.algo != WCAL_STEFCAL && p.n_corr == 4) return ddp_pass_kernel_name(p.n_dir);
     if (p.algo != WCAL_STEFCAL) return p.precision == WCAL_PREC_BF16_GRAM ? "dd_gram_dma_kernel" : "dd_gram_blk_kernel";
     if (di_stats_solve(plan)) return p.n_corr == 1 ? "di_stats_kernel<1>" : "di_stats_kernel<4>";
     if (plan->tri) return "di_tri_pass_kernel";
@@ -433,6 +437,7 @@ static void fill_tables_dd(const wcal_plan* plan, DdArgs& a) {
     a.n_bl = plan->prob.n_bl;
     a.n_int = plan->prob.n_int;
     a.n_dir = plan->prob.n_dir;
+    a.n_corr = plan->prob.n_corr;
     a.max_iter = plan->prob.max_iter;
     a.schedule = plan->prob.schedule;
     a.algo = plan->prob.algo;
@@ -474,7 +479,7 @@ int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, con
         a.n_iter = n_iter;
         a.status = status;
         a.chi2 = chi2;
-        e = launch_dd_solve(plan, a, s);
+        e = plan->prob.n_corr == 4 ? launch_ddp_solve(plan, a, s) : launch_dd_solve(plan, a, s);
     }
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve launch");
 }
@@ -669,7 +674,7 @@ int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model
         a.jhd = reinterpret_cast<float2*>(jhd);
         a.jhr = reinterpret_cast<float2*>(jhr);
         a.count = count;
-        e = launch_dd_accumulate(plan, a, s);
+        e = plan->prob.n_corr == 4 ? launch_ddp_accumulate(plan, a, s) : launch_dd_accumulate(plan, a, s);
     }
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_accumulate launch");
 }
@@ -703,7 +708,7 @@ int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, 
         a.gains_in = reinterpret_cast<const float2*>(gains);
         a.residual = reinterpret_cast<float2*>(residual);
         a.chi2 = chi2;
-        e = launch_dd_residual(plan, a, s);
+        e = plan->prob.n_corr == 4 ? launch_ddp_residual(plan, a, s) : launch_dd_residual(plan, a, s);
     }
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_residual launch");
 }

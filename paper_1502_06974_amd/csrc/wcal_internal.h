@@ -118,7 +118,7 @@ struct DdArgs {
     const float2* data;      // [rows]
     const float2* model;     // [rows][nd]
     const uint8_t* flags;
-    float2* gains;           // [n_int][nd][n_ant]
+    float2* gains;           // [n_int][nd][n_ant][n_corr]
     const float2* gains_in;
     float2* residual;
     int32_t* n_iter;
@@ -135,7 +135,7 @@ struct DdArgs {
     const int32_t* ns;
     const int32_t* order;
     int32_t* queue;
-    int32_t n_ant, n_bl, n_int, n_dir, max_iter, schedule, algo, precision;
+    int32_t n_ant, n_bl, n_int, n_dir, n_corr, max_iter, schedule, algo, precision;
     double tol;
 };
 
@@ -159,5 +159,14 @@ hipError_t launch_dd_residual(const wcal_plan* plan, const DdArgs& a, hipStream_
 size_t dd_stats_bytes(const wcal_problem& p);
 size_t dd_smem_bytes(int nd, int na);
 int dd_max_dir();
+
+// 2x2 Jones gains (n_corr == 4)
+hipError_t launch_ddp_solve(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
+hipError_t launch_ddp_accumulate(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
+hipError_t launch_ddp_residual(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
+size_t ddp_stats_bytes(const wcal_problem& p);
+size_t ddp_smem_bytes(int nd, int na);
+int ddp_max_dir();
+const char* ddp_pass_kernel_name(int nd);
 
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);

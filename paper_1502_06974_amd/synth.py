@@ -225,6 +225,29 @@ def pol_di(n_ant: int, ns: Sequence[int], sigma: float = 0.01, leak: float = 0.1
                    dtype, dict(kind="pol_di", sigma=sigma, leak=leak, seed=seed), noise)
 
 
+def pol_dd(n_ant: int, ns: Sequence[int], n_dir: int, sigma: float = 0.03, leak: float = 0.1,
+           seed: int = 0, flag_frac: float = 0.0, device="cpu", dtype=torch.complex64,
+           noise: bool = True) -> Problem:
+    """Polarized direction-dependent problem (Sect. 4.4) with the 2x2 recipe of pol_di per
+    direction: G^d_p = [[g_x, l_xy], [l_yx, g_y]], g drawn as in scalar_di, leakages
+    CN(0, leak^2); every 2x2 entry of every M^d is CN(0, 1) i.i.d. (generic coherencies,
+    so the only gauge is one phase per direction); D = sum_d G^d_p M^d G^{dH}_q plus
+    CN(0, sigma^2) per correlation."""
+    gen = _gen(SEED_BASE * 16 + 6 + 7919 * seed, device)
+    ant1, ant2 = baselines(n_ant, device)
+    ns = torch.as_tensor(list(ns), dtype=torch.int64)
+    n_int = ns.numel()
+    rows = int(ns.sum()) * ant1.numel()
+    gains = torch.zeros(n_int, n_dir, n_ant, 4, dtype=dtype, device=device)
+    gains[..., 0] = _diag_gain((n_int, n_dir, n_ant), gen, device, dtype)
+    gains[..., 3] = _diag_gain((n_int, n_dir, n_ant), gen, device, dtype)
+    gains[..., 1] = _cn((n_int, n_dir, n_ant), leak * leak, gen, device, dtype)
+    gains[..., 2] = _cn((n_int, n_dir, n_ant), leak * leak, gen, device, dtype)
+    model = _cn((rows, n_dir, 4), 1.0, gen, device, dtype)
+    return _finish(n_ant, n_dir, 4, ant1, ant2, ns, model, gains, sigma, flag_frac, gen, device,
+                   dtype, dict(kind="pol_dd", sigma=sigma, leak=leak, seed=seed), noise)
+
+
 def ragged_ns(n_int: int, t_max: int = 30, f_max: int = 16, seed: int = 0) -> list:
     """Interval sizes Ns_k = T_k * F_k with T ~ U{1..t_max}, F ~ U{1..f_max}."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE, 1, seed])))
@@ -269,6 +292,42 @@ def bandpass_di(n_ant: int, n_chan: int, sigma: float = 0.05, seed: int = 0,
 C_LIGHT = 299792458.0
 
 
+def _array_geometry(n_ant, gen, device, disk_diam, lat_deg):
+    """Antennas uniform in a planar disk of diameter disk_diam (east, north), rotated to
+    local equatorial XYZ at array latitude lat_deg."""
+    f64 = torch.float64
+    r = 0.5 * disk_diam * torch.sqrt(torch.rand(n_ant, generator=gen, device=device, dtype=f64))
+    th = 2 * math.pi * torch.rand(n_ant, generator=gen, device=device, dtype=f64)
+    east, north = r * torch.cos(th), r * torch.sin(th)
+    lat = math.radians(lat_deg)
+    return (-math.sin(lat) * north, east, math.cos(lat) * north)
+
+
+def _uvw(geo, ant1, ant2, k, n_time, n_int, dt, dec_deg, device):
+    """u, v, w [n_time, n_bl] in metres for interval k: n_time timeslots of dt seconds in a
+    contiguous hour-angle block (the textbook XYZ -> uvw rotation at declination dec)."""
+    f64 = torch.float64
+    X, Y, Z = geo
+    dec = math.radians(dec_deg)
+    omega = 2 * math.pi / 86164.0905
+    H = (k * n_time + torch.arange(n_time, device=device, dtype=f64) - 0.5 * n_int * n_time) * dt * omega
+    bx = X[ant2.long()] - X[ant1.long()]
+    by = Y[ant2.long()] - Y[ant1.long()]
+    bz = Z[ant2.long()] - Z[ant1.long()]
+    sH, cH = torch.sin(H)[:, None], torch.cos(H)[:, None]
+    u = sH * bx[None] + cH * by[None]
+    v = -math.sin(dec) * cH * bx[None] + math.sin(dec) * sH * by[None] + math.cos(dec) * bz[None]
+    w = math.cos(dec) * cH * bx[None] - math.cos(dec) * sH * by[None] + math.sin(dec) * bz[None]
+    return u, v, w
+
+
+def _power_law(n, lo, hi, index, gen, device):
+    """n fluxes with dN/dS ~ S^index on [lo, hi] (inverse-CDF draw)."""
+    a1 = index + 1.0
+    uu = torch.rand(n, generator=gen, device=device, dtype=torch.float64)
+    return (lo ** a1 + uu * (hi ** a1 - lo ** a1)) ** (1.0 / a1)
+
+
 def dd_point(n_ant: int = 64, n_dir: int = 10, n_time: int = 30, n_chan: int = 64, n_int: int = 1,
              seed: int = 0, device="cpu", dtype=torch.complex64, noise_frac: float = 0.01,
              dt: float = 10.0, disk_diam: float = 5000.0, lat_deg: float = 52.0, dec_deg: float = 52.0,
@@ -290,39 +349,19 @@ def dd_point(n_ant: int = 64, n_dir: int = 10, n_time: int = 30, n_chan: int = 6
     f64 = torch.float64
     ant1, ant2 = baselines(n_ant, device)
     n_bl = ant1.numel()
-    # antenna positions: uniform in a disk (east, north), planar
-    r = 0.5 * disk_diam * torch.sqrt(torch.rand(n_ant, generator=gen, device=device, dtype=f64))
-    th = 2 * math.pi * torch.rand(n_ant, generator=gen, device=device, dtype=f64)
-    east, north = r * torch.cos(th), r * torch.sin(th)
-    lat = math.radians(lat_deg)
-    dec = math.radians(dec_deg)
-    # ENU -> equatorial XYZ (local)
-    X = -math.sin(lat) * north
-    Y = east
-    Z = math.cos(lat) * north
+    geo = _array_geometry(n_ant, gen, device, disk_diam, lat_deg)
     # sources
     fov = math.radians(fov_deg)
     l = (torch.rand(n_dir, generator=gen, device=device, dtype=f64) * 2 - 1) * fov
     mm = (torch.rand(n_dir, generator=gen, device=device, dtype=f64) * 2 - 1) * fov
     n = torch.sqrt(1 - l * l - mm * mm)
-    a1 = flux_index + 1.0
-    uu = torch.rand(n_dir, generator=gen, device=device, dtype=f64)
-    flux = (flux_lo ** a1 + uu * (flux_hi ** a1 - flux_lo ** a1)) ** (1.0 / a1)
+    flux = _power_law(n_dir, flux_lo, flux_hi, flux_index, gen, device)
     nu = nu_lo + (torch.arange(n_chan, device=device, dtype=f64) + 0.5) * (nu_hi - nu_lo) / n_chan
     ns = torch.full((n_int,), n_time * n_chan, dtype=torch.int64)
     rows = n_int * n_time * n_chan * n_bl
     model = torch.empty(rows, n_dir, 1, dtype=dtype, device=device)
-    omega = 2 * math.pi / 86164.0905
     for k in range(n_int):
-        H = (k * n_time + torch.arange(n_time, device=device, dtype=f64) - 0.5 * n_int * n_time) * dt * omega
-        # baseline vectors in XYZ, then uvw at each hour angle
-        bx = X[ant2.long()] - X[ant1.long()]
-        by = Y[ant2.long()] - Y[ant1.long()]
-        bz = Z[ant2.long()] - Z[ant1.long()]
-        sH, cH = torch.sin(H)[:, None], torch.cos(H)[:, None]
-        u = sH * bx[None] + cH * by[None]
-        v = -math.sin(dec) * cH * bx[None] + math.sin(dec) * sH * by[None] + math.cos(dec) * bz[None]
-        w = math.cos(dec) * cH * bx[None] - math.cos(dec) * sH * by[None] + math.sin(dec) * bz[None]
+        u, v, w = _uvw(geo, ant1, ant2, k, n_time, n_int, dt, dec_deg, device)
         # phase[t, b, d] per unit frequency
         ph = (u[..., None] * l + v[..., None] * mm + w[..., None] * (n - 1)) / C_LIGHT
         # rows ordered [s][bl] with s = t * n_chan + f
@@ -347,6 +386,90 @@ def dd_point(n_ant: int = 64, n_dir: int = 10, n_time: int = 30, n_chan: int = 6
                    dtype, meta, noise)
 
 
+def dd_point_pol(n_ant: int = 64, n_dir: int = 10, n_time: int = 30, n_chan: int = 64, n_int: int = 1,
+                 seed: int = 0, device="cpu", dtype=torch.complex64, noise_frac: float = 0.01,
+                 dt: float = 10.0, disk_diam: float = 5000.0, lat_deg: float = 52.0, dec_deg: float = 52.0,
+                 nu_lo: float = 100e6, nu_hi: float = 200e6, fov_deg: float = 1.0,
+                 n_comp: int = 3, cluster_deg: float = 0.05, pol_frac: float = 0.3, leak: float = 0.1,
+                 xy_phase: float = 0.2,
+                 flux_lo: float = 0.1, flux_hi: float = 10.0, flux_index: float = -1.5,
+                 noise: bool = True, smooth_gains: bool = True, flag_frac: float = 0.0) -> Problem:
+    """Polarized direction-dependent sky (Sect. 4.4) on the geometry of dd_point.
+    Direction d is a cluster of n_comp point sources: centre (l, m) ~ U(+-fov), each
+    component offset by U(+-cluster_deg) in l and m, with flux I from the same power
+    law and brightness B = [[I + Q, U + iV], [U - iV, I - Q]], (Q, U, V) / I each
+    U(+-pol_frac).  M^d_pq(t, nu) = sum_c B_c exp(-2 pi i (u l_c + v m_c + w (n_c - 1)) nu / c),
+    stored row-major (xx, xy, yx, yy).  The gauge of G^d -> G^d X is the set of X with
+    X B_c X^H = B_c for every component: for one positive-definite B a copy of U(2), for
+    two a pair of phases (both forms diagonalise under one congruence), for three or more
+    generic components one phase per direction.  Weakly polarized clusters leave those
+    directions only weakly determined, and the per-antenna updates then converge slowly.
+    Gains per (interval, direction, antenna): a phase screen common to both feeds,
+    U(-pi, pi) (drifting smoothly across intervals with smooth_gains), feed amplitudes
+    exp(N(0, 0.1^2)), a differential phase N(0, xy_phase^2) split between the feeds and
+    off-diagonal leakage CN(0, leak^2).  Noise per correlation CN(0, (noise_frac * sum of
+    fluxes)^2)."""
+    gen = _gen(SEED_BASE * 16 + 5 + 7919 * seed, device)
+    f64 = torch.float64
+    ant1, ant2 = baselines(n_ant, device)
+    n_bl = ant1.numel()
+    geo = _array_geometry(n_ant, gen, device, disk_diam, lat_deg)
+    fov, cl = math.radians(fov_deg), math.radians(cluster_deg)
+    lc = (torch.rand(n_dir, generator=gen, device=device, dtype=f64) * 2 - 1) * fov
+    mc = (torch.rand(n_dir, generator=gen, device=device, dtype=f64) * 2 - 1) * fov
+    l = lc[:, None] + (torch.rand(n_dir, n_comp, generator=gen, device=device, dtype=f64) * 2 - 1) * cl
+    mm = mc[:, None] + (torch.rand(n_dir, n_comp, generator=gen, device=device, dtype=f64) * 2 - 1) * cl
+    n = torch.sqrt(1 - l * l - mm * mm)
+    flux = _power_law(n_comp * n_dir, flux_lo, flux_hi, flux_index, gen, device).reshape(n_dir, n_comp)
+    qu = (torch.rand(n_dir, n_comp, 3, generator=gen, device=device, dtype=f64) * 2 - 1) * pol_frac * flux[..., None]
+    B = torch.empty(n_dir, n_comp, 2, 2, dtype=torch.complex128, device=device)    # [d, c, 2, 2]
+    B[..., 0, 0] = flux + qu[..., 0]
+    B[..., 1, 1] = flux - qu[..., 0]
+    B[..., 0, 1] = torch.complex(qu[..., 1], qu[..., 2])
+    B[..., 1, 0] = torch.complex(qu[..., 1], -qu[..., 2])
+    nu = nu_lo + (torch.arange(n_chan, device=device, dtype=f64) + 0.5) * (nu_hi - nu_lo) / n_chan
+    ns = torch.full((n_int,), n_time * n_chan, dtype=torch.int64)
+    rows = n_int * n_time * n_chan * n_bl
+    model = torch.empty(rows, n_dir, 4, dtype=dtype, device=device)
+    Bf = B.reshape(n_dir, n_comp, 4)
+    for k in range(n_int):
+        u, v, w = _uvw(geo, ant1, ant2, k, n_time, n_int, dt, dec_deg, device)
+        r0 = k * n_time * n_chan * n_bl
+        for t in range(n_time):
+            # phase [b, d, c] per unit frequency, then [f, b, d, c]
+            ph = (u[t, :, None, None] * l + v[t, :, None, None] * mm + w[t, :, None, None] * (n - 1)) / C_LIGHT
+            arg = -2 * math.pi * ph[None] * nu[:, None, None, None]
+            z = torch.polar(torch.ones_like(arg), arg)                           # [f, b, d, c]
+            mk = torch.einsum("fbdc,dce->fbde", z, Bf)                           # [f, b, d, 4]
+            a = r0 + t * n_chan * n_bl
+            model[a:a + n_chan * n_bl] = mk.reshape(-1, n_dir, 4).to(dtype)
+    # a phase common to both feeds (U(-pi, pi) per direction and antenna, drifting smoothly
+    # across intervals), feed amplitudes exp(N(0, 0.1^2)), a differential phase N(0, xy^2)
+    # between the feeds and leakage CN(0, leak^2)
+    amp = torch.exp(0.1 * torch.randn(n_dir, n_ant, 2, generator=gen, device=device, dtype=f64))
+    ph0 = (torch.rand(n_dir, n_ant, 1, generator=gen, device=device, dtype=f64) * 2 - 1) * math.pi
+    ph0 = ph0 + xy_phase * torch.randn(n_dir, n_ant, 2, generator=gen, device=device, dtype=f64) * \
+        torch.tensor([0.5, -0.5], device=device, dtype=f64)
+    lk = _cn((n_dir, n_ant, 2), leak * leak, gen, device, torch.complex128)
+    if smooth_gains and n_int > 1:
+        rate = 0.3 * torch.randn(n_dir, n_ant, 1, generator=gen, device=device, dtype=f64)
+        slope = 0.02 * torch.randn(n_dir, n_ant, 2, generator=gen, device=device, dtype=f64)
+        x = torch.linspace(-1, 1, n_int, device=device, dtype=f64)[:, None, None, None]
+        diag = torch.polar(amp[None] * (1 + slope[None] * x), ph0[None] + rate[None] * x)
+    else:
+        diag = torch.polar(amp, ph0)[None].expand(n_int, -1, -1, -1)
+    gains = torch.empty(n_int, n_dir, n_ant, 4, dtype=torch.complex128, device=device)
+    gains[..., 0] = diag[..., 0]
+    gains[..., 3] = diag[..., 1]
+    gains[..., 1] = lk[None, ..., 0]
+    gains[..., 2] = lk[None, ..., 1]
+    gains = gains.to(dtype).contiguous()
+    sigma = noise_frac * float(flux.sum())
+    meta = dict(kind="dd_point_pol", seed=seed, l=l.cpu(), m=mm.cpu(), B=B.cpu(), sigma=sigma)
+    return _finish(n_ant, n_dir, 4, ant1, ant2, ns, model, gains, sigma, flag_frac, gen, device,
+                   dtype, meta, noise)
+
+
 # ---------------------------------------------------------------- workload presets
 def workload(name: str, device="cpu", dtype=torch.complex64, **kw) -> Problem:
     """Named workloads with the shapes of the measured configurations.
@@ -355,6 +478,8 @@ def workload(name: str, device="cpu", dtype=torch.complex64, **kw) -> Problem:
     pol2x2_na64     : Na=64, 2016 baselines, 1000 ragged intervals (T~U{1..30} x F~U{1..16}),
                       5% flags, 2x2 Jones with 0.1 leakage, sigma 0.01
     cohjones_na64   : Na=64, Nd=10 point-source directions, 30 x 64 samples per interval
+    pol_cohjones_na64 : Na=64, Nd=10, 2x2 Jones, 16 intervals of 30 x 64 samples, i.i.d.
+                      CN(0,1) coherencies per direction (the 2x2 recipe), sigma 0.03
     bandpass_na256  : Na=256, 32640 baselines, 4096 channels solved independently (Ns=1), sigma 0.05
     """
     if name == "scalar_na27":
@@ -366,6 +491,9 @@ def workload(name: str, device="cpu", dtype=torch.complex64, **kw) -> Problem:
                       device=device, dtype=dtype, **kw)
     if name == "cohjones_na64":
         return dd_point(64, 10, device=device, dtype=dtype, **kw)
+    if name == "pol_cohjones_na64":
+        n_int = kw.pop("n_int", 16)
+        return pol_dd(64, kw.pop("ns", None) or [30 * 64] * n_int, 10, device=device, dtype=dtype, **kw)
     if name == "bandpass_na256":
         return bandpass_di(256, kw.pop("n_chan", 4096), sigma=0.05, device=device, dtype=dtype, **kw)
     raise ValueError(name)

@@ -260,7 +260,7 @@ class Plan:
         self._inputs(data, model, flags, gains)
         dev = gains.device
         nd, nc, na, ni = self.n_dir, self.n_corr, self.n_ant, self.n_int
-        blk = 4 if nc == 4 else nd * nd
+        blk = (2 * nd) ** 2 if nc == 4 else nd * nd
         jhj = torch.empty(ni, na, blk, dtype=torch.complex64, device=dev)
         jhd = torch.empty(ni, na, nd * nc, dtype=torch.complex64, device=dev)
         jhr = torch.empty(ni, na, nd * nc, dtype=torch.complex64, device=dev)

@@ -48,7 +48,8 @@ def _create(n_ant, a1, a2, ns, **kw):
     ([0, 0, 1], [1, 2, 2], [2, 0], {}, wcal.ESHAPE),        # empty interval
     ([0, 0, 1], [1, 2, 2], [2], {"n_corr": 2}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"n_dir": 2}, wcal.EINVAL),            # StefCal with 2 directions
-    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_corr": 4}, wcal.EINVAL),  # CohJones 2x2
+    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_corr": 4, "precision": 1}, wcal.EINVAL),  # 2x2 DD + BF16
+    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_corr": 4, "n_dir": 11}, wcal.ESHAPE),     # 2x2 DD, Nd > 10
     ([0, 0, 1], [1, 2, 2], [2], {"max_iter": 0}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"tol": -1.0}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"schedule": 7}, wcal.EINVAL),
