@@ -27,13 +27,28 @@ METRIC = "visibility-iterations/s (JHJ+JHr+residual) and solve time to 1e-6 rel.
 HBM_PEAK_GBS = 8000.0
 MFMA_FP32_PEAK_TFS = 157.3     # dense FP32 matrix peak of one MI355X
 MFMA_BF16_PEAK_TFS = 2500.0    # dense BF16 matrix peak of one MI355X
-# three 16x16x4 FP32 MFMAs per 4 samples, or three 16x16x16 BF16 MFMAs per 16 samples
-MFMA_ISSUED_FLOP_PER_ROW = 3 * 2 * 16 * 16 * 4 / 4
+
+
+def gram_flop_per_row(n_corr: int, n_dir: int) -> float:
+    """Algorithmic flops of the Gram pass per row: the Hermitian model block (complex HERK,
+    4 n^2 per sample for n model columns) and the model-data block (complex GEMM, 8 flops
+    per complex product): n = Nd, one data column (scalar); n = 4 Nd, four (2x2)."""
+    n_m, n_d = n_dir * n_corr, n_corr
+    return 4.0 * n_m * n_m + 8.0 * n_m * n_d
+
+
+def gram_issued_flop_per_row(n_corr: int, n_dir: int) -> float:
+    """Flops the MFMAs issue per row: per 4 samples three 16x16x4 MFMAs per diagonal
+    16-column tile and three per off-diagonal tile pair (Gauss's complex product; the BF16
+    pass issues the same per 16 samples with 16x16x16 MFMAs)."""
+    nt = 1 if n_corr == 1 else (4 * n_dir + 4 + 15) // 16
+    return (3 * nt + 3 * nt * (nt - 1) // 2) * 2 * 16 * 16 * 4 / 4
 
 
 KERNEL_SOURCES = {
     "di": ("di_kernels.hip", "di_common.h"),
-    "dd": ("dd_kernels.hip",),
+    "dd": ("dd_kernels.hip", "dd_common.h", "di_common.h"),
+    "ddp": ("ddp_kernels.hip", "dd_common.h", "di_common.h"),
 }
 
 
@@ -71,21 +86,26 @@ def bytes_per_row(n_corr: int, n_dir: int, flags: bool) -> int:
 
 def cpu_baseline_dd(P, budget_s: float = 15.0):
     """CPU oracle CohJones on the first samples of one interval (the oracle forms every
-    row's Nd x Nd product in complex128, so whole 1920-sample intervals do not fit)."""
+    row's Nd x Nd (2x2: 2Nd x 2Nd) product in complex128, so whole 1920-sample intervals
+    do not fit)."""
     import numpy as np
     from oracle import calib as oc
-    ns_take = 32
+    from oracle import driver as glue
+    ns_take = 32 if P.n_corr == 1 else 8
     iv = P.interval(0)
     nsel = ns_take * P.n_bl
-    d, m = iv["d"][:nsel, 0], iv["m"][:nsel, :, 0]
+    d, m = glue.split(iv, P.n_corr, P.n_dir, "cohjones")
+    d, m = d[:nsel], m[:nsel]
     p, q, fl = iv["p"][:nsel], iv["q"][:nsel], iv["flags"][:nsel]
-    g0 = np.ones((P.n_dir, P.n_ant), complex)
+    g0 = glue.gains_to_oracle(P.unit_gains()[0].cpu().numpy(), P.n_corr, P.n_dir, "cohjones")
+    fn = oc.cohjones if P.n_corr == 1 else oc.cohjones_2x2
     t0 = time.perf_counter()
-    o = oc.cohjones(d, m, p, q, fl, g0, tol=1e-6, max_iter=100)
+    o = fn(d, m, p, q, fl, g0, tol=1e-6, max_iter=100)
     dt = time.perf_counter() - t0
     return dict(value=nsel * o["n_iter"] / dt, unit="vis-iter/s", cores=1, kind="oracle",
-                sample=f"CohJones on the first {ns_take} samples x {P.n_bl} baselines of one interval, "
-                       f"{P.n_dir} directions, unit start, tol 1e-6, {o['n_iter']} updates, one process",
+                sample=f"{'' if P.n_corr == 1 else '2x2 '}CohJones on the first {ns_take} samples x "
+                       f"{P.n_bl} baselines of one interval, {P.n_dir} directions, unit start, tol 1e-6, "
+                       f"{o['n_iter']} updates, one process",
                 seconds=round(dt, 2))
 
 
@@ -246,9 +266,8 @@ def main():
     kms, klaunch = prof[kcls]
     achieved = kbytes / (kms * 1e-3) / 1e9
     if dd:
-        # Gram of [M | d]: Nd x Nd complex products and the Nd-vector with the data per row
-        useful = krows * (8 * P.n_dir * P.n_dir + 8 * P.n_dir)
-        issued = krows * MFMA_ISSUED_FLOP_PER_ROW
+        useful = krows * gram_flop_per_row(P.n_corr, P.n_dir)
+        issued = krows * gram_issued_flop_per_row(P.n_corr, P.n_dir)
         tfs = useful / (kms * 1e-3) / 1e12
         tfs_issued = issued / (kms * 1e-3) / 1e12
     conv = float((st & 1).float().mean())

@@ -22,8 +22,10 @@
 // with W^ce = G^{cH}_o G^e_o.  Lane l of a wavefront holds column l % 16 of sample l / 16;
 // each v_mfma_f32_16x16x4f32 consumes 4 samples.  The complex Gram is formed in a real
 // embedding: a diagonal 16-column tile takes three MFMAs (Re = Ar^T Ar + Ai^T Ai,
-// T = Ar^T Ai, Im = T - T^T), an off-diagonal tile pair four (Re as before,
-// Im = Ar^T Bi - Ai^T Br).  Flagged samples enter as zeros (selected, not multiplied).
+// T = Ar^T Ai, Im = T - T^T), an off-diagonal tile pair three by Gauss's product
+// (T1 = Ar^T Br, T2 = Ai^T Bi, T3 = (Ar + Ai)^T (Br - Bi); Re = T1 + T2,
+// Im = T1 - T2 - T3), 18 MFMAs per 4 samples at three tiles instead of 21.  Flagged
+// samples enter as zeros (selected, not multiplied).
 // The accumulate pass adds four residual columns vec R, R = D - sum_d G^d_p M^d G^{dH}_q
 // formed per sample in the pass, whose products with the model columns give J^H r.
 #include "dd_common.h"
@@ -33,8 +35,8 @@ using namespace wcal_dev;
 namespace {
 
 constexpr int PND = 10;   // directions: 4 (Nd + 2) columns fit three 16-wide tiles
-constexpr int PGB = 8;    // baselines per workgroup task (two per wavefront)
-constexpr int PGS = 8;    // samples per chunk
+constexpr int PGB = 4;    // baselines per workgroup task (one per wavefront)
+constexpr int PGS = 16;   // samples per chunk
 
 // per-sample columns [M | D]
 __host__ __device__ inline int pcols(int nd) { return 4 * nd + 4; }
@@ -50,10 +52,12 @@ inline int ptiles(int nd, bool with_r) { return (4 * nd + (with_r ? 8 : 4) + 15)
 __host__ __device__ inline int pn_h(int nd) { return ntri(2 * nd); }
 __host__ __device__ inline int pn_n(int nd) { return 4 * nd; }
 constexpr int PNOUT = (2 * PND) * (2 * PND + 1) / 2 + 2 * 4 * PND;   // 290
+constexpr int PMCH = 256;   // rows of an antenna whose metadata is staged at once
 // LDS bytes of the gains [nd][na][4], rounded up to 16
 __host__ __device__ inline size_t pg_bytes(int nd, int na) { return (size_t)nd * na * 4 * sizeof(float2); }
 inline size_t pant_smem(int nd, int na) {
-    return pg_bytes(nd, na) + ((size_t)(DT / WAVE) * PNOUT + pn_h(nd) + 4 * pn_n(nd)) * sizeof(double2);
+    return pg_bytes(nd, na) + ((size_t)(DT / WAVE) * PNOUT + pn_h(nd) + 4 * pn_n(nd)) * sizeof(double2) +
+           2 * (size_t)PMCH * sizeof(int);
 }
 
 // ------------------------------------------------------------------ Gram pass
@@ -62,7 +66,9 @@ inline size_t pant_smem(int nd, int na) {
 // segment (PGB * 4 Nd complex) and their data rows another (PGB * 4), so a chunk is read
 // as 16-byte pieces with consecutive addresses across the workgroup, staged in registers
 // while the previous chunk is consumed, and laid out in LDS as [sample][baseline][column].
-// Wavefront w runs the MFMAs of baselines 2w and 2w + 1.
+// Wavefront w runs the MFMAs of baseline w: per chunk it reads its operands of all four
+// 4-sample groups from LDS at once, then issues the first product into every accumulator
+// before any second one, so dependent MFMAs stay a dozen apart.
 constexpr int PQPT = (PGS * PGB * (4 * PND + 4) / 2 + DT - 1) / DT;   // staged float4 per thread
 
 template <int NT, bool WITH_R>
@@ -86,7 +92,7 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
     if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
     const bool has_flags = a.flags != nullptr;
     // static decode of this thread's staged pieces: offset in float4 from the chunk's first
-    // model (or data) row, and a code (LDS float4 slot | sample << 11 | baseline << 14 |
+    // model (or data) row, and a code (LDS float4 slot | sample << 11 | baseline << 15 |
     // data << 17; -1 for no piece)
     const int qm = PGB * nm / 2, qd = PGB * 2;   // float4 per sample: model, data
     int goff[PQPT], code[PQPT];
@@ -100,11 +106,11 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
             if (rem < qm) {
                 const int bl = 2 * rem / nm, c = 2 * rem % nm;
                 goff[r] = sm * nbl * (nm / 2) + rem;
-                code[r] = (((sm * PGB + bl) * W16 + c) >> 1) | (sm << 11) | (bl << 14);
+                code[r] = (((sm * PGB + bl) * W16 + c) >> 1) | (sm << 11) | (bl << 15);
             } else {
                 const int dq = rem - qm, bl = dq >> 1, c = nm + 2 * (dq & 1);
                 goff[r] = sm * nbl * 2 + dq;
-                code[r] = (((sm * PGB + bl) * W16 + c) >> 1) | (sm << 11) | (bl << 14) | (1 << 17);
+                code[r] = (((sm * PGB + bl) * W16 + c) >> 1) | (sm << 11) | (bl << 15) | (1 << 17);
             }
         }
     }
@@ -136,7 +142,7 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
 #pragma unroll
             for (int r = 0; r < PQPT; ++r) {
                 const int cd = code[r];
-                const bool ok = cd >= 0 && s0 + ((cd >> 11) & 7) < ns && b0 + ((cd >> 14) & 7) < nbl;
+                const bool ok = cd >= 0 && s0 + ((cd >> 11) & 15) < ns && b0 + ((cd >> 15) & 3) < nbl;
                 stage[r] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (ok) stage[r] = (cd >> 17) ? load_at(db, goff[r]) : load_at(mb, goff[r]);
             }
@@ -144,15 +150,13 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
             fstage = 1;
             if (fok) fstage = has_flags ? (uint8_t)(a.flags[row0 + (int64_t)fs * nbl + fb] != 0) : (uint8_t)0;
         };
-        floatx4 dre[2][NT], dti[2][NT], ore[2][NT * (NT - 1) / 2 + 1], oim[2][NT * (NT - 1) / 2 + 1];
-        int cnt[2] = {0, 0};
+        constexpr int NO = NT * (NT - 1) / 2 + 1;
+        floatx4 dre[NT], dti[NT], ot1[NO], ot2[NO], ot3[NO];   // diagonal: Re, T; off-diagonal: T1, T2, T3
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int t = 0; t < NT; ++t) { dre[t] = floatx4{0.f, 0.f, 0.f, 0.f}; dti[t] = dre[t]; }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) { dre[j][t] = floatx4{0.f, 0.f, 0.f, 0.f}; dti[j][t] = dre[j][t]; }
-#pragma unroll
-            for (int t = 0; t < NT * (NT - 1) / 2 + 1; ++t) { ore[j][t] = floatx4{0.f, 0.f, 0.f, 0.f}; oim[j][t] = ore[j][t]; }
-        }
+        for (int t = 0; t < NO; ++t) { ot1[t] = floatx4{0.f, 0.f, 0.f, 0.f}; ot2[t] = ot1[t]; ot3[t] = ot1[t]; }
+        int cnt = 0;
         double chi = 0.0;
         fetch(0);
         for (int c = 0; c < nch; ++c) {
@@ -191,39 +195,45 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
                 abuf[sm][bl][ncs + e] = r;
                 __syncthreads();
             }
+            constexpr int NG = PGS / 4;
+            float2 v[NG][NT];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int bl = 2 * w + j;
+            for (int g = 0; g < NG; ++g) {
+                const int sl = 4 * g + kk;
+                const bool use = !fbuf[sl][w];
 #pragma unroll
-                for (int g = 0; g < PGS / 4; ++g) {
-                    const int sl = 4 * g + kk;
-                    const bool use = !fbuf[sl][bl];
-                    float2 v[NT];
+                for (int t = 0; t < NT; ++t) {
+                    const int cc = 16 * t + col;
+                    v[g][t] = (use && cc < nct) ? abuf[sl][w][cc] : make_float2(0.f, 0.f);
+                }
+                if (use && col == 0) ++cnt;
+            }
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        const int cc = 16 * t + col;
-                        v[t] = (use && cc < nct) ? abuf[sl][bl][cc] : make_float2(0.f, 0.f);
-                    }
-                    if (use && col == 0) ++cnt[j];
+            for (int g = 0; g < NG; ++g) {
+                // first products into every accumulator, then the second ones
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    dre[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[g][t].x, v[g][t].x, dre[t], 0, 0, 0);
+                    dti[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[g][t].x, v[g][t].y, dti[t], 0, 0, 0);
+                }
+                {
                     int o = 0;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        dre[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[t].x, v[t].x, dre[j][t], 0, 0, 0);
-                        dre[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[t].y, v[t].y, dre[j][t], 0, 0, 0);
-                        dti[j][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[t].x, v[t].y, dti[j][t], 0, 0, 0);
+                    for (int t = 0; t < NT; ++t)
 #pragma unroll
                         for (int u = t + 1; u < NT; ++u, ++o) {
-                            ore[j][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[t].x, v[u].x, ore[j][o], 0, 0, 0);
-                            ore[j][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[t].y, v[u].y, ore[j][o], 0, 0, 0);
-                            oim[j][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[t].x, v[u].y, oim[j][o], 0, 0, 0);
-                            oim[j][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(-v[t].y, v[u].x, oim[j][o], 0, 0, 0);
+                            ot1[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[g][t].x, v[g][u].x, ot1[o], 0, 0, 0);
+                            ot2[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[g][t].y, v[g][u].y, ot2[o], 0, 0, 0);
+                            ot3[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[g][t].x + v[g][t].y, v[g][u].x - v[g][u].y, ot3[o], 0, 0, 0);
                         }
-                    }
                 }
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    dre[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[g][t].y, v[g][t].y, dre[t], 0, 0, 0);
             }
         }
-        // epilogue: records of the wavefront's two baselines; the diagonal tiles go through
-        // the wavefront's own 2 x 256 floats of the (now free) staging buffer
+        // epilogue: the record of the wavefront's baseline; the diagonal tiles go through the
+        // wavefront's own 2 x 256 floats of the (now free) staging buffer
         __syncthreads();
         float* tile = reinterpret_cast<float*>(&abuf[0][0][0]) + w * 512;
         // entry (c1, c2), c1 <= c2, of the Gram: [M | D] block or the W block
@@ -238,20 +248,18 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
                 rec[t + 1] = im;
             }
         };
+        {
+            const int b = b0 + w;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int b = b0 + 2 * w + j;
-            int cj = cnt[j];
-#pragma unroll
-            for (int o = WAVE / 2; o > 0; o >>= 1) cj += __shfl_xor(cj, o, WAVE);
+            for (int o = WAVE / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, WAVE);
             float* rec = st.rec + ((int64_t)k * nbl + b) * RS;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * (lane >> 4) + r;
-                    tile[i * 16 + col] = dre[j][t][r];
-                    tile[256 + i * 16 + col] = dti[j][t][r];
+                    tile[i * 16 + col] = dre[t][r];
+                    tile[256 + i * 16 + col] = dti[t][r];
                 }
                 __builtin_amdgcn_wave_barrier();
                 if (b < nbl)
@@ -272,9 +280,9 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int c1 = 16 * t + 4 * (lane >> 4) + r, c2 = 16 * u + col;
-                            if (c2 < nct) put(rec, c1, c2, ore[j][o][r], oim[j][o][r]);
+                            if (c2 < nct) put(rec, c1, c2, ot1[o][r] + ot2[o][r], ot1[o][r] - ot2[o][r] - ot3[o][r]);
                         }
-                if (lane == 0) reinterpret_cast<int*>(rec)[prec_cnt(nd)] = cj;
+                if (lane == 0) reinterpret_cast<int*>(rec)[prec_cnt(nd)] = cnt;
             }
         }
         if constexpr (WITH_R) {
@@ -292,7 +300,7 @@ __device__ __forceinline__ void ddp_gram_body(const DdArgs& a, const DdState& st
 }
 
 template <int NT>
-__global__ void __launch_bounds__(DT) ddp_gram_kernel(DdArgs a, DdState st, const int32_t* list,
+__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8))) ddp_gram_kernel(DdArgs a, DdState st, const int32_t* list,
                                                       const int32_t* n_list) {
     ddp_gram_body<NT, false>(a, st, list, n_list);
 }
@@ -324,61 +332,22 @@ __device__ __forceinline__ double2 phget(const double2* h, int i, int j, int n) 
     return i <= j ? h[tri(i, j, n)] : dconj(h[tri(j, i, n)]);
 }
 
-// In-place Cholesky H = R^H R of the packed upper triangle; false when a pivot <= EPS * H_jj.
-__device__ bool pchol_factor(double2* h, int n) {
-    for (int i = 0; i < n; ++i) {
-        const double hii = h[tri(i, i, n)].x;
-        double piv = hii;
-        for (int k = 0; k < i; ++k) {
-            const double2 r = h[tri(k, i, n)];
-            piv -= r.x * r.x + r.y * r.y;
-        }
-        if (!(piv > WCAL_EPS_PIVOT * hii) || !isfinite(piv)) return false;
-        const double rii = sqrt(piv);
-        h[tri(i, i, n)] = make_double2(rii, 0.0);
-        for (int j = i + 1; j < n; ++j) {
-            double2 v = h[tri(i, j, n)];
-            for (int k = 0; k < i; ++k) {
-                const double2 p = dcmulc(h[tri(k, i, n)], h[tri(k, j, n)]);
-                v.x -= p.x; v.y -= p.y;
-            }
-            h[tri(i, j, n)] = make_double2(v.x / rii, v.y / rii);
-        }
-    }
-    return true;
-}
-
-// x = H^-1 c with the factor R of pchol_factor: R^H z = c, then R x = z (x may alias c)
-__device__ void pchol_subst(const double2* h, const double2* c, double2* x, int n) {
-    for (int i = 0; i < n; ++i) {
-        double2 v = c[i];
-        for (int k = 0; k < i; ++k) {
-            const double2 p = dcmulc(h[tri(k, i, n)], x[k]);
-            v.x -= p.x; v.y -= p.y;
-        }
-        const double rii = h[tri(i, i, n)].x;
-        x[i] = make_double2(v.x / rii, v.y / rii);
-    }
-    for (int i = n - 1; i >= 0; --i) {
-        double2 v = x[i];
-        for (int k = i + 1; k < n; ++k) {
-            const double2 p = dmul(h[tri(i, k, n)], x[k]);
-            v.x -= p.x; v.y -= p.y;
-        }
-        const double rii = h[tri(i, i, n)].x;
-        x[i] = make_double2(v.x / rii, v.y / rii);
-    }
-}
-
-// One workgroup per (interval, antenna): lanes run over the outputs (H packed upper, N,
-// and J^H r when accumulating); the four wavefronts take every fourth of the antenna's
-// baselines (in CSR order) and their FP64 sums are folded in wavefront order.  Solve mode:
-// one lane solves (CohJones: Cholesky, two right-hand sides; AllJones: 2x2 per direction,
-// residual form), applies the schedule and writes the candidate gains and its share of the
-// relative-change norms.  Accumulate mode writes the blocks instead.
+// One workgroup per (interval, antenna).  Contraction: lanes run over the outputs (H packed
+// upper, N, and J^H r when accumulating), the four wavefronts take every fourth of the
+// antenna's baselines in CSR order (record offset, side and other antenna staged in LDS
+// once), two baselines' record loads in flight per lane; the wavefronts' FP64 sums are
+// folded in wavefront order.
+// Solve mode, in FP64: CohJones factors H = R^H R across the workgroup (right-looking: one
+// pivot per step, then the trailing triangle in parallel) and one thread per row of the
+// gains substitutes; AllJones forms J^H r = N - G H and the per-direction 2x2 steps in
+// parallel.  The schedule is applied per gain entry, and the FP64 relative-change norms
+// are summed in a fixed order.  Accumulate mode writes the blocks instead.
 template <bool ACC>
 __global__ void __launch_bounds__(DT) ddp_ant_kernel(DdArgs a, DdState st, int it) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[DT / WAVE];
+    __shared__ double hdiag[2 * PND];
+    __shared__ int s_bad;      // 1: non-finite blocks, 2: singular block
     const int nd = a.n_dir, na = a.n_ant, nbl = a.n_bl;
     const int n2 = 2 * nd, nm = 4 * nd, ncs = nm + 4;
     const int nh = pn_h(nd), nn = pn_n(nd);
@@ -394,71 +363,92 @@ __global__ void __launch_bounds__(DT) ddp_ant_kernel(DdArgs a, DdState st, int i
     double2* N = H + nh;               // [2][n2]
     double2* JR = N + nn;              // [2][n2]
     double2* X = JR + nn;              // [2][n2]
+    double2* S = part;                 // [n2][n2] Cholesky factor (after the fold)
     const float2* gk = (ACC ? a.gains_in : a.gains) + (int64_t)k * nd * na * 4;
     for (int i = threadIdx.x; i < nd * na * 4; i += DT) G[i] = gk[i];
+    if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const int RS = prec_floats(nd);
     const float* recs = st.rec + (int64_t)k * nbl * RS;
     const int t0 = st.ant_ptr[p], t1 = st.ant_ptr[p + 1];
-    for (int e = lane; e < nout; e += WAVE) {
-        double2 acc = make_double2(0.0, 0.0);
-        if (e < nh) {
-            int r1 = 0, rem = e;
-            while (rem >= n2 - r1) { rem -= n2 - r1; ++r1; }
-            const int r2 = r1 + rem;
-            const int c = r1 >> 1, kr = r1 & 1, ee = r2 >> 1, l = r2 & 1;
-            for (int t = t0 + w; t < t1; t += nw) {
-                const int code = st.ant_bl[t];
-                const int b = code >> 1, side = code & 1;
-                const int o = side ? a.ant1[b] : a.ant2[b];
-                const float* rec = recs + (int64_t)b * RS;
-                const float2* gc = G + (c * na + o) * 4;
-                const float2* ge = G + (ee * na + o) * 4;
+    // the antenna's rows, staged in LDS in chunks of PMCH: record offset, and
+    // side | other antenna << 1 (chunk starts are multiples of the wavefront count, so each
+    // wavefront sums the same rows in the same order whatever the chunking)
+    int* meta = reinterpret_cast<int*>(X + nn);     // [2 PMCH]
+    for (int e = lane; e < nout; e += WAVE) part[w * PNOUT + e] = make_double2(0.0, 0.0);
+    for (int base = t0; base < t1; base += PMCH) {
+        const int nt = min(PMCH, t1 - base);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nt; t += DT) {
+            const int code = st.ant_bl[base + t];
+            const int b = code >> 1, side = code & 1;
+            meta[2 * t] = b * RS;
+            meta[2 * t + 1] = side | ((side ? a.ant1[b] : a.ant2[b]) << 1);
+        }
+        __syncthreads();
+        for (int e = lane; e < nout; e += WAVE) {
+            double2 acc = part[w * PNOUT + e];
+            if (e < nh) {
+                int r1 = 0, rem = e;
+                while (rem >= n2 - r1) { rem -= n2 - r1; ++r1; }
+                const int r2 = r1 + rem;
+                const int c = r1 >> 1, kr = r1 & 1, ee = r2 >> 1, l = r2 & 1;
+#pragma unroll 2
+                for (int t = w; t < nt; t += nw) {
+                    const int side = meta[2 * t + 1] & 1, o = meta[2 * t + 1] >> 1;
+                    const float* rec = recs + meta[2 * t];
+                    // H[2c+kr][2ee+l] += sum_ab W^{c,ee}[a][b] x_ab, W = G^{cH}_o G^{ee}_o
+                    float2 x[4];
 #pragma unroll
-                for (int aa = 0; aa < 2; ++aa)
+                    for (int ab = 0; ab < 4; ++ab) {
+                        const int aa = ab >> 1, bb = ab & 1;
+                        const int xi = side ? 4 * c + 2 * aa + kr : 4 * c + 2 * kr + aa;
+                        const int yi = side ? 4 * ee + 2 * bb + l : 4 * ee + 2 * l + bb;
+                        // stored (min, max); conjugate when swapped, and once more on side 0
+                        const float* q = rec + 2 * (xi <= yi ? tri(xi, yi, ncs) : tri(yi, xi, ncs));
+                        const bool cj = (xi > yi) != (side == 0);
+                        x[ab] = make_float2(q[0], cj ? -q[1] : q[1]);
+                    }
+                    const float2* gc = G + (c * na + o) * 4;
+                    const float2* ge = G + (ee * na + o) * 4;
 #pragma unroll
-                    for (int bb = 0; bb < 2; ++bb) {
-                        // W^ce[aa][bb] = sum_j conj(G^c_o[j][aa]) G^e_o[j][bb]
+                    for (int ab = 0; ab < 4; ++ab) {
+                        const int aa = ab >> 1, bb = ab & 1;
                         const double2 w0 = dcmulc(d2(gc[aa]), d2(ge[bb]));
                         const double2 w1 = dcmulc(d2(gc[2 + aa]), d2(ge[2 + bb]));
-                        const double2 wv = make_double2(w0.x + w1.x, w0.y + w1.y);
-                        const double2 x = side ? gram_at(rec, 4 * c + 2 * aa + kr, 4 * ee + 2 * bb + l, ncs)
-                                               : dconj(gram_at(rec, 4 * c + 2 * kr + aa, 4 * ee + 2 * l + bb, ncs));
-                        const double2 pr = dmul(wv, x);
+                        const double2 pr = dmul(make_double2(w0.x + w1.x, w0.y + w1.y), d2(x[ab]));
                         acc.x += pr.x; acc.y += pr.y;
                     }
-            }
-        } else {
-            const int f = e - nh;
-            const bool jr = f >= nn;
-            const int idx = jr ? f - nn : f;
-            const int i = idx / n2, cc = idx % n2, ee = cc >> 1, l = cc & 1;
-            for (int t = t0 + w; t < t1; t += nw) {
-                const int code = st.ant_bl[t];
-                const int b = code >> 1, side = code & 1;
-                const int o = side ? a.ant1[b] : a.ant2[b];
-                const float* rec = recs + (int64_t)b * RS;
-                const float2* ge = G + (ee * na + o) * 4;
+                }
+            } else {
+                const int f = e - nh;
+                const bool jr = f >= nn;
+                const int idx = jr ? f - nn : f;
+                const int i = idx / n2, cc = idx % n2, ee = cc >> 1, l = cc & 1;
+#pragma unroll 2
+                for (int t = w; t < nt; t += nw) {
+                    const int side = meta[2 * t + 1] & 1, o = meta[2 * t + 1] >> 1;
+                    const float* rec = recs + meta[2 * t];
+                    // N[i][2ee+l] (or J^H r) += sum_jb G^{ee}_o[j][b] x_jb
+                    float2 x[4];
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                    for (int jb = 0; jb < 4; ++jb) {
+                        const int j = jb >> 1, bb = jb & 1;
+                        const int xi = side ? 4 * ee + 2 * bb + l : 4 * ee + 2 * l + bb;
+                        const int yi = side ? 2 * j + i : 2 * i + j;
+                        const float* q = jr ? rec + prec_w(nd) + 2 * (4 * xi + yi) : rec + 2 * tri(xi, nm + yi, ncs);
+                        x[jb] = make_float2(q[0], side ? -q[1] : q[1]);
+                    }
+                    const float2* ge = G + (ee * na + o) * 4;
 #pragma unroll
-                    for (int bb = 0; bb < 2; ++bb) {
-                        const int x = side ? 4 * ee + 2 * bb + l : 4 * ee + 2 * l + bb;
-                        const int y = side ? 2 * j + i : 2 * i + j;
-                        double2 v;
-                        if (jr) {
-                            const float* q = rec + prec_w(nd) + 2 * (4 * x + y);
-                            v = make_double2(q[0], q[1]);
-                        } else {
-                            v = gram_at(rec, x, nm + y, ncs);
-                        }
-                        if (side) v = dconj(v);
-                        const double2 pr = dmul(d2(ge[2 * j + bb]), v);
+                    for (int jb = 0; jb < 4; ++jb) {
+                        const double2 pr = dmul(d2(ge[jb]), d2(x[jb]));
                         acc.x += pr.x; acc.y += pr.y;
                     }
+                }
             }
+            part[w * PNOUT + e] = acc;
         }
-        part[w * PNOUT + e] = acc;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nout; e += DT) {
@@ -491,69 +481,126 @@ __global__ void __launch_bounds__(DT) ddp_ant_kernel(DdArgs a, DdState st, int i
         }
         return;
     }
-    if (threadIdx.x == 0) {
-        bool fin = true;
-        for (int i = 0; i < nh + nn; ++i) fin = fin && isfinite(H[i].x) && isfinite(H[i].y);
-        bool ok = true;
-        // stacked gains of this antenna: Gs[i][2 d + l] = G^d[i][l]
-        auto gs = [&](int i, int cc) { return d2(G[((cc >> 1) * na + p) * 4 + 2 * i + (cc & 1)]); };
-        if (a.algo == WCAL_COHJONES) {
-            ok = fin && pchol_factor(H, n2);
-            if (ok)
-                for (int i = 0; i < 2; ++i) {
-                    // rows of G H = N: H x = conj(row i of N), row i of G = conj(x)
-                    for (int cc = 0; cc < n2; ++cc) X[i * n2 + cc] = dconj(N[i * n2 + cc]);
-                    pchol_subst(H, X + i * n2, X + i * n2, n2);
-                    for (int cc = 0; cc < n2; ++cc) X[i * n2 + cc] = dconj(X[i * n2 + cc]);
+    {
+        bool f = true;
+        for (int i = threadIdx.x; i < nh + nn; i += DT) f = f && isfinite(H[i].x) && isfinite(H[i].y);
+        if (!f) atomicOr(&s_bad, 1);
+    }
+    __syncthreads();
+    const bool fin = !(s_bad & 1);
+    // stacked gains of this antenna: Gs[i][2 d + l] = G^d[i][l]
+    auto gs = [&](int i, int cc) { return d2(G[((cc >> 1) * na + p) * 4 + 2 * i + (cc & 1)]); };
+    if (a.algo == WCAL_COHJONES) {
+        if (fin) {
+            for (int e = threadIdx.x; e < n2 * n2; e += DT) {
+                const int r = e / n2, c = e % n2;
+                S[e] = r <= c ? H[tri(r, c, n2)] : make_double2(0.0, 0.0);
+            }
+            for (int i = threadIdx.x; i < n2; i += DT) hdiag[i] = H[tri(i, i, n2)].x;
+            __syncthreads();
+            for (int i = 0; i < n2; ++i) {
+                const double piv = S[i * n2 + i].x;
+                if (!(piv > WCAL_EPS_PIVOT * hdiag[i]) || !isfinite(piv)) {   // same value in every thread
+                    if (threadIdx.x == 0) s_bad |= 2;
+                    break;
                 }
-        } else {
-            // AllJones: J^H r = N - G H, then G^d + (J^H r)^d (H^dd)^-1 per direction
-            for (int i = 0; i < 2; ++i)
-                for (int cc = 0; cc < n2; ++cc) {
-                    double2 v = N[i * n2 + cc];
-                    for (int c2 = 0; c2 < n2; ++c2) {
-                        const double2 pr = dmul(gs(i, c2), phget(H, c2, cc, n2));
+                const double rii = sqrt(piv);
+                __syncthreads();
+                for (int c = i + threadIdx.x; c < n2; c += DT) {
+                    const double2 v = S[i * n2 + c];
+                    S[i * n2 + c] = c == i ? make_double2(rii, 0.0) : make_double2(v.x / rii, v.y / rii);
+                }
+                __syncthreads();
+                // trailing triangle: S[r][c] -= conj(R[i][r]) R[i][c], i < r <= c
+                const int mrem = n2 - i - 1;
+                for (int e = threadIdx.x; e < mrem * (mrem + 1) / 2; e += DT) {
+                    int r = 0, q = e;
+                    while (q >= mrem - r) { q -= mrem - r; ++r; }
+                    const int rr = i + 1 + r, cc = rr + q;
+                    const double2 pr = dcmulc(S[i * n2 + rr], S[i * n2 + cc]);
+                    S[rr * n2 + cc].x -= pr.x;
+                    S[rr * n2 + cc].y -= pr.y;
+                }
+                __syncthreads();
+            }
+            __syncthreads();
+            if (!(s_bad & 2) && threadIdx.x < 2) {
+                // row i of G H = N: H x = conj(row i of N), row i of G = conj(x)
+                const int i = threadIdx.x;
+                double2* x = X + i * n2;
+                for (int r = 0; r < n2; ++r) {          // R^H z = conj(N_i)
+                    double2 v = dconj(N[i * n2 + r]);
+                    for (int q = 0; q < r; ++q) {
+                        const double2 pr = dcmulc(S[q * n2 + r], x[q]);
                         v.x -= pr.x; v.y -= pr.y;
                     }
-                    JR[i * n2 + cc] = v;
+                    const double d = S[r * n2 + r].x;
+                    x[r] = make_double2(v.x / d, v.y / d);
                 }
-            for (int d = 0; d < nd; ++d) {
-                const double z00 = H[tri(2 * d, 2 * d, n2)].x, z11 = H[tri(2 * d + 1, 2 * d + 1, n2)].x;
-                const double2 z01 = H[tri(2 * d, 2 * d + 1, n2)];
-                const double det = z00 * z11 - (z01.x * z01.x + z01.y * z01.y);
-                const bool sing = !(z00 > 0.0) || !(det > WCAL_EPS_PIVOT * z00 * z11);
-                for (int i = 0; i < 2; ++i) {
-                    const double2 j0 = JR[i * n2 + 2 * d], j1 = JR[i * n2 + 2 * d + 1];
-                    const double2 g0 = gs(i, 2 * d), g1 = gs(i, 2 * d + 1);
-                    if (sing || !fin) {
-                        X[i * n2 + 2 * d] = g0;
-                        X[i * n2 + 2 * d + 1] = g1;
-                        continue;
+                for (int r = n2 - 1; r >= 0; --r) {     // R x = z
+                    double2 v = x[r];
+                    for (int q = r + 1; q < n2; ++q) {
+                        const double2 pr = dmul(S[r * n2 + q], x[q]);
+                        v.x -= pr.x; v.y -= pr.y;
                     }
-                    // Z^-1 = [[z11, -z01], [-conj(z01), z00]] / det
-                    const double2 a0 = dmul(j1, dconj(z01)), a1 = dmul(j0, z01);
-                    X[i * n2 + 2 * d] = make_double2(g0.x + (j0.x * z11 - a0.x) / det, g0.y + (j0.y * z11 - a0.y) / det);
-                    X[i * n2 + 2 * d + 1] = make_double2(g1.x + (j1.x * z00 - a1.x) / det,
-                                                         g1.y + (j1.y * z00 - a1.y) / det);
+                    const double d = S[r * n2 + r].x;
+                    x[r] = make_double2(v.x / d, v.y / d);
                 }
-                if (sing) ok = false;
+                for (int r = 0; r < n2; ++r) x[r] = dconj(x[r]);
             }
         }
-        const bool avg = avg_step(it, a.schedule);
-        double dsum = 0.0, nsum = 0.0;
-        float2* gn = st.gn + (int64_t)k * nd * na * 4;
-        for (int d = 0; d < nd; ++d)
-            for (int i = 0; i < 2; ++i)
-                for (int l = 0; l < 2; ++l) {
-                    const double2 go = gs(i, 2 * d + l);
-                    double2 v = (a.algo == WCAL_COHJONES && !ok) ? go : X[i * n2 + 2 * d + l];
-                    if (avg) v = make_double2(0.5 * (go.x + v.x), 0.5 * (go.y + v.y));
-                    const float2 g = make_float2((float)v.x, (float)v.y);
-                    gn[(d * na + p) * 4 + 2 * i + l] = g;
-                    const double dr = (double)g.x - go.x, di = (double)g.y - go.y;
-                    dsum += dr * dr + di * di;
-                    nsum += (double)g.x * g.x + (double)g.y * g.y;
-                }
+    } else {
+        // AllJones: J^H r = N - G H, then G^d + (J^H r)^d (H^dd)^-1 per direction
+        for (int e = threadIdx.x; e < nn; e += DT) {
+            const int i = e / n2, cc = e % n2;
+            double2 v = N[e];
+            for (int c2 = 0; c2 < n2; ++c2) {
+                const double2 pr = dmul(gs(i, c2), phget(H, c2, cc, n2));
+                v.x -= pr.x; v.y -= pr.y;
+            }
+            JR[e] = v;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n2; e += DT) {
+            const int d = e >> 1, i = e & 1;
+            const double z00 = H[tri(2 * d, 2 * d, n2)].x, z11 = H[tri(2 * d + 1, 2 * d + 1, n2)].x;
+            const double2 z01 = H[tri(2 * d, 2 * d + 1, n2)];
+            const double det = z00 * z11 - (z01.x * z01.x + z01.y * z01.y);
+            const bool sing = !(z00 > 0.0) || !(det > WCAL_EPS_PIVOT * z00 * z11);
+            const double2 j0 = JR[i * n2 + 2 * d], j1 = JR[i * n2 + 2 * d + 1];
+            const double2 g0 = gs(i, 2 * d), g1 = gs(i, 2 * d + 1);
+            if (sing) atomicOr(&s_bad, 2);
+            if (sing || !fin) {
+                X[i * n2 + 2 * d] = g0;
+                X[i * n2 + 2 * d + 1] = g1;
+                continue;
+            }
+            // Z^-1 = [[z11, -z01], [-conj(z01), z00]] / det
+            const double2 a0 = dmul(j1, dconj(z01)), a1 = dmul(j0, z01);
+            X[i * n2 + 2 * d] = make_double2(g0.x + (j0.x * z11 - a0.x) / det, g0.y + (j0.y * z11 - a0.y) / det);
+            X[i * n2 + 2 * d + 1] = make_double2(g1.x + (j1.x * z00 - a1.x) / det, g1.y + (j1.y * z00 - a1.y) / det);
+        }
+    }
+    __syncthreads();
+    const bool ok = !(s_bad & 2);
+    const bool keep = a.algo == WCAL_COHJONES && (!ok || !fin);
+    const bool avg = avg_step(it, a.schedule);
+    double dsum = 0.0, nsum = 0.0;
+    float2* gn = st.gn + (int64_t)k * nd * na * 4;
+    for (int e = threadIdx.x; e < nn; e += DT) {
+        const int d = e >> 2, i = (e >> 1) & 1, l = e & 1;
+        const double2 go = gs(i, 2 * d + l);
+        double2 v = keep ? go : X[i * n2 + 2 * d + l];
+        if (avg) v = make_double2(0.5 * (go.x + v.x), 0.5 * (go.y + v.y));
+        const float2 g = make_float2((float)v.x, (float)v.y);
+        gn[(d * na + p) * 4 + 2 * i + l] = g;
+        const double dr = (double)g.x - go.x, di = (double)g.y - go.y;
+        dsum += dr * dr + di * di;
+        nsum += (double)g.x * g.x + (double)g.y * g.y;
+    }
+    dsum = block_sum(dsum, red);
+    nsum = block_sum(nsum, red);
+    if (threadIdx.x == 0) {
         st.ant_d[(int64_t)k * na + p] = dsum;
         st.ant_n[(int64_t)k * na + p] = nsum;
         st.ant_f[(int64_t)k * na + p] = (fin ? 0 : 1) | (ok ? 0 : 2);

@@ -227,14 +227,19 @@ def pol_di(n_ant: int, ns: Sequence[int], sigma: float = 0.01, leak: float = 0.1
 
 def pol_dd(n_ant: int, ns: Sequence[int], n_dir: int, sigma: float = 0.03, leak: float = 0.1,
            seed: int = 0, flag_frac: float = 0.0, device="cpu", dtype=torch.complex64,
-           noise: bool = True) -> Problem:
+           noise: bool = True, pairs=None) -> Problem:
     """Polarized direction-dependent problem (Sect. 4.4) with the 2x2 recipe of pol_di per
     direction: G^d_p = [[g_x, l_xy], [l_yx, g_y]], g drawn as in scalar_di, leakages
     CN(0, leak^2); every 2x2 entry of every M^d is CN(0, 1) i.i.d. (generic coherencies,
     so the only gauge is one phase per direction); D = sum_d G^d_p M^d G^{dH}_q plus
-    CN(0, sigma^2) per correlation."""
+    CN(0, sigma^2) per correlation.  pairs = (ant1, ant2) replaces the table of all p < q
+    (pairs may repeat)."""
     gen = _gen(SEED_BASE * 16 + 6 + 7919 * seed, device)
-    ant1, ant2 = baselines(n_ant, device)
+    if pairs is None:
+        ant1, ant2 = baselines(n_ant, device)
+    else:
+        ant1 = torch.as_tensor(pairs[0], dtype=torch.int32, device=device)
+        ant2 = torch.as_tensor(pairs[1], dtype=torch.int32, device=device)
     ns = torch.as_tensor(list(ns), dtype=torch.int64)
     n_int = ns.numel()
     rows = int(ns.sum()) * ant1.numel()

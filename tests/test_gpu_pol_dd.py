@@ -188,6 +188,26 @@ def test_pol_dd_garbage_under_flags_is_bit_identical():
         assert torch.all(b["residual"][fl] == 0)
 
 
+@pytest.mark.parametrize("algo", ["cohjones", "alljones"])
+def test_pol_dd_antenna_with_many_rows(algo):
+    """Repeated baseline pairs give antenna 0 more rows than the per-antenna update stages
+    at once (256): lockstep parity with the oracle."""
+    log(f"[pol dd many rows] algo={algo}")
+    a1 = [0] * 140 + [0] * 130 + [1, 1, 2, 0]
+    a2 = [1] * 140 + [2] * 130 + [2, 3, 3, 3]
+    P = synth.pol_dd(4, [3, 2], 2, seed=8, device=DEV, flag_frac=0.05, pairs=(a1, a2))
+    plan = wcal.plan_for(P, algo=algo, tol=0.0, max_iter=4)
+    out = plan.solve(P.data, P.model, P.flags, unit(P))
+    torch.cuda.synchronize()
+    g = out["gains"].cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.solve(P, k, unit(P)[k].cpu().numpy(), algo=algo, tol=0.0, max_iter=4)
+        go = glue.gains_from_oracle(o["g"], 4, 2, algo)
+        e = rel(g[k], go)
+        log(f"  interval {k}: err={e:.2e}")
+        assert e <= 1e-5, (k, e)
+
+
 def test_pol_dd_nd1_matches_pol_stefcal():
     """One direction: polarized CohJones and AllJones are polarized StefCal."""
     log("[pol dd nd1]")
