@@ -71,8 +71,10 @@ typedef struct { float re, im; } wcal_c64;
 
 /* algorithms */
 #define WCAL_STEFCAL   0   /* n_dir == 1; n_corr 1 or 4                     (Sect. 3.1, 4.3)   */
-#define WCAL_COHJONES  1   /* n_corr == 1; per-antenna Nd x Nd blocks        (Sect. 3.2.2)      */
-#define WCAL_ALLJONES  2   /* n_corr == 1; fully diagonal, residual form     (Sect. 3.2.3)      */
+#define WCAL_COHJONES  1   /* per-antenna Nd x Nd blocks (Sect. 3.2.2); n_corr 4: 2Nd x 2Nd     */
+                           /* blocks of the polarized case (Sect. 4.4), Nd <= 10, FP32 only     */
+#define WCAL_ALLJONES  2   /* fully diagonal, residual form (Sect. 3.2.3; n_corr 4: per-direction*/
+                           /* 2x2 blocks, Eq. update:DD:diag:pol), same limits as CohJones      */
 
 /* update schedules: update k = 0, 1, ... from the starting gains either applies the
  * GN value (Eq. stefcal / its block forms) or the lambda = 1 LM average
@@ -203,8 +205,12 @@ void wcal_graph_destroy(wcal_graph* graph);   /* NULL is a no-op */
  *   jhj  [n_int][n_ant][blk]  scalar: blk = 1 (A_p, imaginary part 0; Eq. JHJ:DI:tfw);
  *                             2x2: blk = 4, Z_p = sum Y Y^H (Eq. JHJ:pol diagonal);
  *                             DD:  blk = n_dir * n_dir, H_p[c][d] = sum conj(y^c) y^d
- *                             (Eq. JHJ:DD:unpol diagonal blocks)
- *   jhd  [n_int][n_ant][n_dir * n_corr]  J^H D (scalar/DD: sum conj(y) d; 2x2: sum D Y^H)
+ *                             (Eq. JHJ:DD:unpol diagonal blocks);
+ *                             2x2 DD: blk = (2 n_dir)^2, H_p = sum Ys Ys^H with Ys the 2Nd x 2
+ *                             stack of Y^d = M^d G^{dH}_q (row 2d + k = row k of Y^d); the
+ *                             operator block of Eq. JHJ:DD:pol is I_2 (x) H_p
+ *   jhd  [n_int][n_ant][n_dir * n_corr]  J^H D (scalar/DD: sum conj(y) d; 2x2: sum D Y^H;
+ *                                        2x2 DD: sum D Y^{dH} per direction, row-major)
  *   jhr  [n_int][n_ant][n_dir * n_corr]  J^H r (same with r in place of d)
  *   count [n_int][n_ant] int32, chi2 [n_int] (FP64), residual [rows][n_corr] or NULL. */
 int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
