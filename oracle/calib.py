@@ -448,6 +448,101 @@ def alljones_2x2(D, M, p, q, flags, G0, tol=1e-6, max_iter=200, schedule=AVG_FIR
                   D, M, p, q, flags, G0, tol, max_iter, schedule)
 
 
+# ------------------------------------------------------------------ smoothing (Sect. 3.4)
+def smoothing_kernel(sigma):
+    """1-D taps w(j) = exp(-j^2 / (2 sigma^2)) for |j| <= ceil(3 sigma) (reading: truncated at
+    three widths; sigma = 0 is the delta kernel, no smoothing).  Returns (taps, radius)."""
+    if sigma <= 0:
+        return np.ones(1), 0
+    r = int(np.ceil(3.0 * sigma))
+    j = np.arange(-r, r + 1)
+    return np.exp(-j * j / (2.0 * sigma * sigma)), r
+
+
+def smooth_grid(x, sigma_t, sigma_f):
+    """(w o x)(t0, f0) = sum over grid cells (t, f) of w(t - t0, f - f0) x(t, f) for x
+    [n_time, n_chan, ...], w the product of the time and frequency kernels; cells beyond the
+    grid edge are absent from the sum (Eq. JHJ:diag:smooth, written as its definition: one
+    shifted slice per kernel tap)."""
+    kt, rt = smoothing_kernel(sigma_t)
+    kf, rf = smoothing_kernel(sigma_f)
+    nt, nf = x.shape[:2]
+    out = np.zeros_like(x)
+    # offsets beyond the grid's extent reach no cell
+    for dt in range(-min(rt, nt - 1), min(rt, nt - 1) + 1):
+        for df in range(-min(rf, nf - 1), min(rf, nf - 1) + 1):
+            w = kt[dt + rt] * kf[df + rf]
+            # out[t0, f0] += w * x[t0 + dt, f0 + df] where both are on the grid
+            t0a, t0b = max(0, -dt), min(nt, nt - dt)
+            f0a, f0b = max(0, -df), min(nf, nf - df)
+            if t0a >= t0b or f0a >= f0b:
+                continue
+            out[t0a:t0b, f0a:f0b] += w * x[t0a + dt:t0b + dt, f0a + df:f0b + df]
+    return out
+
+
+def accumulate_cells(d, m, p, q, cell, flags, g, n_cells):
+    """alpha_p(t, nu) = sum_q conj(y) d and beta_p(t, nu) = sum_q |y|^2 per cell (Sect. 3.4: the
+    accumulators of Eqs. JHJ:DI:tfw, JHR:DI:tfw without the sum over samples), with
+    y_pq = m conj(g_q) at the row's own cell and both sides of every row (Eq. JJ:di).
+    g [n_cells, Na]; returns alpha [n_cells, Na] complex, beta [n_cells, Na] real."""
+    na = g.shape[1]
+    k = _keep(flags, d.shape[0])
+    d, m, p, q, cell = d[k], m[k], p[k], q[k], cell[k]
+    y_pq = m * np.conj(g[cell, q])
+    y_qp = np.conj(m) * np.conj(g[cell, p])
+    alpha = np.zeros(n_cells * na, dtype=np.complex128)
+    beta = np.zeros(n_cells * na)
+    _scatter(alpha, cell * na + p, np.conj(y_pq) * d)
+    _scatter(alpha, cell * na + q, np.conj(y_qp) * np.conj(d))
+    _scatter(beta, cell * na + p, np.abs(y_pq) ** 2)
+    _scatter(beta, cell * na + q, np.abs(y_qp) ** 2)
+    return alpha.reshape(n_cells, na), beta.reshape(n_cells, na)
+
+
+def stefcal_smooth(d, m, p, q, cell, flags, g0, n_time, n_chan, sigma_t, sigma_f, tol=1e-6,
+                   max_iter=100, schedule=AVG_FIRST):
+    """StefCal with time/frequency smoothing (Sect. 3.4) over one chunk of n_time x n_chan
+    cells (cell = t * n_chan + nu of each row): every update takes the per-cell GN value
+    g_p(t, nu) = (w o alpha_p) / (w o beta_p) (Eq. JHJ:diag:smooth), then the schedule of
+    Sect. 3.1.  Convergence (reading; the paper does not test it): the relative change over
+    every cell and antenna of the chunk after removing the best common phase between the
+    two iterates.  The smoothed update is not the step of a least-squares objective: with
+    noise it settles into a rigid rotation of every cell's gains by one phase per update,
+    a motion along the gauge that the plain relative change would never see stop.  A cell
+    whose smoothed beta_p is not positive keeps its gain (SINGULAR_ANT).  g0 [n_cells, Na]."""
+    n_cells = n_time * n_chan
+    g = np.array(g0, dtype=np.complex128, copy=True)
+    na = g.shape[1]
+    status, n_iter, hist = 0, 0, []
+    kr = _keep(flags, d.shape[0])
+    if not (np.all(np.isfinite(d[kr])) and np.all(np.isfinite(m[kr]))):
+        status |= NONFINITE
+    else:
+        for k in range(max_iter):
+            alpha, beta = accumulate_cells(d, m, p, q, cell, flags, g, n_cells)
+            sa = smooth_grid(alpha.reshape(n_time, n_chan, na), sigma_t, sigma_f).reshape(n_cells, na)
+            sb = smooth_grid(beta.reshape(n_time, n_chan, na), sigma_t, sigma_f).reshape(n_cells, na)
+            sing = ~(sb > 0)
+            if np.any(sing):
+                status |= SINGULAR_ANT
+            ghat = np.where(sing, g, sa / np.where(sing, 1.0, sb))
+            g_new = 0.5 * (g + ghat) if _is_average_step(k, schedule) else ghat
+            rel = rel_change(align_phase(g_new, g), g)
+            hist.append(rel)
+            g = g_new
+            n_iter = k + 1
+            if rel < tol:
+                status |= CONVERGED
+                break
+        else:
+            status |= MAXITER
+    r = np.zeros_like(d, dtype=np.complex128)
+    r[kr] = d[kr] - g[cell[kr], p[kr]] * m[kr] * np.conj(g[cell[kr], q[kr]])
+    return dict(g=g, n_iter=n_iter, status=status, residual=r, chi2=float(np.sum(np.abs(r[kr]) ** 2)),
+                history=hist)
+
+
 # ------------------------------------------------------------------ gauge
 def align_phase(g, ref):
     """g * exp(i phi) with phi = arg sum conj(g) ref: the least-squares global phase

@@ -582,6 +582,117 @@ def test_p9_pol_dd_orientation_swap_and_flags():
         assert np.all(c["residual"][fl] == 0) and c["chi2"] == e["chi2"]
 
 
+# ------------------------------------------------------------------ smoothing (Sect. 3.4)
+def _cells(na=6, nt=3, nf=5, sigma=0.0, g=None):
+    """Rows of one chunk of nt x nf cells, cell-major (row = cell * n_bl + b)."""
+    p, q = np.triu_indices(na, 1)
+    nbl, nc = p.size, nt * nf
+    P, Q = np.tile(p, nc), np.tile(q, nc)
+    cell = np.repeat(np.arange(nc), nbl)
+    m = cn(P.size)
+    if g is None:
+        g = np.exp(0.1 * rng.standard_normal(na)) * np.exp(1j * rng.uniform(-np.pi, np.pi, na))
+    G = np.broadcast_to(g, (nc, na)) if g.ndim == 1 else g
+    d = G[cell, P] * m * np.conj(G[cell, Q]) + sigma * cn(P.size)
+    return d, m, P, Q, cell, np.array(G)
+
+
+def test_smooth_delta_kernel_is_per_cell_stefcal():
+    """sigma = 0: the kernel is a delta and every cell is its own StefCal problem."""
+    na, nt, nf = 6, 2, 3
+    d, m, p, q, cell, _ = _cells(na, nt, nf, sigma=0.1)
+    g0 = np.ones((nt * nf, na), complex)
+    out = oc.stefcal_smooth(d, m, p, q, cell, None, g0, nt, nf, 0.0, 0.0, tol=0, max_iter=9)
+    for c in range(nt * nf):
+        k = cell == c
+        o = oc.stefcal_scalar(d[k], m[k], p[k], q[k], None, np.ones(na, complex), tol=0, max_iter=9)
+        assert np.allclose(out["g"][c], o["g"], rtol=1e-12)
+
+
+def test_smooth_wide_kernel_is_chunk_stefcal():
+    """A kernel flat over the grid makes every cell's update the chunk's StefCal update
+    (all cells start equal and stay equal)."""
+    na, nt, nf = 6, 3, 4
+    d, m, p, q, cell, _ = _cells(na, nt, nf, sigma=0.1)
+    g0 = np.ones((nt * nf, na), complex)
+    out = oc.stefcal_smooth(d, m, p, q, cell, None, g0, nt, nf, 1e7, 1e7, tol=0, max_iter=9)
+    o = oc.stefcal_scalar(d, m, p, q, None, np.ones(na, complex), tol=0, max_iter=9)
+    for c in range(nt * nf):
+        assert np.allclose(out["g"][c], o["g"], rtol=1e-9)
+
+
+def test_smooth_update_is_the_weighted_ls_sum():
+    """One GN update equals Eq. stefcal:w evaluated by brute force: for every cell (t0, f0)
+    and antenna, sums over all rows weighted by w(t - t0, f - f0), both sides of each row."""
+    na, nt, nf, st, sf = 4, 3, 5, 0.8, 1.3
+    d, m, p, q, cell, _ = _cells(na, nt, nf, sigma=0.2)
+    g = cn(nt * nf, na) + 1.0
+    out = oc.stefcal_smooth(d, m, p, q, cell, None, g, nt, nf, st, sf, tol=0, max_iter=1,
+                            schedule=oc.GN_ONLY)
+
+    def w(dt, df):
+        rt, rf = int(np.ceil(3 * st)), int(np.ceil(3 * sf))
+        if abs(dt) > rt or abs(df) > rf:
+            return 0.0
+        return np.exp(-dt * dt / (2 * st * st)) * np.exp(-df * df / (2 * sf * sf))
+    for c0 in range(nt * nf):
+        t0, f0 = divmod(c0, nf)
+        num = np.zeros(na, complex)
+        den = np.zeros(na)
+        for r in range(d.size):
+            t, f = divmod(int(cell[r]), nf)
+            wt = w(t - t0, f - f0)
+            a, b, c = p[r], q[r], int(cell[r])
+            y = m[r] * np.conj(g[c, b])               # row pq, antenna a
+            num[a] += wt * np.conj(y) * d[r]
+            den[a] += wt * abs(y) ** 2
+            y2 = np.conj(m[r]) * np.conj(g[c, a])     # row qp, antenna b
+            num[b] += wt * np.conj(y2) * np.conj(d[r])
+            den[b] += wt * abs(y2) ** 2
+        assert np.allclose(out["g"][c0], num / den, rtol=1e-12)
+
+
+def test_smooth_noise_free_constant_gains():
+    """Gains constant over the chunk are a fixed point of the smoothed update; from unit
+    gains the iteration reaches them up to one global phase."""
+    na, nt, nf = 7, 2, 6
+    d, m, p, q, cell, G = _cells(na, nt, nf, sigma=0.0)
+    out = oc.stefcal_smooth(d, m, p, q, cell, None, np.ones((nt * nf, na), complex), nt, nf, 1.0, 2.0,
+                            tol=1e-14, max_iter=500)
+    assert out["status"] & oc.CONVERGED
+    assert oc.rel_err(oc.align_phase(out["g"], G), G) < 1e-10
+
+
+def test_smooth_iterates_rotate_rigidly_along_the_gauge():
+    """With noise the smoothed update settles into one common phase step per update for
+    every cell: removing a single phase leaves a change three orders of magnitude below the raw
+    one, which is why convergence is measured modulo the common phase."""
+    na, nt, nf = 8, 1, 40
+    d, m, p, q, cell, _ = _cells(na, nt, nf, sigma=0.4)
+    a = oc.stefcal_smooth(d, m, p, q, cell, None, np.ones((nf, na), complex), nt, nf, 0.0, 3.0,
+                          tol=0, max_iter=400)
+    b = oc.stefcal_smooth(d, m, p, q, cell, None, a["g"], nt, nf, 0.0, 3.0, tol=0, max_iter=2)
+    raw = oc.rel_err(b["g"], a["g"])
+    aligned = oc.rel_err(oc.align_phase(b["g"], a["g"]), a["g"])
+    assert raw > 1e-5 and aligned < 1e-3 * raw, (raw, aligned)
+
+
+def test_smooth_lowers_the_error_of_noisy_solutions():
+    """Low SNR, gains constant across channels: smoothing over channels gives solutions
+    closer to the truth than solving every channel alone (the motivation of Sect. 3.4)."""
+    na, nt, nf = 8, 1, 40
+    d, m, p, q, cell, G = _cells(na, nt, nf, sigma=0.4)
+    errs = {}
+    for sf in (0.0, 3.0):
+        out = oc.stefcal_smooth(d, m, p, q, cell, None, np.ones((nf, na), complex), nt, nf, 0.0, sf,
+                                tol=1e-6, max_iter=1000)
+        assert out["status"] & oc.CONVERGED
+        # per-cell phase gauge: align each channel separately
+        e = [oc.rel_err(oc.align_phase(out["g"][c], G[c]), G[c]) for c in range(nf)]
+        errs[sf] = float(np.mean(e))
+    assert errs[3.0] < 0.6 * errs[0.0], errs
+
+
 # ------------------------------------------------------------------ P11 GN alone oscillates
 def test_p11_gn_only_oscillates():
     """Sect. 3.1: plain GN converges very slowly (oscillates); the GN / average
