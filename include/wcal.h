@@ -224,6 +224,33 @@ int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                   const uint8_t* flags, const wcal_c64* gains, wcal_c64* residual,
                   double* chi2, void* stream);
 
+/* Time/frequency smoothing of scalar StefCal (Sect. 3.4, Eq. JHJ:diag:smooth).  Every
+ * sample of an interval becomes a cell (t, nu) of an n_time x n_chan grid, sample
+ * s = t * n_chan + nu, with gains of its own; every update takes
+ *     g_p(t, nu) = (w o alpha_p)(t, nu) / (w o beta_p)(t, nu),
+ * alpha_p = sum_q conj(y) d and beta_p = sum_q |y|^2 per cell (y formed with the gains of the
+ * row's own cell), w(t, nu) = exp(-t^2 / 2 sigma_t^2 - nu^2 / 2 sigma_f^2) truncated at
+ * |t| <= ceil(3 sigma_t), |nu| <= ceil(3 sigma_f) (sigma 0: no smoothing along that axis),
+ * cells beyond the grid edge absent from both sums; then the plan's schedule.  Convergence
+ * per interval: relative change over its cells and antennas after removing, per cell, the
+ * best phase between successive iterates (each cell's solution is defined up to its own
+ * phase, and the smoothed iterates keep turning along these phases).  A cell whose smoothed
+ * beta is not positive keeps its gain (SINGULAR_ANT).
+ *
+ * wcal_plan_smoothing prepares a scalar StefCal plan in PASS mode whose intervals all hold
+ * n_time * n_chan samples: it validates, builds the per-cell tables and allocates the
+ * scratch (synchronous; calling it again replaces the previous setting).  Errors:
+ * WCAL_EINVAL (wrong plan kind, n_time or n_chan < 1, negative or non-finite sigma),
+ * WCAL_ESHAPE (an interval of another size, kernel radius above 4096 cells), WCAL_ENOMEM.
+ *
+ * wcal_solve_smooth then solves every interval with smoothing.  gains in/out
+ * [n_int][n_time * n_chan][n_ant] (per cell), residual [rows] or NULL, n_iter, status and
+ * chi2 [n_int] per interval (chi2 may be NULL).  No allocation, no host synchronisation. */
+int wcal_plan_smoothing(wcal_plan* plan, int32_t n_time, int32_t n_chan, double sigma_t, double sigma_f);
+int wcal_solve_smooth(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
+                      wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
+                      void* stream);
+
 /* Kernel timing for benchmarks.  While enabled, every kernel launched by wcal_solve and
  * wcal_residual on this plan is bracketed by HIP events on the call's stream.
  * wcal_profile_read waits for those events and returns, per kernel class, the summed

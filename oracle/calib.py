@@ -506,11 +506,13 @@ def stefcal_smooth(d, m, p, q, cell, flags, g0, n_time, n_chan, sigma_t, sigma_f
     cells (cell = t * n_chan + nu of each row): every update takes the per-cell GN value
     g_p(t, nu) = (w o alpha_p) / (w o beta_p) (Eq. JHJ:diag:smooth), then the schedule of
     Sect. 3.1.  Convergence (reading; the paper does not test it): the relative change over
-    every cell and antenna of the chunk after removing the best common phase between the
-    two iterates.  The smoothed update is not the step of a least-squares objective: with
-    noise it settles into a rigid rotation of every cell's gains by one phase per update,
-    a motion along the gauge that the plain relative change would never see stop.  A cell
-    whose smoothed beta_p is not positive keeps its gain (SINGULAR_ANT).  g0 [n_cells, Na]."""
+    every cell and antenna of the chunk after removing, per cell, the best phase between the
+    two iterates.  Each cell's solution answers its own weighted least-squares problem
+    (Eq. cal:DI:smooth), defined up to one phase per cell, and the smoothed update is not
+    the step of one objective: with noise its iterates keep turning along these phases
+    (rigidly, by one common phase per update, when the gains are constant over the chunk),
+    a motion the plain relative change would never see stop.  A cell whose smoothed beta_p
+    is not positive keeps its gain (SINGULAR_ANT).  g0 [n_cells, Na]."""
     n_cells = n_time * n_chan
     g = np.array(g0, dtype=np.complex128, copy=True)
     na = g.shape[1]
@@ -528,7 +530,8 @@ def stefcal_smooth(d, m, p, q, cell, flags, g0, n_time, n_chan, sigma_t, sigma_f
                 status |= SINGULAR_ANT
             ghat = np.where(sing, g, sa / np.where(sing, 1.0, sb))
             g_new = 0.5 * (g + ghat) if _is_average_step(k, schedule) else ghat
-            rel = rel_change(align_phase(g_new, g), g)
+            aligned = np.stack([align_phase(g_new[c], g[c]) for c in range(n_cells)])
+            rel = rel_change(aligned, g)
             hist.append(rel)
             g = g_new
             n_iter = k + 1

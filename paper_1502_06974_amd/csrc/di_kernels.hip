@@ -1072,6 +1072,50 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
     return hipGetLastError();
 }
 
+// Scalar pass of update `it` that leaves the per-tile per-antenna sums in a.partial and
+// applies no update: the triangle pass over the triangle tiles when the plan uses it, else
+// the tiled pass.  Launches are timed on prof_plan's profiler.  Tiles are listed as the update kernels list them (all tiles for it = 0,
+// a.lists / a.ctr after that).  Used by the smoothed solve, whose update needs the sums of
+// neighbouring cells.
+hipError_t launch_di_pass_partials(const wcal_plan* plan, const wcal_plan* prof_plan, const DiArgs& a, int it,
+                                   hipStream_t s) {
+    const int na = plan->prob.n_ant;
+    prof_begin(prof_plan, WCAL_K_PASS, s);
+    if (plan->tri) {
+        DiArgs at = a;
+        at.tiles = plan->d_ttiles;
+        at.tile_off = plan->d_ttile_off;
+        at.ntiles = plan->nttiles;
+        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TB / WAVE) * (na + 1) * 3 * sizeof(float);
+        const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_tri_pass_kernel<false>), TB, ps, at.ntiles);
+        hipLaunchKernelGGL(di_tri_pass_kernel<false>, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
+    } else {
+        const size_t ps = pass_smem(na, 1);
+        const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_pass_kernel<1>), TB, ps, a.ntiles);
+        hipLaunchKernelGGL(di_pass_kernel<1>, dim3(gp), dim3(TB), ps, s, a, it);
+    }
+    prof_end(prof_plan, WCAL_K_PASS, s);
+    return hipGetLastError();
+}
+
+// The tile table launch_di_pass_partials works on: interval k owns tiles
+// [off[k], off[k + 1]) of it.
+const int32_t* di_pass_tile_off(const wcal_plan* plan) { return plan->tri ? plan->d_ttile_off : plan->d_tile_off; }
+int32_t di_pass_ntiles(const wcal_plan* plan) { return plan->tri ? plan->nttiles : plan->ntiles; }
+
+// Scalar residual rows of every tile with gains a.gains_in, chi^2 per tile in a.chi_part
+// (the sums per interval are left to the caller).
+hipError_t launch_di_resid_tiles(const wcal_plan* plan, const wcal_plan* prof_plan, const DiArgs& a, hipStream_t s) {
+    const int na = plan->prob.n_ant;
+    hipLaunchKernelGGL(di_zero_ctr_kernel, dim3((2 * (a.max_iter + 2) + TB - 1) / TB), dim3(TB), 0, s, a);
+    const size_t rs = (size_t)na * sizeof(float2);
+    const int gr = grid_resident(plan, reinterpret_cast<const void*>(di_resid_kernel<1>), TB, rs, a.ntiles);
+    prof_begin(prof_plan, WCAL_K_RESID, s);
+    hipLaunchKernelGGL(di_resid_kernel<1>, dim3(gr), dim3(TB), rs, s, a);
+    prof_end(prof_plan, WCAL_K_RESID, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_di_solve(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
     return plan->prob.n_corr == 1 ? solve_nc<1>(plan, a, s) : solve_nc<4>(plan, a, s);
 }

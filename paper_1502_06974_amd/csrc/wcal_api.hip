@@ -379,6 +379,8 @@ void wcal_plan_destroy(wcal_plan* plan) {
     if (!plan) return;
     wcal_profile_enable(plan, 0);
     (void)hipSetDevice(plan->device);
+    smooth_free(plan->smooth);
+    plan->smooth = nullptr;
     for (void* p : {(void*)plan->d_ant1, (void*)plan->d_ant2, (void*)plan->d_row_off, (void*)plan->d_ns,
                     (void*)plan->d_order, (void*)plan->d_queue, (void*)plan->d_stats, (void*)plan->d_tiles,
                     (void*)plan->d_tile_off, (void*)plan->d_stiles, (void*)plan->d_lists, (void*)plan->d_ctr,
@@ -424,6 +426,8 @@ static void fill_tables_di(const wcal_plan* plan, DiArgs& a) {
     a.schedule = plan->prob.schedule;
     a.tol = plan->prob.tol;
 }
+
+extern "C++" void fill_di_args(const wcal_plan* plan, DiArgs& a) { fill_tables_di(plan, a); }
 
 static void fill_tables_dd(const wcal_plan* plan, DdArgs& a) {
     a.ant1 = plan->d_ant1;

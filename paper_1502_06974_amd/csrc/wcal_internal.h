@@ -72,6 +72,8 @@ struct wcal_plan {
     int32_t* d_ttile_off = nullptr;
     int32_t nttiles = 0;
     Profiler* prof = nullptr;     // non-null while timing is enabled
+    // time/frequency smoothing (scalar StefCal): the cell plan and its scratch, or null
+    struct SmoothPlan* smooth = nullptr;
 };
 
 // record the message returned by wcal_last_error() and return `code`
@@ -170,3 +172,12 @@ int ddp_max_dir();
 const char* ddp_pass_kernel_name(int nd);
 
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
+
+// pieces of the scalar solve reused by the smoothed solve
+void fill_di_args(const wcal_plan* plan, DiArgs& a);
+hipError_t launch_di_pass_partials(const wcal_plan* plan, const wcal_plan* prof_plan, const DiArgs& a, int it,
+                                   hipStream_t s);
+const int32_t* di_pass_tile_off(const wcal_plan* plan);
+int32_t di_pass_ntiles(const wcal_plan* plan);
+hipError_t launch_di_resid_tiles(const wcal_plan* plan, const wcal_plan* prof_plan, const DiArgs& a, hipStream_t s);
+void smooth_free(struct SmoothPlan* sp);

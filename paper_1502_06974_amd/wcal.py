@@ -34,7 +34,7 @@ EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_des
            "wcal_profile_enable", "wcal_profile_read", "wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains",
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
-           "wcal_mlp_gradients", "wcal_mlp_train_step")
+           "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth")
 K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
@@ -88,6 +88,10 @@ def lib() -> C.CDLL:
     L.wcal_accumulate.restype = C.c_int
     L.wcal_residual.argtypes = [vp] * 8
     L.wcal_residual.restype = C.c_int
+    L.wcal_plan_smoothing.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double]
+    L.wcal_plan_smoothing.restype = C.c_int
+    L.wcal_solve_smooth.argtypes = [vp] * 10
+    L.wcal_solve_smooth.restype = C.c_int
     L.wcal_profile_enable.argtypes = [vp, C.c_int]
     L.wcal_profile_enable.restype = C.c_int
     L.wcal_profile_read.argtypes = [vp, vp, vp]
@@ -110,7 +114,7 @@ def lib() -> C.CDLL:
     L.wcal_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp, vp]
     for f in ("wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains", "wcal_gains_to_bins", "wcal_reset_unconverged",
               "wcal_mlp_create", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
-              "wcal_mlp_gradients", "wcal_mlp_train_step"):
+              "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -273,6 +277,35 @@ class Plan:
                                      _ptr(jhj), _ptr(jhd), _ptr(jhr), _ptr(count), _ptr(chi2),
                                      _ptr(residual), self._stream(stream)))
         return dict(jhj=jhj, jhd=jhd, jhr=jhr, count=count, chi2=chi2, residual=residual)
+
+    def smoothing(self, n_time: int, n_chan: int, sigma_t: float, sigma_f: float):
+        """wcal_plan_smoothing: every sample of an interval becomes a cell of an n_time x n_chan
+        grid with its own gains, smoothed by a Gaussian of widths sigma_t, sigma_f cells."""
+        _check(lib().wcal_plan_smoothing(self._h, int(n_time), int(n_chan), float(sigma_t), float(sigma_f)))
+        self.smooth_cells = int(n_time) * int(n_chan)
+
+    def solve_smooth(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
+                     chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True):
+        """wcal_solve_smooth: gains [n_int][cells][n_ant] (complex64) are updated in place."""
+        R = self.rows
+        self._dev(data, "data", torch.complex64, (R, 1))
+        self._dev(model, "model", torch.complex64, (R, 1, 1))
+        if flags is not None:
+            self._dev(flags, "flags", torch.uint8, (R,))
+        self._dev(gains, "gains", torch.complex64, (self.n_int, self.smooth_cells, self.n_ant))
+        dev = gains.device
+        if residual is None and want_residual:
+            residual = torch.empty_like(data)
+        if n_iter is None:
+            n_iter = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if chi2 is None and want_chi2:
+            chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
+        self._dev(residual, "residual", torch.complex64, (R, 1))
+        _check(lib().wcal_solve_smooth(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains), _ptr(residual),
+                                       _ptr(n_iter), _ptr(status), _ptr(chi2), self._stream(stream)))
+        return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
     def residual(self, data, model, flags, gains, residual=None, stream=None):
         """wcal_residual: R = D - sum_d G_p M G_q^H and chi^2 per interval."""
