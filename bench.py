@@ -109,6 +109,28 @@ def cpu_baseline_dd(P, budget_s: float = 15.0):
                 seconds=round(dt, 2))
 
 
+def cpu_baseline_smooth(P, smooth, n_chan: int = 16):
+    """CPU oracle StefCal with smoothing on the first n_chan cells of the 1 x n_int grid."""
+    import numpy as np
+    from oracle import calib as oc
+    nbl = P.n_bl
+    rows = slice(0, n_chan * nbl)
+    d = P.data[rows, 0].cpu().numpy().astype(np.complex128)
+    m = P.model[rows, 0, 0].cpu().numpy().astype(np.complex128)
+    p = np.tile(P.ant1.cpu().numpy(), n_chan)
+    q = np.tile(P.ant2.cpu().numpy(), n_chan)
+    fl = None if P.flags is None else P.flags[rows].cpu().numpy() != 0
+    cell = np.repeat(np.arange(n_chan), nbl)
+    t0 = time.perf_counter()
+    o = oc.stefcal_smooth(d, m, p, q, cell, fl, np.ones((n_chan, P.n_ant), complex), 1, n_chan, smooth[0],
+                          smooth[1], tol=1e-6, max_iter=100)
+    dt = time.perf_counter() - t0
+    return dict(value=n_chan * nbl * o["n_iter"] / dt, unit="vis-iter/s", cores=1, kind="oracle",
+                sample=f"StefCal with smoothing on the first {n_chan} channels x {nbl} baselines of the grid, "
+                       f"unit start, tol 1e-6, {o['n_iter']} updates, one process",
+                seconds=round(dt, 2))
+
+
 def cpu_baseline(P, budget_s: float = 15.0):
     """Time the CPU oracle (as it stands) on whole intervals of the workload until about
     budget_s seconds of CPU work; report visibility-iterations per second."""
@@ -146,7 +168,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pol2x2_na64")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--max-iter", type=int, default=100)
+    ap.add_argument("--max-iter", type=int, default=None,
+                    help="update cap (default 100; 300 with --smooth, whose updates converge slower)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--mode", default="pass", choices=["pass", "stats"],
@@ -160,11 +183,16 @@ def main():
                     help="CohJones Gram products: FP32 MFMA, or BF16 MFMA with FP32 accumulation")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager wcal_solve calls instead of replays of a captured HIP graph")
+    ap.add_argument("--smooth", default=None, metavar="SIGMA_T,SIGMA_F",
+                    help="StefCal with time/frequency smoothing (Sect. 3.4): a workload of one-sample "
+                         "intervals is taken as one 1 x n_int grid of cells, smoothed with these widths")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(a known-size reference for hardware byte counters)")
     args = ap.parse_args()
 
+    if args.max_iter is None:
+        args.max_iter = 300 if args.smooth else 100
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
               "(solution intervals are independent; see the sharding notes in DESIGN.md)",
@@ -182,9 +210,20 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] rows={P.n_rows} intervals={P.n_int} n_ant={P.n_ant} n_corr={P.n_corr} n_dir={P.n_dir}")
     algo = "stefcal" if P.n_dir == 1 else "cohjones"
-    plan = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=args.mode,
-                         precision=args.precision)
-    g0 = P.unit_gains()
+    smooth = None
+    if args.smooth:
+        smooth = tuple(float(x) for x in args.smooth.split(","))
+        if P.n_dir != 1 or P.n_corr != 1 or int(P.ns.max()) != 1:
+            sys.exit("--smooth needs a scalar workload of one-sample intervals (bandpass_na256)")
+        # the intervals' rows are the samples of one 1 x n_int grid, in the same order
+        plan = wcal.Plan(P.n_ant, P.ant1.cpu(), P.ant2.cpu(), [P.n_int], tol=args.tol, max_iter=args.max_iter)
+        plan.smoothing(1, P.n_int, smooth[0], smooth[1])
+        args.no_graph, args.no_autotune, args.no_alt_mode = True, True, True
+    else:
+        plan = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=args.mode,
+                             precision=args.precision)
+    g0 = P.unit_gains() if smooth is None else torch.ones(1, P.n_int, P.n_ant, dtype=torch.complex64, device=dev)
+    n_out = P.n_int if smooth is None else 1
     tuned = None
     if not args.no_autotune:
         # tiling chosen by the plan autotuner on this workload (before the timed region)
@@ -192,14 +231,14 @@ def main():
         log(f"[bench] autotune: {tuned}")
     gains = g0.clone()
     residual = torch.empty_like(P.data)
-    n_iter = torch.empty(P.n_int, dtype=torch.int32, device=dev)
-    status = torch.empty(P.n_int, dtype=torch.int32, device=dev)
-    chi2 = torch.empty(P.n_int, dtype=torch.float64, device=dev)
+    n_iter = torch.empty(n_out, dtype=torch.int32, device=dev)
+    status = torch.empty(n_out, dtype=torch.int32, device=dev)
+    chi2 = torch.empty(n_out, dtype=torch.float64, device=dev)
 
     def step():
         gains.copy_(g0)
-        plan.solve(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter,
-                   status=status, chi2=chi2)
+        solve = plan.solve if smooth is None else plan.solve_smooth
+        solve(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
@@ -246,6 +285,8 @@ def main():
     plan.profile(False)
 
     rows_k = (P.row_off[1:] - P.row_off[:-1]).to(torch.float64)
+    if smooth is not None:
+        rows_k = torch.tensor([float(P.n_rows)], dtype=torch.float64)
     it = n_iter.cpu().to(torch.float64)
     st = status.cpu()
     vis_iter = float((rows_k * it).sum())
@@ -297,7 +338,9 @@ def main():
             "flag_frac": 0.0 if P.flags is None else round(float(P.flags.float().mean()), 4),
         },
         "solve_time_ms": ms_step,
-        "timed_as": "eager wcal_solve calls" if args.no_graph else "HIP graph replays of wcal_solve",
+        "smoothing": None if smooth is None else {"grid": [1, P.n_int], "sigma_t": smooth[0], "sigma_f": smooth[1]},
+        "timed_as": ("eager wcal_solve_smooth calls" if smooth else
+                     "eager wcal_solve calls" if args.no_graph else "HIP graph replays of wcal_solve"),
         "autotune": tuned,
         "solve_time_ms_with_kernel_events": ms_step_profiled,
         "mode": args.mode,
@@ -359,7 +402,7 @@ def main():
         plan = plan_main
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(P, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(P, args.cpu_budget) if smooth is None else cpu_baseline_smooth(P, smooth)
     line = json.dumps(out)
     print(line, flush=True)
     if args.out_json:

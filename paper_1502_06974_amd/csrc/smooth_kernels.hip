@@ -201,14 +201,17 @@ __global__ void __launch_bounds__(SB) sm_finish_kernel(const double* part, int b
     }
 }
 
-// chi^2 per interval from the residual tiles of its cells, in tile order
-__global__ void __launch_bounds__(SB) sm_chi2_kernel(const double* chi_part, const int32_t* toff, int n_int,
-                                                     int ncell, double* chi2) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_int || !chi2) return;
+// chi^2 per interval from the residual tiles of its cells: one workgroup per interval, each
+// thread a fixed strided share of the tiles, then the fixed-order workgroup sum
+__global__ void __launch_bounds__(SB) sm_chi2_kernel(const double* chi_part, const int32_t* toff, int ncell,
+                                                     double* chi2) {
+    __shared__ double red[SB / WAVE];
+    const int k = blockIdx.x;
     double c = 0.0;
-    for (int t = toff[(int64_t)k * ncell]; t < toff[(int64_t)(k + 1) * ncell]; ++t) c += chi_part[t];
-    chi2[k] = c;
+    for (int t = toff[(int64_t)k * ncell] + threadIdx.x; t < toff[(int64_t)(k + 1) * ncell]; t += SB)
+        c += chi_part[t];
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) chi2[k] = c;
 }
 
 unsigned nblk(int64_t n) { return (unsigned)((n + SB - 1) / SB); }
@@ -340,8 +343,9 @@ int wcal_solve_smooth(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mod
         r.gains_in = a.gains;
         r.residual = reinterpret_cast<float2*>(residual);
         if (launch_di_resid_tiles(cp, plan, r, s) != hipSuccess) return wcal_error(WCAL_EHIP, "residual launch failed");
-        hipLaunchKernelGGL(sm_chi2_kernel, dim3(nblk(p.n_int)), dim3(SB), 0, s, (const double*)cp->d_chi_part,
-                           (const int32_t*)cp->d_tile_off, p.n_int, ncell, chi2);
+        if (chi2)
+            hipLaunchKernelGGL(sm_chi2_kernel, dim3(p.n_int), dim3(SB), 0, s, (const double*)cp->d_chi_part,
+                               (const int32_t*)cp->d_tile_off, ncell, chi2);
     }
     return hipGetLastError() == hipSuccess ? WCAL_OK : wcal_error(WCAL_EHIP, "smoothed solve launch failed");
 }
