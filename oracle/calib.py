@@ -362,6 +362,19 @@ def residual_dd_2x2(D, M, p, q, flags, G):
     return R, float(np.sum(np.abs(R[k]) ** 2))
 
 
+# ------------------------------------------------------------------ point-source models
+C_LIGHT = 299792458.0
+
+
+def point_model(uvw, lmn, flux, freq):
+    """Point-source model of Sect. 3.2.1: m^d = S_d k^d with the phase rotation
+    k^d = exp(-2 pi i (u . sigma_d) nu / c), sigma_d = [l_d, m_d, n_d - 1].
+    uvw [R, 3] (metres) and freq [R] (Hz) per row, lmn [Nd, 3], flux [Nd]; returns [R, Nd]."""
+    ph = (np.asarray(uvw, dtype=np.float64) @ np.asarray(lmn, dtype=np.float64).T)     # [R, Nd]
+    arg = -2.0 * np.pi * ph * np.asarray(freq, dtype=np.float64)[:, None] / C_LIGHT
+    return np.asarray(flux, dtype=np.float64)[None, :] * np.exp(1j * arg)
+
+
 # ------------------------------------------------------------------ iteration driver
 def _solve(accumulate, gn, residual, finite, sing_to_ant, d, m, p, q, flags, g0,
            tol, max_iter, schedule):

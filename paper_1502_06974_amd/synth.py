@@ -349,7 +349,9 @@ def dd_point(n_ant: int = 64, n_dir: int = 10, n_time: int = 30, n_chan: int = 6
     contiguous hour-angle block and all n_chan channels over [nu_lo, nu_hi].
     Gains per (interval, direction, antenna): amplitude exp(N(0, 0.1^2)) and
     phase U(-pi, pi); with smooth_gains they drift smoothly across intervals.
-    Noise is CN(0, (noise_frac * sum_d S_d)^2)."""
+    Noise is CN(0, (noise_frac * sum_d S_d)^2).  meta holds the inputs of the model: uvw
+    [n_int][n_time][n_bl][3] (metres, ant2 - ant1), lmn [n_dir][3] (l, m, n - 1), flux, and the
+    channel grid freq0 + f * dfreq."""
     gen = _gen(SEED_BASE * 16 + 4 + 7919 * seed, device)
     f64 = torch.float64
     ant1, ant2 = baselines(n_ant, device)
@@ -365,8 +367,10 @@ def dd_point(n_ant: int = 64, n_dir: int = 10, n_time: int = 30, n_chan: int = 6
     ns = torch.full((n_int,), n_time * n_chan, dtype=torch.int64)
     rows = n_int * n_time * n_chan * n_bl
     model = torch.empty(rows, n_dir, 1, dtype=dtype, device=device)
+    uvw = torch.empty(n_int, n_time, n_bl, 3, dtype=f64, device=device)
     for k in range(n_int):
         u, v, w = _uvw(geo, ant1, ant2, k, n_time, n_int, dt, dec_deg, device)
+        uvw[k, ..., 0], uvw[k, ..., 1], uvw[k, ..., 2] = u, v, w
         # phase[t, b, d] per unit frequency
         ph = (u[..., None] * l + v[..., None] * mm + w[..., None] * (n - 1)) / C_LIGHT
         # rows ordered [s][bl] with s = t * n_chan + f
@@ -386,7 +390,9 @@ def dd_point(n_ant: int = 64, n_dir: int = 10, n_time: int = 30, n_chan: int = 6
         gains = torch.polar(amp, ph0)[None].expand(n_int, -1, -1)
     gains = gains.to(dtype).reshape(n_int, n_dir, n_ant, 1).contiguous()
     sigma = noise_frac * float(flux.sum())
-    meta = dict(kind="dd_point", seed=seed, l=l.cpu(), m=mm.cpu(), flux=flux.cpu(), sigma=sigma)
+    meta = dict(kind="dd_point", seed=seed, l=l.cpu(), m=mm.cpu(), flux=flux.cpu(), sigma=sigma,
+                uvw=uvw, lmn=torch.stack([l, mm, n - 1], dim=1), n_time=n_time, n_chan=n_chan,
+                freq0=nu_lo + 0.5 * (nu_hi - nu_lo) / n_chan, dfreq=(nu_hi - nu_lo) / n_chan)
     return _finish(n_ant, n_dir, 1, ant1, ant2, ns, model, gains, sigma, flag_frac, gen, device,
                    dtype, meta, noise)
 

@@ -332,6 +332,30 @@ def test_p2_p4_pol_dd_blocks():
     assert np.array_equal(acc["count"], np.bincount(p, minlength=na) + np.bincount(q, minlength=na))
 
 
+def test_point_model_definition():
+    """Sect. 3.2.1: a source at the phase centre is its flux on every baseline; reversing a
+    baseline (u -> -u) conjugates the model (m_qp = conj(m_pq)); and the oracle's model equals
+    the synthetic generator's independent evaluation of the same sky (complex128)."""
+    uvw = 3000.0 * rng.standard_normal((50, 3))
+    freq = 1e8 + 1e8 * rng.random(50)
+    lmn = np.array([[0.0, 0.0, 0.0], [0.01, -0.02, np.sqrt(1 - 0.01 ** 2 - 0.02 ** 2) - 1]])
+    flux = np.array([2.5, 0.7])
+    m = oc.point_model(uvw, lmn, flux, freq)
+    assert np.allclose(m[:, 0], 2.5, atol=0)
+    assert np.allclose(oc.point_model(-uvw, lmn, flux, freq), np.conj(m), rtol=1e-14)
+    P = synth.dd_point(6, 3, n_time=3, n_chan=5, n_int=2, noise=False, dtype=torch.complex128, seed=11)
+    nt, nf, nbl = P.meta["n_time"], P.meta["n_chan"], P.n_bl
+    for k in range(P.n_int):
+        s = np.arange(nt * nf)
+        t, f = np.repeat(s // nf, nbl), np.repeat(s % nf, nbl)
+        b = np.tile(np.arange(nbl), nt * nf)
+        u = P.meta["uvw"][k].numpy()[t, b]
+        nu = P.meta["freq0"] + f * P.meta["dfreq"]
+        mo = oc.point_model(u, P.meta["lmn"].numpy(), P.meta["flux"].numpy(), nu)
+        a, e = int(P.row_off[k]), int(P.row_off[k + 1])
+        assert np.allclose(mo, P.model[a:e, :, 0].numpy(), rtol=1e-12, atol=1e-12)
+
+
 # ------------------------------------------------------------------ P3 conjugate symmetry
 def test_p3_conjugate_symmetry():
     """Eq. JHR:DI1: bottom half of J^H r is conj(top); the GN step has conj symmetry."""
