@@ -186,6 +186,9 @@ def main():
     ap.add_argument("--smooth", default=None, metavar="SIGMA_T,SIGMA_F",
                     help="StefCal with time/frequency smoothing (Sect. 3.4): a workload of one-sample "
                          "intervals is taken as one 1 x n_int grid of cells, smoothed with these widths")
+    ap.add_argument("--points", action="store_true",
+                    help="point-source workloads (cohjones_na64): predict the model in the passes "
+                         "(wcal_solve_points) instead of reading it from HBM")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(a known-size reference for hardware byte counters)")
@@ -222,6 +225,15 @@ def main():
     else:
         plan = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=args.mode,
                              precision=args.precision)
+    pts = None
+    if args.points:
+        if "uvw" not in P.meta:
+            sys.exit("--points needs a point-source workload (cohjones_na64)")
+        m = P.meta
+        pts = dict(n_time=m["n_time"], n_chan=m["n_chan"], freq0=m["freq0"], dfreq=m["dfreq"],
+                   uvw=m["uvw"].contiguous(), lmn=m["lmn"].to(dev).contiguous(),
+                   flux=m["flux"].to(dev, torch.float32).contiguous())
+        args.no_graph, args.no_autotune = True, True
     g0 = P.unit_gains() if smooth is None else torch.ones(1, P.n_int, P.n_ant, dtype=torch.complex64, device=dev)
     n_out = P.n_int if smooth is None else 1
     tuned = None
@@ -237,6 +249,10 @@ def main():
 
     def step():
         gains.copy_(g0)
+        if pts is not None:
+            plan.solve_points(**pts, data=P.data, flags=P.flags, gains=gains, residual=residual, n_iter=n_iter,
+                              status=status, chi2=chi2)
+            return
         solve = plan.solve if smooth is None else plan.solve_smooth
         solve(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
@@ -292,6 +308,9 @@ def main():
     vis_iter = float((rows_k * it).sum())
     value = vis_iter / (ms_step * 1e-3)
     bpr = bytes_per_row(P.n_corr, P.n_dir, P.flags is not None)
+    if pts is not None:
+        # data and flag per row; the uvw of a (time, baseline), 24 B, serves n_chan rows
+        bpr = 8 * P.n_corr + (1 if P.flags is not None else 0) + 24.0 / pts["n_chan"]
     resid_bytes = P.n_rows * (bpr + 8 * P.n_corr)
     dd = P.n_dir > 1
     if args.mode == "pass":
@@ -339,7 +358,8 @@ def main():
         },
         "solve_time_ms": ms_step,
         "smoothing": None if smooth is None else {"grid": [1, P.n_int], "sigma_t": smooth[0], "sigma_f": smooth[1]},
-        "timed_as": ("eager wcal_solve_smooth calls" if smooth else
+        "predicted_model": pts is not None,
+        "timed_as": ("eager wcal_solve_points calls" if pts else "eager wcal_solve_smooth calls" if smooth else
                      "eager wcal_solve calls" if args.no_graph else "HIP graph replays of wcal_solve"),
         "autotune": tuned,
         "solve_time_ms_with_kernel_events": ms_step_profiled,

@@ -224,6 +224,32 @@ int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                   const uint8_t* flags, const wcal_c64* gains, wcal_c64* residual,
                   double* chi2, void* stream);
 
+/* Point-source models predicted in the Gram and residual passes instead of read from HBM
+ * (Sect. 3.2.1: m^d_pq(t, nu) = S_d exp(-2 pi i (u_pq(t) . sigma_d) nu / c), sigma_d =
+ * [l_d, m_d, n_d - 1]), for scalar CohJones / AllJones with the FP32 Gram.  The pass then
+ * reads 9 bytes per row (data and flag) instead of 8 Nd + 9.  Every interval holds
+ * n_time * n_chan samples, sample s = t * n_chan + f, channel f at freq0 + f * dfreq.  The
+ * phase is formed in FP64 and reduced to [-pi, pi] before FP32 sine and cosine at the first
+ * sample of each chunk and at every new time slot, and stepped across channels by one
+ * complex multiply per sample (relative model error ~1e-6).  All arrays are device memory. */
+typedef struct {
+    int32_t n_time;      /* timeslots per interval                                      */
+    int32_t n_chan;      /* channels per interval                                       */
+    double freq0;        /* Hz, channel 0                                               */
+    double dfreq;        /* Hz, channel spacing                                         */
+    const double* uvw;   /* [n_int][n_time][n_bl][3] metres, baseline vector ant2 - ant1 */
+    const double* lmn;   /* [n_dir][3]: l, m, n - 1                                      */
+    const float* flux;   /* [n_dir] Jy                                                   */
+} wcal_points;
+
+/* wcal_solve with the model given by `pts` (data, flags, gains, residual, n_iter, status, chi2
+ * as in wcal_solve; PASS or STATS mode).  Errors: WCAL_EINVAL (plan not scalar CohJones /
+ * AllJones with the FP32 Gram, NULL or misaligned arrays, n_time or n_chan < 1), WCAL_ESHAPE
+ * (an interval that does not hold n_time * n_chan samples). */
+int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* data, const uint8_t* flags,
+                      wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
+                      void* stream);
+
 /* Time/frequency smoothing of scalar StefCal (Sect. 3.4, Eq. JHJ:diag:smooth).  Every
  * sample of an interval becomes a cell (t, nu) of an n_time x n_chan grid, sample
  * s = t * n_chan + nu, with gains of its own; every update takes

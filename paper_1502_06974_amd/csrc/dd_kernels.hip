@@ -196,9 +196,24 @@ __device__ __forceinline__ float2 row16_sum(float2 v) {
     return v;
 }
 
-// list: the intervals to process (n_list of them), or null for every interval in LPT order
+// exp(i x) for an FP64 angle: reduced to [-pi, pi] in FP64, then FP32 sine and cosine
+__device__ __forceinline__ float2 cis_reduced(double x) {
+    const double r = x - 6.283185307179586 * rint(x * 0.15915494309189535);
+    float sn, cs;
+    sincosf((float)r, &sn, &cs);
+    return make_float2(cs, sn);
+}
+
+// list: the intervals to process (n_list of them), or null for every interval in LPT order.
+// PRED: the model columns are the point sources of a.pt, predicted instead of read
+// (Sect. 3.2.1, m^d = S_d exp(-2 pi i (u . sigma_d) nu / c)).  Each (baseline, direction) pair
+// of the task belongs to one thread (spread evenly over the wavefronts), which generates the
+// next chunk's values into the second LDS buffer behind the current chunk's MFMAs: the
+// phasor is taken from an FP64 phase reduced to [-pi, pi] at a new time slot and every 16
+// channels, and stepped from channel to channel by one multiply with exp(-2 pi i phi dfreq).
+template <bool PRED>
 __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8))) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
-    __shared__ float2 abuf[GS][GB][16];
+    __shared__ float2 abuf[PRED ? 2 : 1][GS][GB][16];   // PRED: double-buffered chunks
     __shared__ uint8_t fbuf[GS][GB];
     __shared__ int s_task;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -212,14 +227,15 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     const int64_t ntask = (int64_t)nint * nbb;
     if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
     const bool has_flags = a.flags != nullptr;
-    const int nmod = GS * GB * nd;              // model elements of a chunk
+    constexpr int GPTK = PRED ? (GS * GB + DT - 1) / DT : GPT;
+    const int nmod = PRED ? 0 : GS * GB * nd;   // model elements of a chunk (read, not predicted)
     const int nel = nmod + GS * GB;             // + data elements
     // static decode of this thread's staged elements: chunk-relative global offset (in
     // model or data elements) and a packed code (LDS slot | sample << 12 | baseline << 16;
     // -1 for no element)
-    int goff[GPT], code[GPT];
+    int goff[GPTK], code[GPTK];
 #pragma unroll
-    for (int r = 0; r < GPT; ++r) {
+    for (int r = 0; r < GPTK; ++r) {
         const int i = threadIdx.x + DT * r;
         goff[r] = 0;
         code[r] = -1;
@@ -235,7 +251,18 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     }
     const int fs = threadIdx.x / GB, fb = threadIdx.x % GB;   // flag staged by this thread
     const bool fown = threadIdx.x < GS * GB;
-    float2* lds = &abuf[0][0][0];
+    float2* lds = &abuf[0][0][0][0];
+    // PRED: (baseline, direction) pairs spread evenly over the wavefronts, pair = 4 lane + w
+    const int gpair = PRED ? 4 * (int)(threadIdx.x & (WAVE - 1)) + (int)(threadIdx.x / WAVE) : 1 << 20;
+    double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
+    float gS = 0.f;
+    if constexpr (PRED) {
+        if (gpair < GB * nd) {
+            const int d = gpair % nd;
+            gl0 = a.pt.lmn[3 * d]; gl1 = a.pt.lmn[3 * d + 1]; gl2 = a.pt.lmn[3 * d + 2];
+            gS = a.pt.flux[d];
+        }
+    }
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
@@ -247,15 +274,15 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
         const int nch = (ns + GS - 1) / GS;
-        float2 stage[GPT];
+        float2 stage[GPTK];
         uint8_t fstage = 1;
         auto fetch = [&](int c) {
             const int s0 = c * GS;
             const int64_t row0 = off + (int64_t)s0 * nbl + b0;
-            const float2* mb = a.model + row0 * nd;
+            const float2* mb = PRED ? nullptr : a.model + row0 * nd;
             const float2* db = a.data + row0;
 #pragma unroll
-            for (int r = 0; r < GPT; ++r) {
+            for (int r = 0; r < GPTK; ++r) {
                 const int cd = code[r];
                 const bool ok = cd >= 0 && s0 + ((cd >> 12) & 15) < ns && b0 + (cd >> 16) < nbl;
                 const int i = threadIdx.x + DT * r;
@@ -274,12 +301,58 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
             cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cnt[j] = 0;
         }
+        // PRED: this thread's (baseline, direction) pair of the task and its phasor state,
+        // walked sample by sample (time slot gt, channel gf); the u vector of the next time
+        // slot is loaded one slot ahead, so no wait on it sits inside the chunk loop.
+        // Chunk c's model values go straight to LDS buffer c % 2.
+        float2 gz = make_float2(0.f, 0.f), gw = make_float2(0.f, 0.f);
+        double gph = 0.0, gu0 = 0.0, gu1 = 0.0, gu2 = 0.0;
+        int gt = 0, gf = 0;
+        const int gbl = gpair / (nd > 0 ? nd : 1), gd = gpair - gbl * nd;
+        const bool gown = PRED && gpair < GB * nd && b0 + gbl < nbl;
+        auto load_u = [&](int t) {
+            if (t < a.pt.n_time) {
+                const double* u = a.pt.uvw + (((int64_t)k * a.pt.n_time + t) * nbl + b0 + gbl) * 3;
+                gu0 = u[0]; gu1 = u[1]; gu2 = u[2];
+            }
+        };
+        if (gown) load_u(0);
+        auto generate = [&](int c) {
+            if constexpr (PRED) {
+                if (!gown) return;
+                const int s0 = c * GS, nch_ = a.pt.n_chan;
+                float2 (*buf)[GB][16] = abuf[c & 1];
+#pragma unroll
+                for (int sm = 0; sm < GS; ++sm) {
+                    float2 v = make_float2(0.f, 0.f);
+                    if (s0 + sm < ns) {
+                        if (gf == 0) {
+                            gph = -6.283185307179586 * (gu0 * gl0 + gu1 * gl1 + gu2 * gl2) / 299792458.0;
+                            gw = cis_reduced(gph * a.pt.dfreq);
+                            load_u(gt + 1);
+                        }
+                        // FP64 phase reduced to [-pi, pi] every 16 channels, a step between
+                        if ((gf & 15) == 0) gz = cis_reduced(gph * (a.pt.freq0 + gf * a.pt.dfreq));
+                        else gz = cmul(gz, gw);
+                        v = make_float2(gS * gz.x, gS * gz.y);
+                        if (++gf == nch_) {
+                            gf = 0;
+                            ++gt;
+                        }
+                    }
+                    buf[sm][gbl][gd] = v;
+                }
+            }
+        };
         fetch(0);
+        generate(0);
         for (int c = 0; c < nch; ++c) {
+            const int cb = PRED ? c & 1 : 0;
+            float2 (*cur)[GB][16] = abuf[cb];
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < GPT; ++r)
-                if (code[r] >= 0) lds[code[r] & 4095] = stage[r];
+            for (int r = 0; r < GPTK; ++r)
+                if (code[r] >= 0) lds[cb * (GS * GB * 16) + (code[r] & 4095)] = stage[r];
             if (fown) fbuf[fs][fb] = fstage;
             __syncthreads();
             if (c + 1 < nch) fetch(c + 1);
@@ -291,13 +364,15 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                     const int sl = 4 * g + kk;
                     const bool use = !fbuf[sl][bl];
                     float2 v = make_float2(0.f, 0.f);
-                    if (use && col <= nd) v = abuf[sl][bl][col];
+                    if (use && col <= nd) v = cur[sl][bl][col];
                     if (use && col == 0) ++cnt[j];
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
                     cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
                 }
             }
+            // the next chunk's predicted model, into the other buffer while the MFMAs drain
+            if (c + 1 < nch) generate(c + 1);
         }
         // epilogue: each wavefront writes the records of its four baselines through its own
         // 2 x 256-float area of the (now free) staging buffer
@@ -834,6 +909,9 @@ __global__ void __launch_bounds__(DT) dd_reduce_kernel(DdArgs a, DdState st) {
 }
 
 // Residual rows of one tile: lane <-> baseline, weights g^c_p conj(g^c_q) per round.
+// PRED: the point-source model of a.pt, its phasors recomputed at every new time slot and
+// stepped from channel to channel (as in the Gram pass).
+template <bool PRED>
 __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int ctr_slot) {
     __shared__ double red[DT / WAVE];
     __shared__ int s_t;
@@ -855,17 +933,43 @@ __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int 
 #pragma unroll
             for (int c = 0; c < NDMAX; ++c)
                 w[c] = c < nd ? cmulc(gk[c * na + p], gk[c * na + q]) : make_float2(0.f, 0.f);
+            float2 z[PRED ? NDMAX : 1], step[PRED ? NDMAX : 1];
             float part = 0.f;
             for (int s = T.s0; s < T.s1; ++s) {
                 const int64_t row = off + (int64_t)s * nbl + b;
+                if constexpr (PRED) {
+                    const int tt = s / a.pt.n_chan, f = s - tt * a.pt.n_chan;
+                    if (s == T.s0 || f == 0) {
+                        const double* u = a.pt.uvw + (((int64_t)T.k * a.pt.n_time + tt) * nbl + b) * 3;
+#pragma unroll
+                        for (int c = 0; c < NDMAX; ++c)
+                            if (c < nd) {
+                                const double* l = a.pt.lmn + 3 * c;
+                                const double ph = -6.283185307179586 * (u[0] * l[0] + u[1] * l[1] + u[2] * l[2]) / 299792458.0;
+                                const float2 e = cis_reduced(ph * (a.pt.freq0 + f * a.pt.dfreq));
+                                z[c] = make_float2(a.pt.flux[c] * e.x, a.pt.flux[c] * e.y);
+                                step[c] = cis_reduced(ph * a.pt.dfreq);
+                            }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < NDMAX; ++c)
+                            if (c < nd) z[c] = cmul(z[c], step[c]);
+                    }
+                }
                 const bool fl = has_flags && a.flags[row] != 0;
                 float2 r = make_float2(0.f, 0.f);
                 if (!fl) {
                     r = a.data[row];
-                    const float2* m = a.model + row * nd;
+                    if constexpr (PRED) {
 #pragma unroll
-                    for (int c = 0; c < NDMAX; ++c)
-                        if (c < nd) r = csub(r, cmul(w[c], m[c]));
+                        for (int c = 0; c < NDMAX; ++c)
+                            if (c < nd) r = csub(r, cmul(w[c], z[c]));
+                    } else {
+                        const float2* m = a.model + row * nd;
+#pragma unroll
+                        for (int c = 0; c < NDMAX; ++c)
+                            if (c < nd) r = csub(r, cmul(w[c], m[c]));
+                    }
                     part += nrm(r);
                 }
                 if (a.residual) a.residual[row] = r;
@@ -887,9 +991,13 @@ int dd_max_dir() { return NDMAX; }
 
 static void launch_residual_tiles(const wcal_plan* plan, const DdArgs& a, const DdState& st, hipStream_t s,
                                   int slot) {
-    const int g = dd_grid(plan, reinterpret_cast<const void*>(dd_resid_kernel), 0, st.ntiles);
+    const bool pred = a.pt.uvw != nullptr;
+    const void* fn = pred ? reinterpret_cast<const void*>(dd_resid_kernel<true>)
+                          : reinterpret_cast<const void*>(dd_resid_kernel<false>);
+    const int g = dd_grid(plan, fn, 0, st.ntiles);
     prof_begin(plan, WCAL_K_RESID, s);
-    hipLaunchKernelGGL(dd_resid_kernel, dim3(g), dim3(DT), 0, s, a, st, slot);
+    if (pred) hipLaunchKernelGGL(dd_resid_kernel<true>, dim3(g), dim3(DT), 0, s, a, st, slot);
+    else hipLaunchKernelGGL(dd_resid_kernel<false>, dim3(g), dim3(DT), 0, s, a, st, slot);
     prof_end(plan, WCAL_K_RESID, s);
     hipLaunchKernelGGL(dd_chi2_kernel, dim3((a.n_int + DT - 1) / DT), dim3(DT), 0, s, a, st);
 }
@@ -903,7 +1011,9 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const bool bf = plan->prob.precision == WCAL_PREC_BF16_GRAM;
     const bool p16 = nd % 2 == 0 && reinterpret_cast<uintptr_t>(a.model) % 16 == 0;
     typedef void (*GramFn)(DdArgs, DdState, const int32_t*, const int32_t*);
-    GramFn gram = !bf ? dd_gram_blk_kernel : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
+    const bool pred = a.pt.uvw != nullptr;
+    GramFn gram = pred ? dd_gram_blk_kernel<true>
+                       : !bf ? dd_gram_blk_kernel<false> : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
     const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), 0, nblk);
     const size_t asm_ = ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);

@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/wcal.h: validation, plan tables, launches.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -486,6 +487,45 @@ int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, con
         e = plan->prob.n_corr == 4 ? launch_ddp_solve(plan, a, s) : launch_dd_solve(plan, a, s);
     }
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve launch");
+}
+
+int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* data, const uint8_t* flags,
+                      wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
+                      void* stream) {
+    g_err.clear();
+    if (!plan || !pts || !data || !gains || !n_iter || !status) return fail(WCAL_EINVAL, "NULL argument");
+    const wcal_problem& p = plan->prob;
+    if ((p.algo != WCAL_COHJONES && p.algo != WCAL_ALLJONES) || p.n_corr != 1 || p.precision != WCAL_PREC_FP32)
+        return fail(WCAL_EINVAL, "predicted point-source models need scalar CohJones / AllJones with the FP32 Gram");
+    if (!pts->uvw || !pts->lmn || !pts->flux) return fail(WCAL_EINVAL, "uvw, lmn and flux are required");
+    if (pts->n_time < 1 || pts->n_chan < 1 || !std::isfinite(pts->freq0) || !std::isfinite(pts->dfreq))
+        return fail(WCAL_EINVAL, "n_time, n_chan >= 1 and finite frequencies required");
+    for (int32_t k = 0; k < p.n_int; ++k)
+        if (plan->h_ns[k] != (int64_t)pts->n_time * pts->n_chan)
+            return fail(WCAL_ESHAPE, "every interval must hold n_time * n_chan samples");
+    if (!aligned(data, 8) || !aligned(gains, 8) || (residual && !aligned(residual, 8)) || !aligned(pts->uvw, 8) ||
+        !aligned(pts->lmn, 8) || !aligned(pts->flux, 4))
+        return fail(WCAL_EINVAL, "misaligned argument");
+    if (hipSetDevice(plan->device) != hipSuccess) return fail(WCAL_EHIP, "hipSetDevice failed");
+    DdArgs a{};
+    fill_tables_dd(plan, a);
+    a.data = reinterpret_cast<const float2*>(data);
+    a.model = nullptr;
+    a.pt.uvw = pts->uvw;
+    a.pt.lmn = pts->lmn;
+    a.pt.flux = pts->flux;
+    a.pt.freq0 = pts->freq0;
+    a.pt.dfreq = pts->dfreq;
+    a.pt.n_time = pts->n_time;
+    a.pt.n_chan = pts->n_chan;
+    a.flags = flags;
+    a.gains = reinterpret_cast<float2*>(gains);
+    a.residual = reinterpret_cast<float2*>(residual);
+    a.n_iter = n_iter;
+    a.status = status;
+    a.chi2 = chi2;
+    const hipError_t e = launch_dd_solve(plan, a, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve_points launch");
 }
 
 int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,

@@ -116,9 +116,20 @@ struct DiArgs {
     double tol;
 };
 
+// Point-source models predicted on the device instead of read from model[] (Sect. 3.2.1):
+// sample s = t * n_chan + f of every interval, channel frequency freq0 + f * dfreq.
+struct PointArgs {
+    const double* uvw = nullptr;   // [n_int][n_time][n_bl][3] metres (ant2 - ant1)
+    const double* lmn = nullptr;   // [nd][3]: l, m, n - 1
+    const float* flux = nullptr;   // [nd]
+    double freq0 = 0.0, dfreq = 0.0;
+    int32_t n_time = 0, n_chan = 0;
+};
+
 struct DdArgs {
     const float2* data;      // [rows]
-    const float2* model;     // [rows][nd]
+    const float2* model;     // [rows][nd], or null with pt.uvw set
+    PointArgs pt;
     const uint8_t* flags;
     float2* gains;           // [n_int][nd][n_ant][n_corr]
     const float2* gains_in;

@@ -34,7 +34,8 @@ EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_des
            "wcal_profile_enable", "wcal_profile_read", "wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains",
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
-           "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth")
+           "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth",
+           "wcal_solve_points")
 K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
@@ -42,6 +43,11 @@ class WcalError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"wcal error {code}: {msg}")
         self.code = code
+
+
+class Points(C.Structure):
+    _fields_ = [("n_time", C.c_int32), ("n_chan", C.c_int32), ("freq0", C.c_double), ("dfreq", C.c_double),
+                ("uvw", C.c_void_p), ("lmn", C.c_void_p), ("flux", C.c_void_p)]
 
 
 class Problem(C.Structure):
@@ -92,6 +98,8 @@ def lib() -> C.CDLL:
     L.wcal_plan_smoothing.restype = C.c_int
     L.wcal_solve_smooth.argtypes = [vp] * 10
     L.wcal_solve_smooth.restype = C.c_int
+    L.wcal_solve_points.argtypes = [vp, C.POINTER(Points)] + [vp] * 8
+    L.wcal_solve_points.restype = C.c_int
     L.wcal_profile_enable.argtypes = [vp, C.c_int]
     L.wcal_profile_enable.restype = C.c_int
     L.wcal_profile_read.argtypes = [vp, vp, vp]
@@ -114,7 +122,8 @@ def lib() -> C.CDLL:
     L.wcal_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp, vp]
     for f in ("wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains", "wcal_gains_to_bins", "wcal_reset_unconverged",
               "wcal_mlp_create", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
-              "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth"):
+              "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth",
+           "wcal_solve_points"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -304,6 +313,34 @@ class Plan:
             chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
         self._dev(residual, "residual", torch.complex64, (R, 1))
         _check(lib().wcal_solve_smooth(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains), _ptr(residual),
+                                       _ptr(n_iter), _ptr(status), _ptr(chi2), self._stream(stream)))
+        return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
+
+    def solve_points(self, n_time: int, n_chan: int, freq0: float, dfreq: float, uvw, lmn, flux, data, flags,
+                     gains, residual=None, n_iter=None, status=None, chi2=None, stream=None,
+                     want_residual: bool = True, want_chi2: bool = True):
+        """wcal_solve_points: the point-source model (uvw [n_int][n_time][n_bl][3] float64,
+        lmn [n_dir][3] float64, flux [n_dir] float32, device) predicted in the passes."""
+        R = self.rows
+        self._dev(data, "data", torch.complex64, (R, 1))
+        if flags is not None:
+            self._dev(flags, "flags", torch.uint8, (R,))
+        self._dev(gains, "gains", torch.complex64, (self.n_int, self.n_dir, self.n_ant, 1))
+        self._dev(uvw, "uvw", torch.float64, (self.n_int, n_time, self.n_bl, 3))
+        self._dev(lmn, "lmn", torch.float64, (self.n_dir, 3))
+        self._dev(flux, "flux", torch.float32, (self.n_dir,))
+        dev = gains.device
+        if residual is None and want_residual:
+            residual = torch.empty_like(data)
+        if n_iter is None:
+            n_iter = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if chi2 is None and want_chi2:
+            chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
+        self._dev(residual, "residual", torch.complex64, (R, 1))
+        pts = Points(int(n_time), int(n_chan), float(freq0), float(dfreq), _ptr(uvw), _ptr(lmn), _ptr(flux))
+        _check(lib().wcal_solve_points(self._h, C.byref(pts), _ptr(data), _ptr(flags), _ptr(gains), _ptr(residual),
                                        _ptr(n_iter), _ptr(status), _ptr(chi2), self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
