@@ -313,14 +313,14 @@ def main():
         bpr = 8 * P.n_corr + (1 if P.flags is not None else 0) + 24.0 / pts["n_chan"]
     resid_bytes = P.n_rows * (bpr + 8 * P.n_corr)
     dd = P.n_dir > 1
+    # wcal_solve_points runs its own Gram kernel, which predicts the model instead of reading it
+    kname = "dd_gram_pts_kernel" if pts is not None else plan.pass_kernel
     if args.mode == "pass":
         # every update's pass streams D, M and flags of the interval once
         kcls = "pass"
-        kname = plan.pass_kernel
         krows = float((rows_k * it).sum()) * args.steps
     else:
         kcls = "stats"
-        kname = plan.pass_kernel
         krows = float(P.n_rows) * args.steps
     kbytes = krows * bpr
     kms, klaunch = prof[kcls]

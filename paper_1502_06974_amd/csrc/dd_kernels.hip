@@ -196,24 +196,24 @@ __device__ __forceinline__ float2 row16_sum(float2 v) {
     return v;
 }
 
-// exp(i x) for an FP64 angle: reduced to [-pi, pi] in FP64, then FP32 sine and cosine
-__device__ __forceinline__ float2 cis_reduced(double x) {
-    const double r = x - 6.283185307179586 * rint(x * 0.15915494309189535);
-    float sn, cs;
-    sincosf((float)r, &sn, &cs);
-    return make_float2(cs, sn);
+// exp(i x) for an FP64 angle x (|x| < 2^30): the quarter-turn count q (nearest integer to
+// x / (pi / 2)) and the remainder r = x - q pi / 2, |r| <= pi / 4, are taken in FP64; sin r
+// and cos r are their Taylor series in FP32, through r^9 and r^10 (the first terms left out
+// are below 2e-9 on |r| <= pi / 4), turned by q quarter turns.
+__device__ __forceinline__ float2 cis_quarter(double x) {
+    const double q = rint(x * 0.63661977236758134);
+    const float r = (float)fma(-q, 1.5707963267948966, x);
+    const float r2 = r * r;
+    const float sn = r * fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, 1.f / 362880.f, -1.f / 5040.f), 1.f / 120.f), -1.f / 6.f), 1.f);
+    const float cs = fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, fmaf(r2, -1.f / 3628800.f, 1.f / 40320.f), -1.f / 720.f), 1.f / 24.f), -0.5f), 1.f);
+    const int qi = (int)q & 3;
+    const float u = (qi & 1) ? sn : cs, v = (qi & 1) ? cs : sn;
+    return make_float2((qi == 1 || qi == 2) ? -u : u, qi >= 2 ? -v : v);
 }
 
-// list: the intervals to process (n_list of them), or null for every interval in LPT order.
-// PRED: the model columns are the point sources of a.pt, predicted instead of read
-// (Sect. 3.2.1, m^d = S_d exp(-2 pi i (u . sigma_d) nu / c)).  Each (baseline, direction) pair
-// of the task belongs to one thread (spread evenly over the wavefronts), which generates the
-// next chunk's values into the second LDS buffer behind the current chunk's MFMAs: the
-// phasor is taken from an FP64 phase reduced to [-pi, pi] at a new time slot and every 16
-// channels, and stepped from channel to channel by one multiply with exp(-2 pi i phi dfreq).
-template <bool PRED>
+// list: the intervals to process (n_list of them), or null for every interval in LPT order
 __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8))) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
-    __shared__ float2 abuf[PRED ? 2 : 1][GS][GB][16];   // PRED: double-buffered chunks
+    __shared__ float2 abuf[GS][GB][16];
     __shared__ uint8_t fbuf[GS][GB];
     __shared__ int s_task;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -227,15 +227,14 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     const int64_t ntask = (int64_t)nint * nbb;
     if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
     const bool has_flags = a.flags != nullptr;
-    constexpr int GPTK = PRED ? (GS * GB + DT - 1) / DT : GPT;
-    const int nmod = PRED ? 0 : GS * GB * nd;   // model elements of a chunk (read, not predicted)
+    const int nmod = GS * GB * nd;              // model elements of a chunk
     const int nel = nmod + GS * GB;             // + data elements
     // static decode of this thread's staged elements: chunk-relative global offset (in
     // model or data elements) and a packed code (LDS slot | sample << 12 | baseline << 16;
     // -1 for no element)
-    int goff[GPTK], code[GPTK];
+    int goff[GPT], code[GPT];
 #pragma unroll
-    for (int r = 0; r < GPTK; ++r) {
+    for (int r = 0; r < GPT; ++r) {
         const int i = threadIdx.x + DT * r;
         goff[r] = 0;
         code[r] = -1;
@@ -251,18 +250,7 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     }
     const int fs = threadIdx.x / GB, fb = threadIdx.x % GB;   // flag staged by this thread
     const bool fown = threadIdx.x < GS * GB;
-    float2* lds = &abuf[0][0][0][0];
-    // PRED: (baseline, direction) pairs spread evenly over the wavefronts, pair = 4 lane + w
-    const int gpair = PRED ? 4 * (int)(threadIdx.x & (WAVE - 1)) + (int)(threadIdx.x / WAVE) : 1 << 20;
-    double gl0 = 0.0, gl1 = 0.0, gl2 = 0.0;
-    float gS = 0.f;
-    if constexpr (PRED) {
-        if (gpair < GB * nd) {
-            const int d = gpair % nd;
-            gl0 = a.pt.lmn[3 * d]; gl1 = a.pt.lmn[3 * d + 1]; gl2 = a.pt.lmn[3 * d + 2];
-            gS = a.pt.flux[d];
-        }
-    }
+    float2* lds = &abuf[0][0][0];
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
@@ -274,15 +262,15 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
         const int nch = (ns + GS - 1) / GS;
-        float2 stage[GPTK];
+        float2 stage[GPT];
         uint8_t fstage = 1;
         auto fetch = [&](int c) {
             const int s0 = c * GS;
             const int64_t row0 = off + (int64_t)s0 * nbl + b0;
-            const float2* mb = PRED ? nullptr : a.model + row0 * nd;
+            const float2* mb = a.model + row0 * nd;
             const float2* db = a.data + row0;
 #pragma unroll
-            for (int r = 0; r < GPTK; ++r) {
+            for (int r = 0; r < GPT; ++r) {
                 const int cd = code[r];
                 const bool ok = cd >= 0 && s0 + ((cd >> 12) & 15) < ns && b0 + (cd >> 16) < nbl;
                 const int i = threadIdx.x + DT * r;
@@ -301,58 +289,12 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
             cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cnt[j] = 0;
         }
-        // PRED: this thread's (baseline, direction) pair of the task and its phasor state,
-        // walked sample by sample (time slot gt, channel gf); the u vector of the next time
-        // slot is loaded one slot ahead, so no wait on it sits inside the chunk loop.
-        // Chunk c's model values go straight to LDS buffer c % 2.
-        float2 gz = make_float2(0.f, 0.f), gw = make_float2(0.f, 0.f);
-        double gph = 0.0, gu0 = 0.0, gu1 = 0.0, gu2 = 0.0;
-        int gt = 0, gf = 0;
-        const int gbl = gpair / (nd > 0 ? nd : 1), gd = gpair - gbl * nd;
-        const bool gown = PRED && gpair < GB * nd && b0 + gbl < nbl;
-        auto load_u = [&](int t) {
-            if (t < a.pt.n_time) {
-                const double* u = a.pt.uvw + (((int64_t)k * a.pt.n_time + t) * nbl + b0 + gbl) * 3;
-                gu0 = u[0]; gu1 = u[1]; gu2 = u[2];
-            }
-        };
-        if (gown) load_u(0);
-        auto generate = [&](int c) {
-            if constexpr (PRED) {
-                if (!gown) return;
-                const int s0 = c * GS, nch_ = a.pt.n_chan;
-                float2 (*buf)[GB][16] = abuf[c & 1];
-#pragma unroll
-                for (int sm = 0; sm < GS; ++sm) {
-                    float2 v = make_float2(0.f, 0.f);
-                    if (s0 + sm < ns) {
-                        if (gf == 0) {
-                            gph = -6.283185307179586 * (gu0 * gl0 + gu1 * gl1 + gu2 * gl2) / 299792458.0;
-                            gw = cis_reduced(gph * a.pt.dfreq);
-                            load_u(gt + 1);
-                        }
-                        // FP64 phase reduced to [-pi, pi] every 16 channels, a step between
-                        if ((gf & 15) == 0) gz = cis_reduced(gph * (a.pt.freq0 + gf * a.pt.dfreq));
-                        else gz = cmul(gz, gw);
-                        v = make_float2(gS * gz.x, gS * gz.y);
-                        if (++gf == nch_) {
-                            gf = 0;
-                            ++gt;
-                        }
-                    }
-                    buf[sm][gbl][gd] = v;
-                }
-            }
-        };
         fetch(0);
-        generate(0);
         for (int c = 0; c < nch; ++c) {
-            const int cb = PRED ? c & 1 : 0;
-            float2 (*cur)[GB][16] = abuf[cb];
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < GPTK; ++r)
-                if (code[r] >= 0) lds[cb * (GS * GB * 16) + (code[r] & 4095)] = stage[r];
+            for (int r = 0; r < GPT; ++r)
+                if (code[r] >= 0) lds[code[r] & 4095] = stage[r];
             if (fown) fbuf[fs][fb] = fstage;
             __syncthreads();
             if (c + 1 < nch) fetch(c + 1);
@@ -364,15 +306,13 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                     const int sl = 4 * g + kk;
                     const bool use = !fbuf[sl][bl];
                     float2 v = make_float2(0.f, 0.f);
-                    if (use && col <= nd) v = cur[sl][bl][col];
+                    if (use && col <= nd) v = abuf[sl][bl][col];
                     if (use && col == 0) ++cnt[j];
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
                     cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
                 }
             }
-            // the next chunk's predicted model, into the other buffer while the MFMAs drain
-            if (c + 1 < nch) generate(c + 1);
         }
         // epilogue: each wavefront writes the records of its four baselines through its own
         // 2 x 256-float area of the (now free) staging buffer
@@ -401,6 +341,208 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                         const int t = tri(i, jj, nd);
                         rec[2 * t] = re;
                         rec[2 * t + 1] = im;
+                    } else if (i < nd && jj == nd) {
+                        rec[rec_z(nd) + 2 * i] = re;
+                        rec[rec_z(nd) + 2 * i + 1] = im;
+                    } else if (i == nd && jj == nd) {
+                        rec[rec_d2(nd)] = re;
+                    }
+                }
+                if (lane == 0) reinterpret_cast<int*>(rec)[rec_cnt(nd)] = cj;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// ------------------------------------------------------------------ predicted-model Gram pass
+// Point-source models (Sect. 3.2.1, m^d = S_d exp(-2 pi i (u . sigma_d) nu / c)) generated in
+// the MFMA operand layout.  Wavefront w of a task owns PBW consecutive baselines and walks
+// their samples four at a time, lane l holding column l % 16 of sample 4g + l / 16 (as in the
+// blocked pass).  A lane of model column d keeps one phasor per baseline for its own sample and
+// steps it by exp(-2 pi i phi 4 dfreq) from one group to the next; the phasor is re-based from
+// the FP64 phase whenever the lane's sample enters a new time slot and after PREBASE steps, so
+// the walk runs in segments between re-bases with a branch-free inner loop.  Data and flags
+// pass through the wavefront's own LDS slice, PCH samples at a time (each lane loads one
+// sample of the wavefront's baselines, a chunk ahead): the slice holds the data value, zeroed
+// where the row is flagged or absent, and a weight 1 or 0.  Every lane then forms its operand
+// as a product, v = z * P: model lanes take P = (weight, weight), the data lane keeps
+// z = (1, 1) and takes P = the data value, and lanes past column Nd keep z = 0.  The
+// wavefronts of a task meet only at the task pop.
+constexpr int PREBASE = 16;
+constexpr int PCH = 64;   // samples per staged chunk: one per lane
+constexpr int PBW = 2;    // baselines per wavefront
+constexpr int PGB = (DT / WAVE) * PBW;   // baselines per task
+__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8))) dd_gram_pts_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+    // per wavefront: [0] [sample][baseline] data, [1] [sample][baseline] (weight, weight);
+    // both together hold the 512-float record tile afterwards
+    __shared__ float2 sbuf[DT / WAVE][2][PCH * PBW];
+    __shared__ int s_task;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int nd = a.n_dir, nbl = a.n_bl;
+    const int RS = rec_floats(nd);
+    const int kk = lane >> 4, col = lane & 15;
+    const int nbb = (nbl + PGB - 1) / PGB;
+    const int nint = list ? *n_list : a.n_int;
+    const int64_t ntask = (int64_t)nint * nbb;
+    if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
+    const bool has_flags = a.flags != nullptr;
+    const bool is_m = col < nd, is_d = col == nd;
+    const int nch = a.pt.n_chan, nt = a.pt.n_time;
+    const double f0 = a.pt.freq0, df4 = 4.0 * a.pt.dfreq, df = a.pt.dfreq;
+    // this lane's direction: -2 pi sigma / c with sigma = (l, m, n - 1), and its flux
+    double sg0 = 0.0, sg1 = 0.0, sg2 = 0.0;
+    float flux = 0.f;
+    if (is_m) {
+        const double sc = -6.283185307179586 / 299792458.0;
+        sg0 = sc * a.pt.lmn[3 * col];
+        sg1 = sc * a.pt.lmn[3 * col + 1];
+        sg2 = sc * a.pt.lmn[3 * col + 2];
+        flux = a.pt.flux[col];
+    }
+    const float2* src = sbuf[w][is_d ? 0 : 1];   // this lane's operand factors
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
+        __syncthreads();
+        const int task = __builtin_amdgcn_readfirstlane(s_task);
+        if (task >= ntask) break;
+        const int k = list ? list[task / nbb] : a.order[task / nbb];
+        const int bw = (task % nbb) * PGB + PBW * w;   // this wavefront's first baseline
+        const int nv = min(PBW, nbl - bw);             // its baselines inside the interval (may be <= 0)
+        if (nv <= 0) continue;
+        const int64_t off = a.row_off[k];
+        const int ns = a.ns[k];
+        const double* uvk = a.pt.uvw + (int64_t)k * nt * nbl * 3;
+        floatx4 crr[PBW], cri[PBW];
+        int cnt[PBW];
+        float2 z[PBW], stp[PBW];
+#pragma unroll
+        for (int j = 0; j < PBW; ++j) {
+            crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cnt[j] = 0;
+            z[j] = is_d ? make_float2(1.f, 1.f) : make_float2(0.f, 0.f);
+            stp[j] = is_d ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
+        }
+        // the lane's sample (kk + 4g) sits at time slot t, channel f (f may run past the slot
+        // until the next re-base); left counts the groups its phasor stays valid for
+        int t = 0, f = kk, left = 0;
+        // chunk staging: lane l loads sample c PCH + l of the wavefront's baselines (clamped
+        // rows keep every address inside the interval)
+        float2 pd[PBW];
+        int pf[PBW];
+        auto fetch = [&](int c) {
+            const int sc = min(c * PCH + lane, ns - 1);
+            const int64_t r0 = off + (int64_t)sc * nbl + bw;
+#pragma unroll
+            for (int j = 0; j < PBW; ++j) {
+                const int jc = min(j, nv - 1);
+                pd[j] = a.data[r0 + jc];
+                pf[j] = has_flags ? (int)a.flags[r0 + jc] : 0;
+            }
+        };
+        const int nchunk = (ns + PCH - 1) / PCH;
+        fetch(0);
+        for (int c = 0; c < nchunk; ++c) {
+            __builtin_amdgcn_wave_barrier();
+            {
+                const bool sv = c * PCH + lane < ns;
+#pragma unroll
+                for (int j = 0; j < PBW; ++j) {
+                    const bool ok = sv && j < nv && pf[j] == 0;
+                    const float wv = ok ? 1.f : 0.f;
+                    sbuf[w][0][lane * PBW + j] = ok ? pd[j] : make_float2(0.f, 0.f);
+                    sbuf[w][1][lane * PBW + j] = make_float2(wv, wv);
+                    cnt[j] += ok ? 1 : 0;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int ng = min(PCH / 4, (ns - c * PCH + 3) / 4);
+            // operand factors of group gg, read one group ahead of their MFMAs
+            float2 P[PBW];
+#pragma unroll
+            for (int j = 0; j < PBW; ++j) P[j] = src[kk * PBW + j];
+            int gg = 0;
+            while (gg < ng) {
+                if (left == 0) {
+                    // re-base: the lane's sample enters a new time slot or has taken PREBASE steps
+                    while (f >= nch) {
+                        f -= nch;
+                        ++t;
+                    }
+                    if (is_m && 4 * (c * (PCH / 4) + gg) + kk < ns) {
+                        const double nu = f0 + f * df;
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) {
+                            if (j < nv) {
+                                const double* u = uvk + ((int64_t)t * nbl + bw + j) * 3;
+                                const double ph = u[0] * sg0 + u[1] * sg1 + u[2] * sg2;
+                                stp[j] = cis_quarter(ph * df4);
+                                const float2 e = cis_quarter(ph * nu);
+                                z[j] = make_float2(flux * e.x, flux * e.y);
+                            }
+                        }
+                    }
+                    left = min(PREBASE, (nch - f + 3) / 4);
+                }
+                // groups until the first of the wavefront's four sample rows needs a re-base
+                // (lanes of one row, l / 16, share their state)
+                int seg = min(__builtin_amdgcn_readlane(left, 0), __builtin_amdgcn_readlane(left, 16));
+                seg = min(seg, min(__builtin_amdgcn_readlane(left, 32), __builtin_amdgcn_readlane(left, 48)));
+                seg = min(seg, ng - gg);
+                if (gg == 0 && c + 1 < nchunk) fetch(c + 1);   // behind the re-base's uvw loads
+                for (int i = 0; i < seg; ++i, ++gg) {
+                    float vx[PBW], vy[PBW];
+#pragma unroll
+                    for (int j = 0; j < PBW; ++j) {
+                        vx[j] = z[j].x * P[j].x;
+                        vy[j] = z[j].y * P[j].y;
+                    }
+                    // next group's factors (the index wraps inside the slice after the last)
+                    const float2* pr = src + ((4 * gg + 4 + kk) * PBW & (PCH * PBW - 1));
+#pragma unroll
+                    for (int j = 0; j < PBW; ++j) P[j] = pr[j];
+#pragma unroll
+                    for (int j = 0; j < PBW; ++j) {
+                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx[j], vx[j], crr[j], 0, 0, 0);
+                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy[j], vy[j], crr[j], 0, 0, 0);
+                        cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx[j], vy[j], cri[j], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int j = 0; j < PBW; ++j) z[j] = cmul(z[j], stp[j]);
+                }
+                left -= seg;
+                f += 4 * seg;
+            }
+        }
+        // records of the wavefront's baselines, through its own LDS slice
+        __builtin_amdgcn_wave_barrier();
+        float* tile = reinterpret_cast<float*>(&sbuf[w][0][0]);
+#pragma unroll
+        for (int j = 0; j < PBW; ++j) {
+            const int b = bw + j;
+            int cj = cnt[j];
+#pragma unroll
+            for (int o = WAVE / 2; o > 0; o >>= 1) cj += __shfl_xor(cj, o, WAVE);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * kk + r;
+                tile[i * 16 + col] = crr[j][r];
+                tile[256 + i * 16 + col] = cri[j][r];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (b < nbl) {
+                float* rec = st.rec + ((int64_t)k * nbl + b) * RS;
+                for (int e = lane; e < 256; e += WAVE) {
+                    const int i = e >> 4, jj = e & 15;
+                    const float re = tile[i * 16 + jj];
+                    const float im = tile[256 + i * 16 + jj] - tile[256 + jj * 16 + i];
+                    if (i <= jj && jj < nd) {
+                        const int tt = tri(i, jj, nd);
+                        rec[2 * tt] = re;
+                        rec[2 * tt + 1] = im;
                     } else if (i < nd && jj == nd) {
                         rec[rec_z(nd) + 2 * i] = re;
                         rec[rec_z(nd) + 2 * i + 1] = im;
@@ -909,8 +1051,8 @@ __global__ void __launch_bounds__(DT) dd_reduce_kernel(DdArgs a, DdState st) {
 }
 
 // Residual rows of one tile: lane <-> baseline, weights g^c_p conj(g^c_q) per round.
-// PRED: the point-source model of a.pt, its phasors recomputed at every new time slot and
-// stepped from channel to channel (as in the Gram pass).
+// PRED: the point-source model of a.pt, its phasors taken from an FP64 phase at every new time
+// slot and every 16 channels, and stepped from channel to channel in between.
 template <bool PRED>
 __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int ctr_slot) {
     __shared__ double red[DT / WAVE];
@@ -939,16 +1081,16 @@ __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int 
                 const int64_t row = off + (int64_t)s * nbl + b;
                 if constexpr (PRED) {
                     const int tt = s / a.pt.n_chan, f = s - tt * a.pt.n_chan;
-                    if (s == T.s0 || f == 0) {
+                    if (s == T.s0 || f % 16 == 0) {
                         const double* u = a.pt.uvw + (((int64_t)T.k * a.pt.n_time + tt) * nbl + b) * 3;
 #pragma unroll
                         for (int c = 0; c < NDMAX; ++c)
                             if (c < nd) {
                                 const double* l = a.pt.lmn + 3 * c;
                                 const double ph = -6.283185307179586 * (u[0] * l[0] + u[1] * l[1] + u[2] * l[2]) / 299792458.0;
-                                const float2 e = cis_reduced(ph * (a.pt.freq0 + f * a.pt.dfreq));
+                                const float2 e = cis_quarter(ph * (a.pt.freq0 + f * a.pt.dfreq));
                                 z[c] = make_float2(a.pt.flux[c] * e.x, a.pt.flux[c] * e.y);
-                                step[c] = cis_reduced(ph * a.pt.dfreq);
+                                step[c] = cis_quarter(ph * a.pt.dfreq);
                             }
                     } else {
 #pragma unroll
@@ -1012,9 +1154,9 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const bool p16 = nd % 2 == 0 && reinterpret_cast<uintptr_t>(a.model) % 16 == 0;
     typedef void (*GramFn)(DdArgs, DdState, const int32_t*, const int32_t*);
     const bool pred = a.pt.uvw != nullptr;
-    GramFn gram = pred ? dd_gram_blk_kernel<true>
-                       : !bf ? dd_gram_blk_kernel<false> : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
-    const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), 0, nblk);
+    GramFn gram = pred ? dd_gram_pts_kernel
+                       : !bf ? dd_gram_blk_kernel : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
+    const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), 0, pred ? (int64_t)a.n_int * ((a.n_bl + PGB - 1) / PGB) : nblk);
     const size_t asm_ = ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
     hipLaunchKernelGGL(dd_init_kernel, dim3((std::max(a.n_int, nctr) + DT - 1) / DT), dim3(DT), 0, s, a, st, 1, nctr);

@@ -5,8 +5,9 @@ model from HBM.
 
 The predicted model carries ~1e-6 relative error (FP32 sine/cosine of an FP64-reduced phase,
 stepped from channel to channel and re-based at every time slot and every 16 channels), well
-inside the 1e-5 bound on gains.  Channel counts that are not multiples of the Gram pass's
-8-sample chunks put time-slot boundaries inside a chunk.
+inside the 1e-5 bound on gains.  The grids cover time slots shorter than the Gram pass's
+four-sample groups (1 and 2 channels), channel counts that are not multiples of four, and a
+200-channel slot in which the phasors are re-based inside the slot.
 """
 import sys
 
@@ -56,10 +57,10 @@ def oracle_model(P, k):
 
 @pytest.mark.parametrize("algo", ["cohjones", "alljones"])
 @pytest.mark.parametrize("mode", ["pass", "stats"])
-@pytest.mark.parametrize("n_chan", [8, 5])
-def test_points_lockstep(algo, mode, n_chan):
-    log(f"[points lockstep] algo={algo} mode={mode} n_chan={n_chan}")
-    P = problem(n_chan=n_chan, seed=1)
+@pytest.mark.parametrize("n_time,n_chan", [(3, 8), (3, 5), (5, 2), (12, 1), (1, 200)])
+def test_points_lockstep(algo, mode, n_time, n_chan):
+    log(f"[points lockstep] algo={algo} mode={mode} grid={n_time}x{n_chan}")
+    P = problem(n_time=n_time, n_chan=n_chan, seed=1)
     plan = wcal.plan_for(P, algo=algo, tol=0.0, max_iter=6, mode=mode)
     out = plan.solve_points(**points_args(P), data=P.data, flags=P.flags, gains=P.unit_gains())
     ref = plan.solve(P.data, P.model, P.flags, P.unit_gains())
