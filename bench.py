@@ -37,6 +37,16 @@ def gram_flop_per_row(n_corr: int, n_dir: int) -> float:
     return 4.0 * n_m * n_m + 8.0 * n_m * n_d
 
 
+def unit_gram_flop_per_row(n_corr: int, n_dir: int) -> float:
+    """Algorithmic Gram flops per visibility row as the per-unit figure of the roofline: for
+    scalar CohJones the per-antenna Nd x Nd Hermitian block (Eq. JHJ:DD:unpol) on both antennas
+    of the row, unique entries only, 8 flops per complex product: 8 Nd (Nd + 1) (880 at Nd = 10).
+    The polarized Gram has no such figure; it keeps the pass's own count (gram_flop_per_row)."""
+    if n_corr == 1:
+        return 8.0 * n_dir * (n_dir + 1)
+    return gram_flop_per_row(n_corr, n_dir)
+
+
 def gram_issued_flop_per_row(n_corr: int, n_dir: int) -> float:
     """Flops the MFMAs issue per row: per 4 samples three 16x16x4 MFMAs per diagonal
     16-column tile and three per off-diagonal tile pair (Gauss's complex product; the BF16
@@ -326,9 +336,11 @@ def main():
     kms, klaunch = prof[kcls]
     achieved = kbytes / (kms * 1e-3) / 1e9
     if dd:
-        useful = krows * gram_flop_per_row(P.n_corr, P.n_dir)
+        useful = krows * unit_gram_flop_per_row(P.n_corr, P.n_dir)
+        own = krows * gram_flop_per_row(P.n_corr, P.n_dir)
         issued = krows * gram_issued_flop_per_row(P.n_corr, P.n_dir)
         tfs = useful / (kms * 1e-3) / 1e12
+        tfs_own = own / (kms * 1e-3) / 1e12
         tfs_issued = issued / (kms * 1e-3) / 1e12
     conv = float((st & 1).float().mean())
     log(f"[bench] {ms_step:.3f} ms/step, {kname}: {kms / args.steps:.3f} ms/step over "
@@ -394,6 +406,7 @@ def main():
             "kernel_ms_per_launch": kms / max(klaunch, 1),
             "launches_per_step": klaunch / args.steps,
             "alg_flops_per_launch": useful / max(klaunch, 1),
+            "pass_alg_TFLOPs": tfs_own,
             "issued_TFLOPs": tfs_issued,
             "issued_frac": tfs_issued / peak,
         }
