@@ -654,7 +654,7 @@ __device__ __forceinline__ float wave_total(float x) {
     return (r0 + r1) + (r2 + r3);
 }
 
-constexpr int TRI_U = 8;    // chunks in flight per lane
+constexpr int TRI_U = 4;    // chunks in flight per lane (4 measured best of 2..16)
 
 // One unit of a tile (samples [s0, s1) of interval k) into this wavefront's slice
 // acc[na + 1][3]; G holds na + 1 gains.  Lanes past the end of a row load the row's last
