@@ -62,9 +62,34 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_only(text: str) -> str:
+    """C / C++ source without its comments (string literals kept), so that edits to comments
+    alone leave a kernel family's hash unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def source_hash(family: str) -> str:
     """sha256 of what decides a kernel family's memory traffic: its kernel sources, the plan
-    and launch code, and the public header."""
+    and launch code, and the public header, comments removed."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1502_06974_amd", "csrc")
@@ -72,7 +97,7 @@ def source_hash(family: str) -> str:
     files.append(os.path.join(ROOT, "include", "wcal.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+        h.update(_code_only(open(f, encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -229,9 +229,11 @@ int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
  * [l_d, m_d, n_d - 1]), for scalar CohJones / AllJones with the FP32 Gram.  The pass then
  * reads 9 bytes per row (data and flag) instead of 8 Nd + 9.  Every interval holds
  * n_time * n_chan samples, sample s = t * n_chan + f, channel f at freq0 + f * dfreq.  The
- * phase is formed in FP64 and reduced to [-pi, pi] before FP32 sine and cosine at the first
- * sample of each chunk and at every new time slot, and stepped across channels by one
- * complex multiply per sample (relative model error ~1e-6).  All arrays are device memory. */
+ * phase is formed in FP64 and reduced by quarter turns; sine and cosine of the remainder are
+ * FP32 Taylor series.  That happens at every new time slot and at least every 16 channels
+ * (the Gram pass: every 16 steps of 4 channels); in between, the phasor is stepped across
+ * channels by one complex multiply (relative model error ~1e-7).  All arrays are device
+ * memory. */
 typedef struct {
     int32_t n_time;      /* timeslots per interval                                      */
     int32_t n_chan;      /* channels per interval                                       */
