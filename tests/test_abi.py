@@ -73,6 +73,9 @@ def test_null_arguments():
     assert L.wcal_accumulate(*([None] * 12)) == wcal.EINVAL
     assert L.wcal_residual(*([None] * 8)) == wcal.EINVAL
     assert L.wcal_plan_rows(None) == -1
+    assert L.wcal_plan_smoothing(None, 1, 4, 0.0, 1.0) == wcal.EINVAL
+    assert L.wcal_solve_smooth(*([None] * 10)) == wcal.EINVAL
+    assert L.wcal_solve_points(None, None, *([None] * 8)) == wcal.EINVAL
     L.wcal_plan_destroy(None)
 
 
