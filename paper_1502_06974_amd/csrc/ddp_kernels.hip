@@ -311,16 +311,6 @@ __global__ void __launch_bounds__(DT) ddp_gram_r_kernel(DdArgs a, DdState st) {
 }
 
 // ------------------------------------------------------------------ per-antenna update
-// Gram entry (x, y) of a record, any x, y < 4 Nd + 4
-__device__ __forceinline__ double2 gram_at(const float* rec, int x, int y, int ncs) {
-    if (x <= y) {
-        const float* v = rec + 2 * tri(x, y, ncs);
-        return make_double2(v[0], v[1]);
-    }
-    const float* v = rec + 2 * tri(y, x, ncs);
-    return make_double2(v[0], -v[1]);
-}
-
 __device__ __forceinline__ double2 dcmulc(double2 a, double2 b) {   // conj(a) b
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
