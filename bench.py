@@ -196,6 +196,78 @@ def cpu_baseline(P, budget_s: float = 15.0):
                 seconds=round(t_used, 2))
 
 
+def _host_rows(P, k: int, nrows):
+    """The first nrows rows of interval k (all if None) as host complex128 arrays, in the
+    layout of Problem.interval."""
+    import numpy as np
+    a = int(P.row_off[k])
+    n = int(P.row_off[k + 1]) - a if nrows is None else nrows
+    ns = (n + P.n_bl - 1) // P.n_bl
+    a1 = P.ant1.cpu().numpy().astype(np.int64)
+    a2 = P.ant2.cpu().numpy().astype(np.int64)
+    return dict(d=P.data[a:a + n].cpu().numpy().astype(np.complex128),
+                m=P.model[a:a + n].cpu().numpy().astype(np.complex128),
+                p=np.tile(a1, ns)[:n], q=np.tile(a2, ns)[:n],
+                flags=(np.zeros(n, dtype=bool) if P.flags is None else P.flags[a:a + n].cpu().numpy() != 0))
+
+
+def cpu_baseline_all_cores(P, budget_s: float = 15.0):
+    """The same oracle, interval-parallel over the host cores (at most 16 worker processes, the
+    CPU share of one GPU; one BLAS thread each): whole intervals for StefCal, the first 32
+    samples of every interval for CohJones (8 for 2x2), one job per worker in flight, new jobs
+    dispatched for budget_s seconds; the jobs then running finish.  The figure is the summed
+    visibility-iterations over the wall time of the pool."""
+    import multiprocessing as mp
+    from concurrent.futures import FIRST_COMPLETED, ProcessPoolExecutor, wait
+    import numpy as np
+    from oracle import driver as glue
+    workers = max(1, min(16, os.cpu_count() or 1))
+    dd = P.n_dir > 1
+    algo = "cohjones" if dd else "stefcal"
+    nsel = (32 if P.n_corr == 1 else 8) * P.n_bl if dd else None
+    order = iter(np.random.default_rng(0).permutation(P.n_int).tolist())
+    g0 = P.unit_gains().cpu().numpy()
+    saved = {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for v in saved:
+        os.environ[v] = "1"
+    vis, n_done, busy = 0, 0, 0.0
+    try:
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            list(ex.map(glue.worker_ready, range(2 * workers)))
+            t0 = time.perf_counter()
+            pending = set()
+
+            def submit():
+                k = next(order, None)
+                if k is not None:
+                    job = (_host_rows(P, k, nsel), P.n_corr, P.n_dir, g0[k], algo, 1e-6, 100)
+                    pending.add(ex.submit(glue.solve_arrays, job))
+
+            for _ in range(workers):
+                submit()
+            while pending:
+                done, pending = wait(pending, return_when=FIRST_COMPLETED)
+                for f in done:
+                    v, dt = f.result()
+                    vis += v
+                    busy += dt
+                    n_done += 1
+                    if time.perf_counter() - t0 < budget_s:
+                        submit()
+            wall = time.perf_counter() - t0
+    finally:
+        for v, x in saved.items():
+            if x is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = x
+    what = (f"the first {nsel // P.n_bl} samples of {n_done} intervals" if dd else f"{n_done} whole intervals")
+    return dict(value=vis / wall, unit="vis-iter/s", cores=workers, kind="oracle",
+                sample=f"{what} of the same workload, unit start, tol 1e-6, {workers} worker processes "
+                       f"(one thread each), {busy / wall:.1f} of them busy on average",
+                seconds=round(wall, 2))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +279,8 @@ def main():
                     help="update cap (default 100; 300 with --smooth, whose updates converge slower)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-all-cores", action="store_true",
+                    help="skip the interval-parallel oracle run beside the one-process baseline")
     ap.add_argument("--mode", default="pass", choices=["pass", "stats"],
                     help="pass: every update streams all samples (the measured metric); "
                          "stats: per-baseline statistics once, updates on them")
@@ -461,6 +535,9 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_budget) if smooth is None else cpu_baseline_smooth(P, smooth)
+        if smooth is None and not args.no_cpu_all_cores:
+            log("[bench] timing the CPU oracle interval-parallel over the host cores")
+            out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(P, args.cpu_budget)
     line = json.dumps(out)
     print(line, flush=True)
     if args.out_json:

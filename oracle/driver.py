@@ -48,20 +48,40 @@ def gains_from_oracle(g, n_corr, n_dir, algo=None):
     return g[:, :, None]
 
 
+def _solver(algo, nc):
+    if algo == "stefcal":
+        return oc.stefcal_scalar if nc == 1 else oc.stefcal_2x2
+    if algo == "cohjones":
+        return oc.cohjones if nc == 1 else oc.cohjones_2x2
+    return oc.alljones if nc == 1 else oc.alljones_2x2
+
+
 def solve(problem, k, g0, algo="stefcal", tol=1e-6, max_iter=100, schedule="avg_first", flags=True):
     iv = problem.interval(k)
     nc, nd = problem.n_corr, problem.n_dir
     d, m = split(iv, nc, nd, algo)
     fl = iv["flags"] if flags else None
     g0o = gains_to_oracle(g0, nc, nd, algo)
-    s = SCHED[schedule]
-    if algo == "stefcal":
-        fn = oc.stefcal_scalar if nc == 1 else oc.stefcal_2x2
-    elif algo == "cohjones":
-        fn = oc.cohjones if nc == 1 else oc.cohjones_2x2
-    else:
-        fn = oc.alljones if nc == 1 else oc.alljones_2x2
-    return fn(d, m, iv["p"], iv["q"], fl, g0o, tol=tol, max_iter=max_iter, schedule=s)
+    return _solver(algo, nc)(d, m, iv["p"], iv["q"], fl, g0o, tol=tol, max_iter=max_iter, schedule=SCHED[schedule])
+
+
+def worker_ready(i):
+    """A no-op for starting a process pool before timing it."""
+    return i
+
+
+def solve_arrays(job):
+    """One interval (or the leading rows of one) solved from host arrays alone, for a pool of
+    worker processes: job = (iv, n_corr, n_dir, g0, algo, tol, max_iter) with iv holding d, m,
+    p, q and flags as Problem.interval gives them.  Returns (rows x updates, seconds)."""
+    import time
+    iv, nc, nd, g0, algo, tol, max_iter = job
+    d, m = split(iv, nc, nd, algo)
+    g0o = gains_to_oracle(g0, nc, nd, algo)
+    t0 = time.perf_counter()
+    o = _solver(algo, nc)(d, m, iv["p"], iv["q"], iv["flags"], g0o, tol=tol, max_iter=max_iter,
+                          schedule=oc.AVG_FIRST)
+    return d.shape[0] * o["n_iter"], time.perf_counter() - t0
 
 
 def accumulate(problem, k, g, flags=True, algo=None):
