@@ -307,7 +307,7 @@ def main():
         args.max_iter = 300 if args.smooth else 100
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(solution intervals are independent; see the sharding notes in DESIGN.md)",
+              "(solution intervals are independent: a batch shards by interval over GPUs with no exchange)",
               file=sys.stderr)
         sys.exit(2)
 
