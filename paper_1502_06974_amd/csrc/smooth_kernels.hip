@@ -19,6 +19,8 @@
 // over the cell's antennas, in FP64.  With noise the smoothed iterates keep turning along
 // these phases, which the plain relative change would never see stop.
 #include <cmath>
+#include <utility>
+#include <vector>
 
 #include "di_common.h"
 
@@ -87,6 +89,51 @@ __global__ void __launch_bounds__(SB) sm_conv_kernel(const float* __restrict__ i
     double acc = 0.0;
     for (int j = j0; j <= j1; ++j) acc += (double)taps[j < 0 ? -j : j] * (double)in[i + j * stride];
     out[i] = (float)acc;
+}
+
+// The same one-axis pass through LDS: a workgroup owns CT_C consecutive cells of one line of
+// the grid (a time slot along frequency, or a channel along time) and CT_E consecutive
+// (antenna, component) values, loads them with the kernel's halo once, and sums the taps
+// in the order of sm_conv_kernel (so the results are the same bits).  Radii up to CT_RMAX.
+constexpr int CT_C = 64;
+constexpr int CT_E = 64;
+constexpr int CT_RMAX = 64;
+__global__ void __launch_bounds__(SB) sm_conv_tile_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                                          int na, int ncell, int nf, int along_t, int r,
+                                                          const float* __restrict__ taps,
+                                                          const int32_t* active, int ntc, int nte, int nline) {
+    __shared__ float sh[(CT_C + 2 * CT_RMAX) * CT_E];
+    __shared__ float stap[CT_RMAX + 1];
+    int b = blockIdx.x;
+    const int te = b % nte;
+    b /= nte;
+    const int tc = b % ntc;
+    b /= ntc;
+    const int line = b % nline, k = b / nline;
+    if (!active[k]) return;
+    const int E = 3 * na;
+    const int len = along_t ? ncell / nf : nf;
+    const int64_t S = (int64_t)(along_t ? nf : 1) * E;
+    const int64_t base = ((int64_t)k * ncell + (along_t ? line : (int64_t)line * nf)) * E;
+    const int p0 = tc * CT_C, e0 = te * CT_E;
+    const int lo = max(0, p0 - r), hi = min(len, p0 + CT_C + r);   // cells loaded: [lo, hi)
+    const int ne = min(CT_E, E - e0);
+    for (int i = threadIdx.x; i <= r; i += SB) stap[i] = taps[i];
+    for (int i = threadIdx.x; i < (hi - lo) * CT_E; i += SB) {
+        const int pc = i / CT_E, e = i - pc * CT_E;
+        if (e < ne) sh[i] = in[base + (int64_t)(lo + pc) * S + e0 + e];
+    }
+    __syncthreads();
+    const int np = min(CT_C, len - p0);
+    for (int i = threadIdx.x; i < np * CT_E; i += SB) {
+        const int pc = i / CT_E, e = i - pc * CT_E;
+        if (e >= ne) continue;
+        const int pos = p0 + pc;
+        const int j0 = max(-r, -pos), j1 = min(r, len - 1 - pos);
+        double acc = 0.0;
+        for (int j = j0; j <= j1; ++j) acc += (double)stap[j < 0 ? -j : j] * (double)sh[(pos + j - lo) * CT_E + e];
+        out[base + (int64_t)pos * S + e0 + e] = (float)acc;
+    }
 }
 
 // Per (cell, antenna) of a chunk: the smoothed GN value, the schedule, the gains written in
@@ -326,11 +373,26 @@ int wcal_solve_smooth(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mod
         prof_begin(plan, WCAL_K_UPDATE, s);
         hipLaunchKernelGGL(sm_fold_kernel, dim3(nblk(nab)), dim3(SB), 0, s, (const float*)cp->d_partial, toff, nab, na,
                            ncell, (const int32_t*)sp->d_active, sp->d_flag, sp->d_ab);
-        hipLaunchKernelGGL(sm_conv_kernel, dim3(nblk(nab)), dim3(SB), 0, s, (const float*)sp->d_ab, sp->d_tmp, nab, na,
-                           ncell, sp->nf, 0, sp->rf, (const float*)(sp->d_taps + sp->rt + 1), (const int32_t*)sp->d_active);
-        hipLaunchKernelGGL(sm_conv_kernel, dim3(nblk(nab)), dim3(SB), 0, s, (const float*)sp->d_tmp, sp->d_ab, nab, na,
-                           ncell, sp->nf, 1, sp->rt, (const float*)sp->d_taps, (const int32_t*)sp->d_active);
-        hipLaunchKernelGGL(sm_update_kernel, dim3((unsigned)(p.n_int * sp->bpc)), dim3(SB), 0, s, (const float*)sp->d_ab,
+        // the two one-axis passes; an axis of radius 0 is the identity (its only tap is 1) and
+        // is skipped
+        float* cur = sp->d_ab;
+        float* spare = sp->d_tmp;
+        auto conv = [&](int along_t, int r, const float* taps) {
+            if (r <= CT_RMAX) {
+                const int len = along_t ? ncell / sp->nf : sp->nf;
+                const int nline = ncell / len, ntc = (len + CT_C - 1) / CT_C, nte = (3 * na + CT_E - 1) / CT_E;
+                hipLaunchKernelGGL(sm_conv_tile_kernel, dim3((unsigned)((int64_t)p.n_int * nline * ntc * nte)), dim3(SB),
+                                   0, s, (const float*)cur, spare, na, ncell, sp->nf, along_t, r, taps,
+                                   (const int32_t*)sp->d_active, ntc, nte, nline);
+            } else {
+                hipLaunchKernelGGL(sm_conv_kernel, dim3(nblk(nab)), dim3(SB), 0, s, (const float*)cur, spare, nab, na,
+                                   ncell, sp->nf, along_t, r, taps, (const int32_t*)sp->d_active);
+            }
+            std::swap(cur, spare);
+        };
+        if (sp->rf > 0) conv(0, sp->rf, (const float*)(sp->d_taps + sp->rt + 1));
+        if (sp->rt > 0) conv(1, sp->rt, (const float*)sp->d_taps);
+        hipLaunchKernelGGL(sm_update_kernel, dim3((unsigned)(p.n_int * sp->bpc)), dim3(SB), 0, s, (const float*)cur,
                            a.gains, na, ncell, sp->cpb, sp->bpc, p.schedule, it, (const int32_t*)sp->d_active,
                            sp->d_flag, sp->d_part);
         hipLaunchKernelGGL(sm_finish_kernel, dim3(p.n_int), dim3(SB), 0, s, (const double*)sp->d_part, sp->bpc,
