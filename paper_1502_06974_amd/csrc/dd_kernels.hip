@@ -160,17 +160,13 @@ __global__ void __launch_bounds__(DT) dd_gram_kernel(DdArgs a, DdState st, int o
     }
 }
 
-// ------------------------------------------------------------------ blocked Gram pass
-// The solve's Gram pass (no residual column).  A workgroup owns GB consecutive baselines of
-// one interval and walks its samples in chunks of GS: for each sample the model rows of the
-// GB baselines are one contiguous segment (GB * Nd complex), so the chunk is read with
-// consecutive addresses across the workgroup, staged in registers while the previous chunk
-// is consumed, and laid out in LDS as [sample][baseline][16 columns].  Wavefront w then
-// runs the MFMAs of baselines 4w .. 4w + 3 from LDS (lane l: column l % 16 of sample l / 16,
-// as in the per-baseline kernel above).
+// ------------------------------------------------------------------ Gram passes of the solve
+// Work split of the solve's Gram passes: a workgroup owns GB consecutive baselines of one
+// interval and walks its samples in chunks; for each sample the model rows of the GB
+// baselines are one contiguous segment (GB * Nd complex), so a chunk is read with
+// consecutive addresses across the workgroup.  Wavefront w runs the MFMAs of baselines
+// 4w .. 4w + 3 (lane l: column l % 16 of sample l / 16, as in the per-baseline kernel above).
 constexpr int GB = 16;                 // baselines per workgroup task
-constexpr int GS = 8;                  // samples per chunk (register-staged FP32 kernel)
-constexpr int GPT = (GS * GB * (NDMAX + 1) + DT - 1) / DT;   // staged elements per thread
 typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16 bits, round to nearest, ties to even (infinities and NaN stay non-finite)
@@ -211,155 +207,11 @@ __device__ __forceinline__ float2 cis_quarter(double x) {
     return make_float2((qi == 1 || qi == 2) ? -u : u, qi >= 2 ? -v : v);
 }
 
-// list: the intervals to process (n_list of them), or null for every interval in LPT order
-__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8))) dd_gram_blk_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
-    __shared__ float2 abuf[GS][GB][16];
-    __shared__ uint8_t fbuf[GS][GB];
-    __shared__ int s_task;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int nd = a.n_dir, nbl = a.n_bl;
-    const int RS = rec_floats(nd);
-    const int kk = lane >> 4;
-    const int col = lane & 15;
-    const int nbb = (nbl + GB - 1) / GB;
-    const int nint = list ? *n_list : a.n_int;
-    const int64_t ntask = (int64_t)nint * nbb;
-    if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
-    const bool has_flags = a.flags != nullptr;
-    const int nmod = GS * GB * nd;              // model elements of a chunk
-    const int nel = nmod + GS * GB;             // + data elements
-    // static decode of this thread's staged elements: chunk-relative global offset (in
-    // model or data elements) and a packed code (LDS slot | sample << 12 | baseline << 16;
-    // -1 for no element)
-    int goff[GPT], code[GPT];
-#pragma unroll
-    for (int r = 0; r < GPT; ++r) {
-        const int i = threadIdx.x + DT * r;
-        goff[r] = 0;
-        code[r] = -1;
-        if (i < nmod) {
-            const int sm = i / (GB * nd), e = i % (GB * nd);
-            goff[r] = sm * nbl * nd + e;
-            code[r] = ((sm * GB + e / nd) * 16 + e % nd) | (sm << 12) | ((e / nd) << 16);
-        } else if (i < nel) {
-            const int j = i - nmod, sm = j / GB, bl = j % GB;
-            goff[r] = sm * nbl + bl;
-            code[r] = ((sm * GB + bl) * 16 + nd) | (sm << 12) | (bl << 16);
-        }
-    }
-    const int fs = threadIdx.x / GB, fb = threadIdx.x % GB;   // flag staged by this thread
-    const bool fown = threadIdx.x < GS * GB;
-    float2* lds = &abuf[0][0][0];
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
-        __syncthreads();
-        const int task = __builtin_amdgcn_readfirstlane(s_task);
-        if (task >= ntask) break;
-        const int k = list ? list[task / nbb] : a.order[task / nbb];
-        const int b0 = (task % nbb) * GB;
-        const int64_t off = a.row_off[k];
-        const int ns = a.ns[k];
-        const int nch = (ns + GS - 1) / GS;
-        float2 stage[GPT];
-        uint8_t fstage = 1;
-        auto fetch = [&](int c) {
-            const int s0 = c * GS;
-            const int64_t row0 = off + (int64_t)s0 * nbl + b0;
-            const float2* mb = a.model + row0 * nd;
-            const float2* db = a.data + row0;
-#pragma unroll
-            for (int r = 0; r < GPT; ++r) {
-                const int cd = code[r];
-                const bool ok = cd >= 0 && s0 + ((cd >> 12) & 15) < ns && b0 + (cd >> 16) < nbl;
-                const int i = threadIdx.x + DT * r;
-                stage[r] = make_float2(0.f, 0.f);
-                if (ok) stage[r] = i < nmod ? load_at(mb, goff[r]) : load_at(db, goff[r]);
-            }
-            const bool fok = fown && s0 + fs < ns && b0 + fb < nbl;
-            fstage = 1;
-            if (fok) fstage = has_flags ? (uint8_t)(a.flags[row0 + (int64_t)fs * nbl + fb] != 0) : (uint8_t)0;
-        };
-        floatx4 crr[4], cri[4];
-        int cnt[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-            cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-            cnt[j] = 0;
-        }
-        fetch(0);
-        for (int c = 0; c < nch; ++c) {
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < GPT; ++r)
-                if (code[r] >= 0) lds[code[r] & 4095] = stage[r];
-            if (fown) fbuf[fs][fb] = fstage;
-            __syncthreads();
-            if (c + 1 < nch) fetch(c + 1);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int bl = 4 * w + j;
-#pragma unroll
-                for (int g = 0; g < GS / 4; ++g) {
-                    const int sl = 4 * g + kk;
-                    const bool use = !fbuf[sl][bl];
-                    float2 v = make_float2(0.f, 0.f);
-                    if (use && col <= nd) v = abuf[sl][bl][col];
-                    if (use && col == 0) ++cnt[j];
-                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
-                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
-                    cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
-                }
-            }
-        }
-        // epilogue: each wavefront writes the records of its four baselines through its own
-        // 2 x 256-float area of the (now free) staging buffer
-        __syncthreads();
-        float* tile = reinterpret_cast<float*>(lds) + w * 512;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = b0 + 4 * w + j;
-            int cj = cnt[j];
-#pragma unroll
-            for (int o = WAVE / 2; o > 0; o >>= 1) cj += __shfl_xor(cj, o, WAVE);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * (lane >> 4) + r;
-                tile[i * 16 + col] = crr[j][r];
-                tile[256 + i * 16 + col] = cri[j][r];
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (b < nbl) {
-                float* rec = st.rec + ((int64_t)k * nbl + b) * RS;
-                for (int e = lane; e < 256; e += WAVE) {
-                    const int i = e >> 4, jj = e & 15;
-                    const float re = tile[i * 16 + jj];
-                    const float im = tile[256 + i * 16 + jj] - tile[256 + jj * 16 + i];
-                    if (i <= jj && jj < nd) {
-                        const int t = tri(i, jj, nd);
-                        rec[2 * t] = re;
-                        rec[2 * t + 1] = im;
-                    } else if (i < nd && jj == nd) {
-                        rec[rec_z(nd) + 2 * i] = re;
-                        rec[rec_z(nd) + 2 * i + 1] = im;
-                    } else if (i == nd && jj == nd) {
-                        rec[rec_d2(nd)] = re;
-                    }
-                }
-                if (lane == 0) reinterpret_cast<int*>(rec)[rec_cnt(nd)] = cj;
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
-}
-
 // ------------------------------------------------------------------ predicted-model Gram pass
 // Point-source models (Sect. 3.2.1, m^d = S_d exp(-2 pi i (u . sigma_d) nu / c)) generated in
 // the MFMA operand layout.  Wavefront w of a task owns PBW consecutive baselines and walks
 // their samples four at a time, lane l holding column l % 16 of sample 4g + l / 16 (as in the
-// blocked pass).  A lane of model column d keeps one phasor per baseline for its own sample and
+// read-model passes).  A lane of model column d keeps one phasor per baseline for its own sample and
 // steps it by exp(-2 pi i phi 4 dfreq) from one group to the next; the phasor is re-based from
 // the FP64 phase whenever the lane's sample enters a new time slot and after PREBASE steps, so
 // the walk runs in segments between re-bases with a branch-free inner loop.  Data and flags
@@ -563,7 +415,7 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 // to even), accumulated in FP32.  With the MFMA work this small the pass is a stream: the
 // model rows are copied straight from HBM into LDS (global_load_lds), with no register
 // staging, so more workgroups fit per CU and hide each other's copy phases.  Same work split
-// as dd_gram_blk_kernel, chunks of GSD = 16 samples.  The model rows of a chunk land in LDS
+// and copy as dd_gram_dmaf_kernel, chunks of GSD = 16 samples.  The model rows of a chunk land in LDS
 // in their HBM order, [sample][baseline][Nd], as pieces of PIECE bytes: 16 when Nd is even
 // and the model array is 16-byte aligned (every sample's segment is then 16-byte aligned),
 // else 4.  Data and flags (9 B per row) go through registers.  Columns Nd + 1 and Nd + 2
@@ -572,10 +424,9 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 // and the update takes the residual form g + H^-1 J^H r: its fixed point is that of the
 // exact sums up to the fixed rounding of M, although H comes from BF16 products.  A single
 // BF16 column for r would make J^H r jump with the rounding of r as the gains move, and
-// the iteration would chatter above the tolerance instead of converging.  Needs Nd <= 13.  (With FP32 MFMAs the copy
-// and the products do not overlap inside a workgroup and the register-staged kernel is
-// faster; a double-buffered copy serialises, because the compiler waits for every
-// outstanding copy before any LDS read.)
+// the iteration would chatter above the tolerance instead of converging.  Needs Nd <= 13.
+// (A double-buffered copy serialises: the compiler waits for every outstanding copy before
+// any LDS read.)
 constexpr int GSD = 16;
 
 template <int PIECE>
@@ -714,6 +565,142 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
                     }
                 }
                 if (lane == 0) reinterpret_cast<int*>(rec)[rec_cnt(nd)] = cj;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// dynamic LDS of dd_gram_dmaf_kernel: a chunk's model rows, at least the 4 x 512-float
+// epilogue tiles
+inline size_t dmaf_smem_bytes(int nd) { return (size_t)GSD * GB * (nd > 4 ? nd : 4) * sizeof(float2); }
+
+
+// The FP32 Gram pass of the solve (no residual column): the model rows of a chunk of GSD
+// samples are copied straight from HBM into LDS (global_load_lds, no register staging, so
+// the copy costs no vector instructions, which on this part do not overlap the MFMAs).  Data and
+// flags go through registers; a chunk that holds a flagged or absent row (a block-wide OR at
+// the barrier) gets those rows' model values zeroed in LDS before use (a selection, so
+// non-finite values under a flag never reach a product).  Each lane reads its operand with
+// one precomputed base and stride: model column col < Nd, the data column Nd, or a zero slot.
+template <int PIECE>
+__global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+    extern __shared__ __align__(16) float2 mbuf[];   // GSD * GB * max(Nd, 4) (dmaf_smem_bytes)
+    __shared__ float2 dbuf[GSD * GB + 1];      // the last slot stays zero
+    __shared__ uint8_t fbuf[GSD][GB];
+    __shared__ int s_cnt[GB];
+    __shared__ int s_task;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int nd = a.n_dir, nbl = a.n_bl;
+    const int RS = rec_floats(nd);
+    const int kk = lane >> 4;
+    const int col = lane & 15;
+    const int nbb = (nbl + GB - 1) / GB;
+    const int nint = list ? *n_list : a.n_int;
+    const int64_t ntask = (int64_t)nint * nbb;
+    if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
+    const bool has_flags = a.flags != nullptr;
+    const int seg_bytes = GB * nd * 8;          // one sample's model segment
+    const int pps = seg_bytes / PIECE;          // pieces per sample
+    const int npc = GSD * pps;                  // pieces per chunk
+    const int ds = threadIdx.x / GB, db = threadIdx.x % GB;   // data / flag element of this thread
+    // this lane's operand: element (sample sl, baseline bl) at base[(sl GB + bl) * stride]
+    const float2* obase = col < nd ? mbuf + col : col == nd ? dbuf : dbuf + GSD * GB;
+    const int ostride = col < nd ? nd : col == nd ? 1 : 0;
+    if (threadIdx.x == 0) dbuf[GSD * GB] = make_float2(0.f, 0.f);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
+        if (threadIdx.x < GB) s_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const int task = __builtin_amdgcn_readfirstlane(s_task);
+        if (task >= ntask) break;
+        const int k = list ? list[task / nbb] : a.order[task / nbb];
+        const int b0 = (task % nbb) * GB;
+        const int64_t off = a.row_off[k];
+        const int ns = a.ns[k];
+        const int nch = (ns + GSD - 1) / GSD;
+        floatx4 crr[4], cri[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+        for (int c = 0; c < nch; ++c) {
+            const int s0 = c * GSD;
+            // model: pieces p = p0 + lane of the chunk, p0 uniform per wavefront; piece p lands
+            // at byte p * PIECE of mbuf
+            for (int p0 = w * WAVE; p0 < npc; p0 += DT) {
+                const int p = p0 + lane;
+                const int sm = p / pps, jb = (p - sm * pps) * PIECE;
+                const bool ok = p < npc && s0 + sm < ns && b0 + jb / (8 * nd) < nbl;
+                if (ok) {
+                    const char* src = reinterpret_cast<const char*>(a.model + (off + (int64_t)(s0 + sm) * nbl + b0) * nd) + jb;
+                    auto dst = (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(mbuf) + p0 * PIECE);
+                    if constexpr (PIECE == 16) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+                    else __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+                }
+            }
+            bool skip = true;
+            {
+                const bool ok = s0 + ds < ns && b0 + db < nbl;
+                const int64_t row = off + (int64_t)(s0 + ds) * nbl + b0 + db;
+                skip = !ok || (has_flags && a.flags[row] != 0);
+                dbuf[ds * GB + db] = skip ? make_float2(0.f, 0.f) : a.data[row];
+                fbuf[ds][db] = (uint8_t)skip;
+                if (!skip) atomicAdd(&s_cnt[db], 1);
+            }
+            // the model pieces have landed (the barrier waits for them); any row to clear?
+            if (__syncthreads_or(skip)) {
+                for (int e = threadIdx.x; e < GSD * GB * nd; e += DT) {
+                    const int rowc = e / nd;
+                    if (fbuf[rowc / GB][rowc % GB]) mbuf[e] = make_float2(0.f, 0.f);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int bl = 4 * w + j;
+#pragma unroll
+                for (int g = 0; g < GSD / 4; ++g) {
+                    const float2 v = obase[((4 * g + kk) * GB + bl) * ostride];
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
+                    crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
+                    cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
+                }
+            }
+            __syncthreads();     // every wavefront is done with this chunk before the next lands
+        }
+        // epilogue through each wavefront's own 2 x 256 floats of mbuf (free now)
+        float* tile = reinterpret_cast<float*>(mbuf) + w * 512;
+        for (int j = 0; j < 4; ++j) {
+            const int b = b0 + 4 * w + j;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * (lane >> 4) + r;
+                tile[i * 16 + col] = crr[j][r];
+                tile[256 + i * 16 + col] = cri[j][r];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (b < nbl) {
+                float* rec = st.rec + ((int64_t)k * nbl + b) * RS;
+                for (int e = lane; e < 256; e += WAVE) {
+                    const int i = e >> 4, jj = e & 15;
+                    const float re = tile[i * 16 + jj];
+                    const float im = tile[256 + i * 16 + jj] - tile[256 + jj * 16 + i];
+                    if (i <= jj && jj < nd) {
+                        const int t = tri(i, jj, nd);
+                        rec[2 * t] = re;
+                        rec[2 * t + 1] = im;
+                    } else if (i < nd && jj == nd) {
+                        rec[rec_z(nd) + 2 * i] = re;
+                        rec[rec_z(nd) + 2 * i + 1] = im;
+                    } else if (i == nd && jj == nd) {
+                        rec[rec_d2(nd)] = re;
+                    }
+                }
+                if (lane == 0) reinterpret_cast<int*>(rec)[rec_cnt(nd)] = s_cnt[4 * w + j];
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -1155,8 +1142,9 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     typedef void (*GramFn)(DdArgs, DdState, const int32_t*, const int32_t*);
     const bool pred = a.pt.uvw != nullptr;
     GramFn gram = pred ? dd_gram_pts_kernel
-                       : !bf ? dd_gram_blk_kernel : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
-    const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), 0, pred ? (int64_t)a.n_int * ((a.n_bl + PGB - 1) / PGB) : nblk);
+                       : !bf ? (p16 ? dd_gram_dmaf_kernel<16> : dd_gram_dmaf_kernel<4>) : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
+    const size_t gsm = !pred && !bf ? dmaf_smem_bytes(nd) : 0;
+    const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), gsm, pred ? (int64_t)a.n_int * ((a.n_bl + PGB - 1) / PGB) : nblk);
     const size_t asm_ = ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
     hipLaunchKernelGGL(dd_init_kernel, dim3((std::max(a.n_int, nctr) + DT - 1) / DT), dim3(DT), 0, s, a, st, 1, nctr);
@@ -1164,7 +1152,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const bool stats = plan->prob.mode == WCAL_MODE_STATS;
     if (stats) {
         prof_begin(plan, WCAL_K_STATS, s);
-        hipLaunchKernelGGL(gram, dim3(gg), dim3(DT), 0, s, a, st, (const int32_t*)nullptr, (const int32_t*)nullptr);
+        hipLaunchKernelGGL(gram, dim3(gg), dim3(DT), gsm, s, a, st, (const int32_t*)nullptr, (const int32_t*)nullptr);
         prof_end(plan, WCAL_K_STATS, s);
     }
     for (int it = 0; it < a.max_iter; ++it) {
@@ -1174,7 +1162,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
             const int32_t* lst = it == 0 ? nullptr : st.alist + (it & 1) * a.n_int;
             prof_begin(plan, WCAL_K_PASS, s);
             const int32_t* nl = st.ctr + dd_nlist_slot(it);
-            hipLaunchKernelGGL(gram, dim3(gg), dim3(DT), 0, s, a, sti, lst, nl);
+            hipLaunchKernelGGL(gram, dim3(gg), dim3(DT), gsm, s, a, sti, lst, nl);
             prof_end(plan, WCAL_K_PASS, s);
         }
         prof_begin(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);

@@ -398,7 +398,7 @@ const char* wcal_plan_pass_kernel(const wcal_plan* plan) {
     if (!plan) return "";
     const wcal_problem& p = plan->prob;
     if (p.algo != WCAL_STEFCAL && p.n_corr == 4) return ddp_pass_kernel_name(p.n_dir);
-    if (p.algo != WCAL_STEFCAL) return p.precision == WCAL_PREC_BF16_GRAM ? "dd_gram_dma_kernel" : "dd_gram_blk_kernel";
+    if (p.algo != WCAL_STEFCAL) return p.precision == WCAL_PREC_BF16_GRAM ? "dd_gram_dma_kernel" : "dd_gram_dmaf_kernel";
     if (di_stats_solve(plan)) return p.n_corr == 1 ? "di_stats_kernel<1>" : "di_stats_kernel<4>";
     if (plan->tri) return "di_tri_pass_kernel";
     return p.n_corr == 1 ? "di_pass_kernel<1>" : "di_pass_kernel<4>";
@@ -543,7 +543,7 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
         if (tri_out) *tri_out = plan->tri ? 1 : 0;
         return WCAL_OK;
     };
-    // CohJones / AllJones stream the rows in their own blocked Gram pass: nothing to tune
+    // CohJones / AllJones stream the rows in their own Gram pass: nothing to tune
     if (p.algo != WCAL_STEFCAL) return report();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const size_t gbytes = (size_t)p.n_int * p.n_dir * p.n_ant * p.n_corr * sizeof(wcal_c64);

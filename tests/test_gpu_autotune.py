@@ -61,7 +61,7 @@ def test_autotune_dd_and_bad_arguments():
     P = synth.dd_point(12, 3, n_time=2, n_chan=4, n_int=1, seed=33, device=DEV, fov_deg=2.0, disk_diam=2e4)
     plan = wcal.plan_for(P)
     choice = plan.autotune(P.data, P.model, P.flags, P.unit_gains(), n_updates=2)
-    assert choice["pass_kernel"] == "dd_gram_blk_kernel"
+    assert choice["pass_kernel"] == "dd_gram_dmaf_kernel"
     Q = CASES["pol"]()
     plan_q = wcal.plan_for(Q, max_iter=5)
     with pytest.raises(wcal.WcalError):
