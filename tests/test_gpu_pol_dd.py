@@ -188,6 +188,20 @@ def test_pol_dd_garbage_under_flags_is_bit_identical():
         assert torch.all(b["residual"][fl] == 0)
 
 
+def test_pol_dd_model_must_be_16_byte_aligned():
+    """The 2x2 Gram copies model rows to LDS in 16-byte pieces: a model array that is only
+    8-byte aligned is refused before any launch."""
+    log("[pol dd alignment]")
+    P = small(n_dir=2, seed=8)
+    buf = torch.empty(P.model.numel() + 1, dtype=P.model.dtype, device=DEV)
+    model_u = buf[1:].view(P.model.shape)
+    model_u.copy_(P.model)
+    assert model_u.data_ptr() % 16 == 8
+    plan = wcal.plan_for(P, algo="cohjones", tol=0.0, max_iter=2)
+    with pytest.raises(wcal.WcalError):
+        plan.solve(P.data, model_u, P.flags, unit(P))
+
+
 @pytest.mark.parametrize("algo", ["cohjones", "alljones"])
 def test_pol_dd_antenna_with_many_rows(algo):
     """Repeated baseline pairs give antenna 0 more rows than the per-antenna update stages
