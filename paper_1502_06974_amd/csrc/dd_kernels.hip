@@ -571,12 +571,16 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
     }
 }
 
+constexpr int GSF = 16;   // samples per chunk of dd_gram_dmaf_kernel
 // dynamic LDS of dd_gram_dmaf_kernel: a chunk's model rows, at least the 4 x 512-float
 // epilogue tiles
-inline size_t dmaf_smem_bytes(int nd) { return (size_t)GSD * GB * (nd > 4 ? nd : 4) * sizeof(float2); }
+inline size_t dmaf_smem_bytes(int nd) {
+    const size_t n = (size_t)GSF * GB * nd;
+    return (n > 1024 ? n : 1024) * sizeof(float2);
+}
 
 
-// The FP32 Gram pass of the solve (no residual column): the model rows of a chunk of GSD
+// The FP32 Gram pass of the solve (no residual column): the model rows of a chunk of GSF
 // samples are copied straight from HBM into LDS (global_load_lds, no register staging, so
 // the copy costs no vector instructions, which on this part do not overlap the MFMAs).  Data and
 // flags go through registers; a chunk that holds a flagged or absent row (a block-wide OR at
@@ -585,9 +589,9 @@ inline size_t dmaf_smem_bytes(int nd) { return (size_t)GSD * GB * (nd > 4 ? nd :
 // one precomputed base and stride: model column col < Nd, the data column Nd, or a zero slot.
 template <int PIECE>
 __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
-    extern __shared__ __align__(16) float2 mbuf[];   // GSD * GB * max(Nd, 4) (dmaf_smem_bytes)
-    __shared__ float2 dbuf[GSD * GB + 1];      // the last slot stays zero
-    __shared__ uint8_t fbuf[GSD][GB];
+    extern __shared__ __align__(16) float2 mbuf[];   // dmaf_smem_bytes(Nd)
+    __shared__ float2 dbuf[GSF * GB + 1];      // the last slot stays zero
+    __shared__ uint8_t fbuf[GSF][GB];
     __shared__ int s_cnt[GB];
     __shared__ int s_task;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -603,12 +607,11 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
     const bool has_flags = a.flags != nullptr;
     const int seg_bytes = GB * nd * 8;          // one sample's model segment
     const int pps = seg_bytes / PIECE;          // pieces per sample
-    const int npc = GSD * pps;                  // pieces per chunk
-    const int ds = threadIdx.x / GB, db = threadIdx.x % GB;   // data / flag element of this thread
+    const int npc = GSF * pps;                  // pieces per chunk
     // this lane's operand: element (sample sl, baseline bl) at base[(sl GB + bl) * stride]
-    const float2* obase = col < nd ? mbuf + col : col == nd ? dbuf : dbuf + GSD * GB;
+    const float2* obase = col < nd ? mbuf + col : col == nd ? dbuf : dbuf + GSF * GB;
     const int ostride = col < nd ? nd : col == nd ? 1 : 0;
-    if (threadIdx.x == 0) dbuf[GSD * GB] = make_float2(0.f, 0.f);
+    if (threadIdx.x == 0) dbuf[GSF * GB] = make_float2(0.f, 0.f);
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
@@ -620,7 +623,7 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
         const int b0 = (task % nbb) * GB;
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
-        const int nch = (ns + GSD - 1) / GSD;
+        const int nch = (ns + GSF - 1) / GSF;
         floatx4 crr[4], cri[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -628,7 +631,7 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
             cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
         for (int c = 0; c < nch; ++c) {
-            const int s0 = c * GSD;
+            const int s0 = c * GSF;
             // model: pieces p = p0 + lane of the chunk, p0 uniform per wavefront; piece p lands
             // at byte p * PIECE of mbuf
             for (int p0 = w * WAVE; p0 < npc; p0 += DT) {
@@ -642,18 +645,20 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
                     else __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
                 }
             }
-            bool skip = true;
-            {
-                const bool ok = s0 + ds < ns && b0 + db < nbl;
-                const int64_t row = off + (int64_t)(s0 + ds) * nbl + b0 + db;
-                skip = !ok || (has_flags && a.flags[row] != 0);
-                dbuf[ds * GB + db] = skip ? make_float2(0.f, 0.f) : a.data[row];
-                fbuf[ds][db] = (uint8_t)skip;
-                if (!skip) atomicAdd(&s_cnt[db], 1);
+            bool skip = false;
+            for (int i = threadIdx.x; i < GSF * GB; i += DT) {   // data and flag of row (i / GB, i % GB)
+                const int si = i / GB, bi = i - si * GB;
+                const bool ok = s0 + si < ns && b0 + bi < nbl;
+                const int64_t row = off + (int64_t)(s0 + si) * nbl + b0 + bi;
+                const bool sk = !ok || (has_flags && a.flags[row] != 0);
+                dbuf[i] = sk ? make_float2(0.f, 0.f) : a.data[row];
+                fbuf[si][bi] = (uint8_t)sk;
+                if (!sk) atomicAdd(&s_cnt[bi], 1);
+                skip = skip || sk;
             }
             // the model pieces have landed (the barrier waits for them); any row to clear?
             if (__syncthreads_or(skip)) {
-                for (int e = threadIdx.x; e < GSD * GB * nd; e += DT) {
+                for (int e = threadIdx.x; e < GSF * GB * nd; e += DT) {
                     const int rowc = e / nd;
                     if (fbuf[rowc / GB][rowc % GB]) mbuf[e] = make_float2(0.f, 0.f);
                 }
@@ -663,7 +668,7 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
             for (int j = 0; j < 4; ++j) {
                 const int bl = 4 * w + j;
 #pragma unroll
-                for (int g = 0; g < GSD / 4; ++g) {
+                for (int g = 0; g < GSF / 4; ++g) {
                     const float2 v = obase[((4 * g + kk) * GB + bl) * ostride];
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
