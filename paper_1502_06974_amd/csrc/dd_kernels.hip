@@ -226,9 +226,10 @@ constexpr int PCH = 64;   // samples per staged chunk: one per lane
 constexpr int PBW = 2;    // baselines per wavefront
 constexpr int PGB = (DT / WAVE) * PBW;   // baselines per task
 __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8))) dd_gram_pts_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
-    // per wavefront: [0] [sample][baseline] data, [1] [sample][baseline] (weight, weight);
-    // both together hold the 512-float record tile afterwards
-    __shared__ float2 sbuf[DT / WAVE][2][PCH * PBW];
+    // per wavefront: [0] [sample][baseline] data, [1] [sample][baseline] (weight, weight),
+    // each followed by two groups of padding that the read-ahead after a chunk's last two
+    // groups lands in (its values are never used); the slice also holds the 512-float record tile
+    __shared__ float2 sbuf[DT / WAVE][2][(PCH + 8) * PBW];
     __shared__ int s_task;
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -312,10 +313,13 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
             }
             __builtin_amdgcn_wave_barrier();
             const int ng = min(PCH / 4, (ns - c * PCH + 3) / 4);
-            // operand factors of group gg, read one group ahead of their MFMAs
-            float2 P[PBW];
+            // operand factors of groups gg (Pa) and gg + 1 (Pb), read two groups ahead of their MFMAs
+            float2 Pa[PBW], Pb[PBW];
 #pragma unroll
-            for (int j = 0; j < PBW; ++j) P[j] = src[kk * PBW + j];
+            for (int j = 0; j < PBW; ++j) {
+                Pa[j] = src[kk * PBW + j];
+                Pb[j] = src[(4 + kk) * PBW + j];
+            }
             int gg = 0;
             while (gg < ng) {
                 if (left == 0) {
@@ -345,15 +349,17 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                 seg = min(seg, min(__builtin_amdgcn_readlane(left, 32), __builtin_amdgcn_readlane(left, 48)));
                 seg = min(seg, ng - gg);
                 if (gg == 0 && c + 1 < nchunk) fetch(c + 1);   // behind the re-base's uvw loads
-                for (int i = 0; i < seg; ++i, ++gg) {
+                // one group: operands from z and the staged factors P, which then take group
+                // g + 2's (after a chunk's last two groups: the padding), three MFMAs per
+                // baseline, step z
+                auto group = [&](int g, float2 (&P)[PBW]) {
                     float vx[PBW], vy[PBW];
 #pragma unroll
                     for (int j = 0; j < PBW; ++j) {
                         vx[j] = z[j].x * P[j].x;
                         vy[j] = z[j].y * P[j].y;
                     }
-                    // next group's factors (the index wraps inside the slice after the last)
-                    const float2* pr = src + ((4 * gg + 4 + kk) * PBW & (PCH * PBW - 1));
+                    const float2* pr = src + (4 * g + 8 + kk) * PBW;
 #pragma unroll
                     for (int j = 0; j < PBW; ++j) P[j] = pr[j];
 #pragma unroll
@@ -364,6 +370,22 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                     }
 #pragma unroll
                     for (int j = 0; j < PBW; ++j) z[j] = cmul(z[j], stp[j]);
+                };
+                // two groups per trip (a loop-carried z then needs no register copies); after an
+                // odd count the next group's factors are in Pb
+                const int ge = gg + seg;
+                for (; gg + 1 < ge; gg += 2) {
+                    group(gg, Pa);
+                    group(gg + 1, Pb);
+                }
+                if (gg < ge) {
+                    group(gg++, Pa);
+#pragma unroll
+                    for (int j = 0; j < PBW; ++j) {
+                        const float2 t = Pa[j];
+                        Pa[j] = Pb[j];
+                        Pb[j] = t;
+                    }
                 }
                 left -= seg;
                 f += 4 * seg;
