@@ -108,7 +108,11 @@ def measured_traffic(key: str):
     except (OSError, KeyError, ValueError):
         return None
     family = key.split("_", 1)[0]
-    return rec["traffic_bytes_per_launch"] if rec.get("src_sha") == source_hash(family) else None
+    try:
+        sha = source_hash(family)
+    except OSError:    # sources not shipped: the record cannot be matched to this build
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("src_sha") == sha else None
 
 
 def log(*a):

@@ -48,6 +48,17 @@ def test_source_hash_and_traffic_records():
     assert bench.measured_traffic("no_such_kernel/no_such_workload") is None
 
 
+def test_traffic_record_without_sources_is_not_reported(tmp_path, monkeypatch):
+    # a tree that ships the records but not the kernel sources cannot match a record to its
+    # build: no traffic figure, and no crash
+    import json
+    (tmp_path / "profiles").mkdir()
+    rec = {"dd_gram_dmaf_kernel/cohjones_na64": {"traffic_bytes_per_launch": 1.0, "src_sha": "0" * 16}}
+    (tmp_path / "profiles" / "pmc_traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("dd_gram_dmaf_kernel/cohjones_na64") is None
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
