@@ -1121,10 +1121,15 @@ __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int 
                         for (int c = 0; c < NDMAX; ++c)
                             if (c < nd) r = csub(r, cmul(w[c], z[c]));
                     } else {
+                        // every model value of the row is requested before the first is used
+                        // (indices past the last direction repeat it and are not summed)
                         const float2* m = a.model + row * nd;
+                        float2 mv[NDMAX];
+#pragma unroll
+                        for (int c = 0; c < NDMAX; ++c) mv[c] = m[min(c, nd - 1)];
 #pragma unroll
                         for (int c = 0; c < NDMAX; ++c)
-                            if (c < nd) r = csub(r, cmul(w[c], m[c]));
+                            if (c < nd) r = csub(r, cmul(w[c], mv[c]));
                     }
                     part += nrm(r);
                 }

@@ -609,6 +609,7 @@ __global__ void __launch_bounds__(DT) ddp_chi2_bl_kernel(DdArgs a, DdState st) {
 // ------------------------------------------------------------------ residual pass
 // Persistent over the plan's tiles; per tile the interval's gains are staged in LDS and
 // lane <-> baseline walks the tile's samples: R = D - sum_d G^d_p M^d G^{dH}_q.
+constexpr int RB = 10;   // directions whose model blocks are loaded together
 __global__ void __launch_bounds__(DT) ddp_resid_kernel(DdArgs a, DdState st, int ctr_slot) {
     extern __shared__ __align__(16) float2 gsh[];
     __shared__ double red[DT / WAVE];
@@ -636,12 +637,21 @@ __global__ void __launch_bounds__(DT) ddp_resid_kernel(DdArgs a, DdState st, int
                 J2 R = J2{make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
                 if (!fl) {
                     R = load_j2(a.data, row);
-                    for (int d = 0; d < nd; ++d) {
-                        const J2 M = load_j2(a.model, row * nd + d);
-                        const float2* gp = gsh + (d * na + p) * 4;
-                        const float2* gq = gsh + (d * na + q) * 4;
-                        const J2 Gp{gp[0], gp[1], gp[2], gp[3]}, Gq{gq[0], gq[1], gq[2], gq[3]};
-                        R = jsub(R, mulH(mul(Gp, M), Gq));
+                    // the model blocks of RB directions are all requested before the first is
+                    // used (indices past the last direction repeat it and are not summed)
+                    for (int d0 = 0; d0 < nd; d0 += RB) {
+                        J2 M[RB];
+#pragma unroll
+                        for (int u = 0; u < RB; ++u) M[u] = load_j2(a.model, row * nd + min(d0 + u, nd - 1));
+#pragma unroll
+                        for (int u = 0; u < RB; ++u) {
+                            if (d0 + u < nd) {
+                                const float2* gp = gsh + ((d0 + u) * na + p) * 4;
+                                const float2* gq = gsh + ((d0 + u) * na + q) * 4;
+                                const J2 Gp{gp[0], gp[1], gp[2], gp[3]}, Gq{gq[0], gq[1], gq[2], gq[3]};
+                                R = jsub(R, mulH(mul(Gp, M[u]), Gq));
+                            }
+                        }
                     }
                     part += nrm(R.a) + nrm(R.b) + nrm(R.c) + nrm(R.d);
                 }

@@ -641,17 +641,24 @@ __device__ __forceinline__ float dpp_row_shr(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + N, 0xf, 0xf, true));
 }
 
-// Sum over the 64 lanes, returned uniformly.  Call with every lane active.
+// In the rows of ROWS: lane 15 of the row before (row broadcast, CTRL 0x142) or lane 31
+// (0x143); x itself in the other rows.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_row_bcast(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, ROWS, 0xf, false));
+}
+
+// Sum over the 64 lanes, returned uniformly: (r0 + r1) + (r2 + r3) of the four 16-lane row
+// sums r.  Call with every lane active.  Only lane 63 is read at the end; the rows a
+// broadcast leaves out hold values nothing reads.
 __device__ __forceinline__ float wave_total(float x) {
     x += dpp_row_shr<1>(x);
     x += dpp_row_shr<2>(x);
     x += dpp_row_shr<4>(x);
-    x += dpp_row_shr<8>(x);   // lane 16 r + 15 holds the sum of row r
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 15));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 31));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 47));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
-    return (r0 + r1) + (r2 + r3);
+    x += dpp_row_shr<8>(x);                  // lane 16 r + 15 holds the sum of row r
+    x += dpp_row_bcast<0x142, 0xa>(x);       // lane 31: r1 + r0, lane 63: r3 + r2
+    x += dpp_row_bcast<0x143, 0xc>(x);       // lane 63: (r3 + r2) + (r1 + r0)
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 constexpr int TRI_U = 4;    // chunks in flight per lane (4 measured best of 2..16)
