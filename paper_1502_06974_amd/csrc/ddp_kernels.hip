@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(DT) ddp_chi2_bl_kernel(DdArgs a, DdState st) {
 // ------------------------------------------------------------------ residual pass
 // Persistent over the plan's tiles; per tile the interval's gains are staged in LDS and
 // lane <-> baseline walks the tile's samples: R = D - sum_d G^d_p M^d G^{dH}_q.
-constexpr int RB = 10;   // directions whose model blocks are loaded together
+constexpr int RB = 10;   // directions loaded together: PND, one batch (as a loop: 151 VGPRs; as one block: 180)
 __global__ void __launch_bounds__(DT) ddp_resid_kernel(DdArgs a, DdState st, int ctr_slot) {
     extern __shared__ __align__(16) float2 gsh[];
     __shared__ double red[DT / WAVE];
