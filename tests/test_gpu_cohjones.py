@@ -90,6 +90,36 @@ def test_dd_lockstep(algo, mode):
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
 
+@pytest.mark.parametrize("nd", [11, 14])
+def test_dd_most_directions_lockstep(nd):
+    """The largest direction counts of the FP32 path: 11 (odd, the model copied in 4-byte pieces)
+    and 14 (the most the library takes, 16-byte pieces; every model value of a residual row
+    loaded without repeats).  Six updates from unit gains on both sides, gains, chi^2 and the
+    residual compared; one direction more is refused at plan creation."""
+    log(f"[dd most directions] nd={nd}")
+    P = small(seed=7, n_dir=nd, n_ant=16, flag_frac=0.05)
+    plan = wcal.plan_for(P, algo="cohjones", tol=0.0, max_iter=6)
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    g = out["gains"].cpu().numpy()
+    for k in range(P.n_int):
+        o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), algo="cohjones", tol=0.0, max_iter=6)
+        go = glue.gains_from_oracle(o["g"], 1, P.n_dir)
+        e = rel(g[k], go)
+        log(f"  interval {k}: vs oracle {e:.2e}")
+        assert e <= 1e-5, (k, e)
+        assert int(out["n_iter"][k]) == 6 and int(out["status"][k]) == o["status"]
+        assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
+        a, b = int(P.row_off[k]), int(P.row_off[k + 1])
+        res = out["residual"][a:b, 0].cpu().numpy()
+        assert np.abs(res - o["residual"]).max() <= 1e-4 * np.abs(o["residual"]).max()
+        assert np.all(res[P.interval(k)["flags"]] == 0)
+    if nd == 14:
+        Q = small(seed=7, n_dir=15, n_ant=16, n_int=1)
+        with pytest.raises(wcal.WcalError):
+            wcal.plan_for(Q, algo="cohjones")
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_cohjones_converged(mode):
     log(f"[cohjones converged] mode={mode}")
