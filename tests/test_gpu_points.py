@@ -86,6 +86,30 @@ def test_points_lockstep(algo, mode, n_time, n_chan):
         assert np.all(res[iv["flags"]] == 0)
 
 
+def test_points_most_directions_lockstep():
+    """14 point sources, the most the library takes: 14 model lanes, the data lane at column 14,
+    one padding lane.  Six updates on both sides against the oracle on the model of the
+    definition, and against the solve that reads the same model from HBM."""
+    log("[points most directions] nd=14")
+    P = problem(n_dir=14, n_ant=16, n_time=3, n_chan=8, seed=5)
+    plan = wcal.plan_for(P, algo="cohjones", tol=0.0, max_iter=6)
+    out = plan.solve_points(**points_args(P), data=P.data, flags=P.flags, gains=P.unit_gains())
+    ref = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    g = out["gains"][:, :, :, 0].cpu().numpy()
+    e_ref = rel(g, ref["gains"][:, :, :, 0].cpu().numpy())
+    log(f"  vs model read from HBM: {e_ref:.2e}")
+    assert e_ref <= 1e-5
+    for k in range(P.n_int):
+        iv = P.interval(k)
+        o = oc.cohjones(iv["d"][:, 0], oracle_model(P, k), iv["p"], iv["q"], iv["flags"],
+                        np.ones((P.n_dir, P.n_ant), complex), tol=0.0, max_iter=6)
+        e = rel(g[k], o["g"])
+        log(f"  interval {k}: vs oracle {e:.2e}")
+        assert e <= 1e-5
+        assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
+
+
 def test_points_na64_full_size():
     """cohjones_na64 at full size (30 x 64 samples per interval): the predicted-model solve
     reaches the same solution as the solve that reads the model, and noise-free gains."""
