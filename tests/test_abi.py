@@ -50,6 +50,11 @@ def _create(n_ant, a1, a2, ns, **kw):
     ([0, 0, 1], [1, 2, 2], [2], {"n_dir": 2}, wcal.EINVAL),            # StefCal with 2 directions
     ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_corr": 4, "precision": 1}, wcal.EINVAL),  # 2x2 DD + BF16
     ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_corr": 4, "n_dir": 11}, wcal.ESHAPE),     # 2x2 DD, Nd > 10
+    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_dir": 15}, wcal.ESHAPE),                  # scalar DD, Nd > 14
+    ([0, 0, 1], [1, 2, 2], [2], {"algo": 1, "n_dir": 14, "precision": 1}, wcal.ESHAPE),  # BF16 Gram, Nd > 13
+    ([0, 0, 1], [1, 2, 2], [], {}, wcal.EINVAL),                                          # no interval
+    ([], [], [2], {}, wcal.EINVAL),                                                       # no baseline
+    ([0, 0, 1], [1, 2, 2], [2], {"max_iter": 100001}, wcal.ESHAPE),
     ([0, 0, 1], [1, 2, 2], [2], {"max_iter": 0}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"tol": -1.0}, wcal.EINVAL),
     ([0, 0, 1], [1, 2, 2], [2], {"schedule": 7}, wcal.EINVAL),
@@ -63,6 +68,11 @@ def test_plan_validation_errors(a1, a2, ns, kw, code):
     assert rc == code
     assert not h.value
     assert len(wcal.lib().wcal_last_error()) > 0
+
+
+def test_plan_needs_two_antennas():
+    rc, h = _create(1, [0], [0], [2])
+    assert rc == wcal.EINVAL and not h.value
 
 
 def test_null_arguments():
