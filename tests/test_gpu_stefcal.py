@@ -325,6 +325,31 @@ def test_triangle_pass_lockstep(n_ant, ns, monkeypatch):
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
 
+@pytest.mark.parametrize("tri", ["1", "0"])
+@pytest.mark.parametrize("n_ant", [2, 3])
+def test_smallest_arrays_lockstep(n_ant, tri, monkeypatch):
+    """Two antennas (one baseline: a triangle of one row of length 1) and three, through the
+    triangle pass and the generic pass, scalar and 2x2: six updates on both sides."""
+    log(f"[smallest arrays] n_ant={n_ant} triangle={tri}")
+    monkeypatch.setenv("WCAL_TRI", tri)
+    for kind in ("scalar", "pol"):
+        P = make(kind, n_ant, [1, 4], flag_frac=0.0, seed=13)
+        plan = wcal.plan_for(P, tol=0.0, max_iter=6)
+        out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+        torch.cuda.synchronize()
+        g = out["gains"].cpu().numpy()
+        nc = P.n_corr
+        for k in range(P.n_int):
+            o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=6)
+            go = glue.gains_from_oracle(o["g"], nc, 1)
+            assert rel(g[k], go) <= 1e-5, (kind, k, rel(g[k], go))
+            assert int(out["n_iter"][k]) == 6 and int(out["status"][k]) == o["status"]
+            # one baseline can be fitted exactly: chi^2 then sits at the FP32 rounding of the
+            # residual, so the bound has a floor at 1e-9 of the data power
+            power = float(np.sum(np.abs(P.interval(k)["d"]) ** 2))
+            assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"] + 1e-9 * power
+
+
 def test_triangle_pass_split_tiles(monkeypatch):
     """Tiles holding one unit each (a 700-row target) give the same updates."""
     log("[triangle tiles]")
