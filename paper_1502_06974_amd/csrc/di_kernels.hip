@@ -741,6 +741,102 @@ __device__ __forceinline__ void tri_unit(const DiArgs& a, const Tile& T, const T
     }
 }
 
+// Paired rows (n_ant >= TRI_PAIR_MIN): packed row r holds triangle row b = n_ant - 2 - r
+// followed by row r, n_ant entries in all (row r alone when b == r), so every chunk but the
+// last of the middle row is full.  A lane's entry is in row b or row r; each row's sum builds
+// up in its own lane share (rb_, ra_) and both are reduced when the packed row ends; lane
+// 2 (r - p0) keeps row r's total and lane 2 (r - p0) + 1 row b's.  With n_ant >= 127 the two
+// rows of a chunk never share a column antenna, so the column read-modify-writes of a chunk
+// stay distinct.  The unit's [p0, p1) counts packed rows.
+__device__ __forceinline__ void tri_unit_paired(const DiArgs& a, const Tile& T, const TriUnit& U, const float2* G,
+                                                float* acc) {
+    const int na = a.n_ant;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t off = a.row_off[T.k];
+    const bool has_flags = a.flags != nullptr;
+    float ra0 = 0.f, ra1 = 0.f, ra2 = 0.f;    // this lane's share of row r's sum
+    float rb0 = 0.f, rb1 = 0.f, rb2 = 0.f;    // and of row b's
+    float pr0 = 0.f, pr1 = 0.f, pr2 = 0.f;    // totals of the unit's row 2 (r - p0) + (lane & 1)
+    float m2 = 0.f, tr = 0.f, ti = 0.f;       // sum|m|^2, sum conj(m) d of the current entry
+    int r = U.p0, j = 0, s = T.s0;
+    while (r < U.p1) {
+        float2 d[TRI_U], m[TRI_U];
+        bool use[TRI_U], inb[TRI_U], end_e[TRI_U], end_r[TRI_U];
+        int pu[TRI_U], qu[TRI_U], ru[TRI_U];
+        int rr = r, jj = j, ss = s;
+#pragma unroll
+        for (int u = 0; u < TRI_U; ++u) {
+            const bool in = rr < U.p1;
+            const int ra = in ? rr : U.p1 - 1;           // a packed row that exists
+            const int rb = na - 2 - ra;
+            const int la = na - 1 - ra, lb = rb > ra ? ra + 1 : 0;
+            const int x = 64 * jj + lane;                // position in the packed row
+            const bool valid = in && x < la + lb;
+            const bool ib = x < lb;
+            const int prow = ib ? rb : ra, c = ib ? x : x - lb;
+            const int64_t rowbase = off + (int64_t)ss * a.n_bl;
+            const int64_t ba = rowbase + (int64_t)ra * na - (int64_t)ra * (ra + 1) / 2;
+            const int64_t bb = rowbase + (int64_t)rb * na - (int64_t)rb * (rb + 1) / 2;
+            const int64_t at = valid ? (ib ? bb : ba) + c : ba + la - 1;   // else row r's last element
+            d[u] = a.data[at];
+            m[u] = a.model[at];
+            use[u] = valid && !(has_flags && a.flags[at] != 0);
+            inb[u] = valid && ib;
+            pu[u] = valid ? prow : ra;
+            qu[u] = valid ? prow + 1 + c : na;
+            ru[u] = ra;
+            end_e[u] = in && ss + 1 == T.s1;
+            end_r[u] = end_e[u] && 64 * (jj + 1) >= la + lb;
+            if (in && ++ss == T.s1) {
+                ss = T.s0;
+                if (64 * (++jj) >= la + lb) { jj = 0; ++rr; }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < TRI_U; ++u) {
+            if (use[u]) {
+                m2 += nrm(m[u]);
+                const float2 t = ccmul(m[u], d[u]);     // conj(m) d
+                tr += t.x;
+                ti += t.y;
+            }
+            if (end_e[u]) {                             // entry (pu, qu) complete: contract
+                const float2 gp = G[pu[u]];
+                const float2 gq = G[qu[u]];
+                const float2 sv = make_float2(tr, ti);
+                const float2 cp = cmul(gq, sv);
+                const float2 cq = cmulc(gp, sv);        // g_p conj(s)
+                const float c0 = nrm(gq) * m2;
+                if (inb[u]) { rb0 += c0; rb1 += cp.x; rb2 += cp.y; }
+                else { ra0 += c0; ra1 += cp.x; ra2 += cp.y; }
+                float* dq = acc + qu[u] * 3;
+                dq[0] += nrm(gp) * m2;
+                dq[1] += cq.x;
+                dq[2] += cq.y;
+                m2 = 0.f; tr = 0.f; ti = 0.f;
+            }
+            if (end_r[u]) {                             // packed row complete: reduce both sums
+                const float a0 = wave_total(ra0), a1 = wave_total(ra1), a2 = wave_total(ra2);
+                const float b0 = wave_total(rb0), b1 = wave_total(rb1), b2 = wave_total(rb2);
+                const int slot = 2 * (ru[u] - U.p0);
+                if (lane == slot) { pr0 = a0; pr1 = a1; pr2 = a2; }
+                if (lane == slot + 1) { pr0 = b0; pr1 = b1; pr2 = b2; }
+                ra0 = 0.f; ra1 = 0.f; ra2 = 0.f;
+                rb0 = 0.f; rb1 = 0.f; rb2 = 0.f;
+            }
+        }
+        r = rr; j = jj; s = ss;
+    }
+    if (lane < 2 * (U.p1 - U.p0)) {
+        const int rw = U.p0 + (lane >> 1), rbw = na - 2 - rw;
+        const int p = (lane & 1) ? rbw : rw;
+        if (!((lane & 1) && rbw <= rw)) {             // a middle row has no partner
+            float* dst = acc + p * 3;
+            dst[0] += pr0; dst[1] += pr1; dst[2] += pr2;
+        }
+    }
+}
+
 template <int NC>
 __device__ void finish_interval(const DiArgs& a, int it, int k, int t0, int t1, const float* acc, float2* G,
                                 float2* Gn, double* red, int* s_flags, int* s_pos);
@@ -778,7 +874,10 @@ __global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit
         for (int i = threadIdx.x; i <= na; i += blockDim.x) G[i] = i < na ? gk[i] : make_float2(0.f, 0.f);
         for (int i = threadIdx.x; i < nw * ns; i += blockDim.x) acc[i] = 0.f;
         __syncthreads();
-        for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
+        if (na >= TRI_PAIR_MIN)
+            for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit_paired(a, T, units[u], G, myacc);
+        else
+            for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
         __syncthreads();
         if constexpr (FUSED) {
             // fold the wavefront slices into the first, in wavefront order

@@ -168,11 +168,15 @@ static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
         // order, so the round-robin share of each of the four wavefronts of a workgroup is
         // even
         const int32_t target = 8;
+        // rows, or packed rows (row n_ant - 2 - r with row r) from TRI_PAIR_MIN antennas on
+        const bool paired = p.n_ant >= TRI_PAIR_MIN;
+        const int32_t nrows = paired ? p.n_ant / 2 : p.n_ant - 1;
         std::vector<TriUnit> raw;
-        for (int32_t r0 = 0; r0 < p.n_ant - 1;) {
+        for (int32_t r0 = 0; r0 < nrows;) {
             int32_t r1 = r0, ent = 0, chunks = 0;
-            while (r1 < p.n_ant - 1 && r1 - r0 < 64) {
-                const int32_t len = p.n_ant - 1 - r1, ch = (len + 63) / 64;
+            while (r1 < nrows && r1 - r0 < 32) {
+                const int32_t len = !paired ? p.n_ant - 1 - r1 : (p.n_ant - 2 - r1 > r1 ? p.n_ant : p.n_ant - 1 - r1);
+                const int32_t ch = (len + 63) / 64;
                 if (r1 > r0 && chunks + ch > target) break;
                 ent += len;
                 chunks += ch;

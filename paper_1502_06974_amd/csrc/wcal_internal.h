@@ -20,7 +20,9 @@ void prof_begin(const wcal_plan* plan, int cls, hipStream_t s);
 void prof_end(const wcal_plan* plan, int cls, hipStream_t s);
 
 // A unit of the triangle pass (baselines in the canonical order: all pairs p < q,
-// p-major, q increasing): the whole rows p in [p0, p1) of the triangle, at most 64.
+// p-major, q increasing): the whole rows p in [p0, p1) of the triangle, at most 64; from
+// TRI_PAIR_MIN antennas on, packed rows r in [p0, p1), each row n_ant - 2 - r and row r.
+constexpr int TRI_PAIR_MIN = 127;
 struct TriUnit {
     int32_t p0, p1, entries, chunks;   // chunks: sum over rows of ceil(length / 64)
 };
