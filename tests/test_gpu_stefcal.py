@@ -305,7 +305,9 @@ def test_small_tiles_split_intervals(tile_rows, monkeypatch):
 # ------------------------------------------------------------------ triangle pass
 # Scalar StefCal with every pair p < q in p-major order runs the triangle pass (by default
 # from 64 antennas; WCAL_TRI=1 forces it for any canonical table, 0 disables it).
-TRI_CASES = [(12, [1, 1, 3]), (64, [1, 3]), (100, [1, 2, 5, 1]), (130, [1, 2])]
+# from 127 antennas on the pass walks packed rows: 127 and 129 (odd: every row has a partner)
+# and 130 (even: the middle row walks alone)
+TRI_CASES = [(12, [1, 1, 3]), (64, [1, 3]), (100, [1, 2, 5, 1]), (127, [2, 1]), (129, [1, 3]), (130, [1, 2])]
 
 
 @pytest.mark.parametrize("n_ant,ns", TRI_CASES)
