@@ -30,6 +30,8 @@ def same(a, b):
 CASES = {
     "scalar": lambda: synth.scalar_di(30, [3, 10, 1], sigma=0.01, flag_frac=0.1, seed=21, device=DEV),
     "triangle": lambda: synth.scalar_di(80, [1, 1, 4], sigma=0.01, flag_frac=0.1, seed=22, device=DEV),
+    # from 127 antennas on the triangle pass walks packed rows
+    "triangle_paired": lambda: synth.scalar_di(130, [1, 1, 4], sigma=0.01, flag_frac=0.1, seed=23, device=DEV),
     "pol": lambda: synth.pol_di(24, [2, 9, 5], sigma=0.01, flag_frac=0.1, seed=23, device=DEV),
     "cohjones": lambda: synth.dd_point(12, 3, n_time=3, n_chan=4, n_int=2, seed=24, device=DEV, flag_frac=0.05,
                                        fov_deg=2.0, disk_diam=2e4),
