@@ -744,7 +744,7 @@ __device__ __forceinline__ void tri_unit(const DiArgs& a, const Tile& T, const T
 // Paired rows (n_ant >= TRI_PAIR_MIN): packed row r holds triangle row b = n_ant - 2 - r
 // followed by row r, n_ant entries in all (row r alone when b == r), so every chunk but the
 // last of the middle row is full.  A lane's entry is in row b or row r; each row's sum builds
-// up in its own lane share (rb_, ra_) and both are reduced when the packed row ends; lane
+// up in its own lane share (ra0..2, rb0..2), both reduced when the packed row ends; lane
 // 2 (r - p0) keeps row r's total and lane 2 (r - p0) + 1 row b's.  With n_ant >= 127 the two
 // rows of a chunk never share a column antenna, so the column read-modify-writes of a chunk
 // stay distinct.  The unit's [p0, p1) counts packed rows.
