@@ -909,3 +909,122 @@ def test_bins_and_channels_round_trip():
     cp = np.exp(1j * rng.uniform(-np.pi, np.pi, n_int))[:, None]
     assert np.allclose(mlp.channels_to_bins(g * cp, n_ant, bw, 2), mlp.channels_to_bins(g, n_ant, bw, 2),
                        atol=1e-13)
+
+
+# ------------------------------------------------------------------ residuals and chi^2
+def _noise_pair(make, **kw):
+    """The same synthetic problem with and without its noise (the generator draws the noise
+    last, so the sky and the gains are the same draws)."""
+    clean = make(noise=False, dtype=torch.complex128, **kw)
+    noisy = make(noise=True, dtype=torch.complex128, **kw)
+    return clean, noisy
+
+
+def test_residual_2x2_is_the_noise_at_the_true_gains():
+    """Eq. cal:DI:pol: at the true Jones matrices the residual of the data is exactly the
+    noise the generator added (its own evaluation of D = G_p M G_q^H + N), the residual of
+    noise-free data vanishes, and at other gains R = D - f(G) with f the vectorised model
+    of the definition layer.  Flagged rows are 0 and chi^2 sums ||R||_F^2 over the rest."""
+    clean, noisy = _noise_pair(lambda **k: synth.pol_di(6, [3, 2], sigma=0.05, seed=21, **k))
+    for k in range(2):
+        ivc, ivn = clean.interval(k), noisy.interval(k)
+        Gt = ivc["g_true"][0].reshape(-1, 2, 2)
+        M = ivc["m"][:, 0].reshape(-1, 2, 2)
+        p, q = ivc["p"], ivc["q"]
+        R0, chi0 = oc.residual_2x2(ivc["d"].reshape(-1, 2, 2), M, p, q, None, Gt)
+        assert chi0 < 1e-24 and np.abs(R0).max() < 1e-12
+        Dn = ivn["d"].reshape(-1, 2, 2)
+        noise = Dn - ivc["d"].reshape(-1, 2, 2)
+        R, chi = oc.residual_2x2(Dn, M, p, q, None, Gt)
+        assert np.allclose(R, noise, rtol=0, atol=1e-13)
+        assert np.isclose(chi, np.sum(np.abs(noise) ** 2), rtol=1e-12)
+    # arbitrary gains: against the definition layer's vec(G_p M G_q^H)
+    G = cn(6, 2, 2) + np.eye(2)
+    R, _ = oc.residual_2x2(Dn, M, p, q, None, G)
+    f = oj.model_2x2(oj.vec(G).reshape(-1), M, p, q, 6)
+    assert np.allclose(oj.vec(R).reshape(-1), oj.vec(Dn).reshape(-1) - f, atol=1e-12)
+    fl = rng.random(p.size) < 0.3
+    Rf, chif = oc.residual_2x2(Dn, M, p, q, fl, G)
+    assert np.all(Rf[fl] == 0) and np.array_equal(Rf[~fl], R[~fl])
+    assert np.isclose(chif, np.sum(np.abs(R[~fl]) ** 2), rtol=1e-13)
+
+
+def test_residual_dd_is_the_noise_at_the_true_gains():
+    """Eq. cal:dd:unpol: at the true per-direction gains the residual is exactly the noise
+    the generator added to its point-source sky, the residual of noise-free data vanishes,
+    and at other gains r = d - f(g) with f the DD model of the definition layer."""
+    mk = lambda **k: synth.dd_point(7, 3, n_time=2, n_chan=3, n_int=1, seed=22,
+                                    noise_frac=0.02, **k)
+    clean, noisy = _noise_pair(mk)
+    ivc, ivn = clean.interval(0), noisy.interval(0)
+    gt = ivc["g_true"][:, :, 0]
+    m, p, q = ivc["m"][:, :, 0], ivc["p"], ivc["q"]
+    r0, chi0 = oc.residual_dd(ivc["d"][:, 0], m, p, q, None, gt)
+    assert chi0 < 1e-24 and np.abs(r0).max() < 1e-12
+    dn = ivn["d"][:, 0]
+    noise = dn - ivc["d"][:, 0]
+    r, chi = oc.residual_dd(dn, m, p, q, None, gt)
+    assert np.allclose(r, noise, rtol=0, atol=1e-13)
+    assert np.isclose(chi, np.sum(np.abs(noise) ** 2), rtol=1e-12)
+    nd, na = gt.shape
+    g = cn(nd, na) + 1.0
+    r, _ = oc.residual_dd(dn, m, p, q, None, g)
+    f = oj.model_dd(g.T.reshape(-1), m, p, q, nd, na)
+    assert np.allclose(r, dn - f, atol=1e-12)
+    fl = rng.random(p.size) < 0.3
+    rf, chif = oc.residual_dd(dn, m, p, q, fl, g)
+    assert np.all(rf[fl] == 0) and np.array_equal(rf[~fl], r[~fl])
+    assert np.isclose(chif, np.sum(np.abs(r[~fl]) ** 2), rtol=1e-13)
+
+
+def test_accumulate_2x2_jhr_is_the_explicit_jacobian_product():
+    """Sect. 4.2-4.3: the top half of J^H r, with J the numerical Wirtinger Jacobian of
+    the vectorised model vec(G_p M G_q^H), holds vec(sum R Y^H) per antenna (the reading of
+    the update order); at the LS minimum (converged polarized StefCal) it vanishes."""
+    na, ns = 4, 3
+    p, q = np.triu_indices(na, 1)
+    p, q = np.tile(p, ns), np.tile(q, ns)
+    G = cn(na, 2, 2) + np.eye(2)
+    M = cn(p.size, 2, 2)
+    D = cn(p.size, 2, 2)
+    z = oj.vec(G).reshape(-1)
+    f = lambda zz: oj.model_2x2(zz, M, p, q, na)
+    J = oj.full_jacobian(*oj.wirtinger_jacobian(f, z))
+    r = oj.vec(D).reshape(-1) - f(z)
+    JHr = J.conj().T @ np.concatenate([r, np.conj(r)])
+    acc = oc.accumulate_2x2(D, M, p, q, None, G)
+    for a in range(na):
+        assert np.allclose(JHr[4 * a:4 * a + 4], oj.vec(acc["jhr"][a]), atol=1e-12)
+    # stationarity at the minimum
+    Gt = cn(na, 2, 2) + 2 * np.eye(2)
+    D = Gt[p] @ M @ np.conj(np.swapaxes(Gt[q], -1, -2)) + 0.1 * cn(p.size, 2, 2)
+    G0 = np.tile(np.eye(2, dtype=complex), (na, 1, 1))
+    out = oc.stefcal_2x2(D, M, p, q, None, G0, tol=1e-14, max_iter=3000)
+    assert out["status"] & oc.CONVERGED
+    acc = oc.accumulate_2x2(D, M, p, q, None, out["g"])
+    scale = np.abs(acc["N"]).max()
+    assert np.abs(acc["jhr"]).max() < 1e-10 * scale
+
+
+def test_rel_change_two_antennas_by_hand():
+    """Reading of the convergence appendix: the parameter-update test is
+    ||g_{k+1} - g_k||_F / ||g_{k+1}||_F over every antenna (and direction) of the interval.
+    Hand-computed: g_k = (1 + i, 2), g_{k+1} = (1, 2i): the change is (-i, -2 + 2i), of norm
+    sqrt(1 + 8) = 3, and ||g_{k+1}|| = sqrt(5), so the value is 3 / sqrt(5)."""
+    g_old = np.array([1 + 1j, 2 + 0j])
+    g_new = np.array([1 + 0j, 2j])
+    assert oc.rel_change(g_new, g_old) == pytest.approx(3 / np.sqrt(5), rel=1e-15)
+    # the reverse step divides by the other iterate's norm sqrt(6)
+    assert oc.rel_change(g_old, g_new) == pytest.approx(3 / np.sqrt(6), rel=1e-15)
+    # two directions x two antennas: one Frobenius norm over all four values
+    G_old = np.array([[1, 1], [1j, -1]], dtype=complex)
+    G_new = np.array([[1, 2], [1j, -1]], dtype=complex)
+    assert oc.rel_change(G_new, G_old) == pytest.approx(1 / np.sqrt(7), rel=1e-15)
+    # 2x2 Jones of two antennas: the norm runs over every matrix entry
+    J_old = np.stack([np.eye(2), np.eye(2)]).astype(complex)
+    J_new = J_old.copy()
+    J_new[1, 0, 1] = 2
+    assert oc.rel_change(J_new, J_old) == pytest.approx(2 / np.sqrt(8), rel=1e-15)
+    assert oc.rel_change(g_new, g_new) == 0.0
+    assert oc.rel_change(np.zeros(2, complex), np.zeros(2, complex)) == 0.0
+    assert oc.rel_change(np.zeros(2, complex), g_old) == np.inf
