@@ -119,6 +119,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> dict:
+    """The host's CPU model (from /proc/cpuinfo) and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
 def bytes_per_row(n_corr: int, n_dir: int, flags: bool) -> int:
     return 8 * n_corr + 8 * n_corr * n_dir + (1 if flags else 0)
 
@@ -479,6 +497,9 @@ def main():
         "autotune": tuned,
         "solve_time_ms_with_kernel_events": ms_step_profiled,
         "mode": args.mode,
+        "pass_form": ("every update streams the samples once and accumulates J^H J and J^H D per antenna "
+                      "(data form, Eq. ghat; J^H r = J^H D - J^H J g); the residual R and chi^2 are formed "
+                      "once, by the residual pass after the last update"),
         "mean_iters": float(it.mean()),
         "converged_frac": conv,
         "roofline": {
@@ -539,9 +560,11 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_budget) if smooth is None else cpu_baseline_smooth(P, smooth)
+        out["cpu_baseline"].update(host_cpu())
         if smooth is None and not args.no_cpu_all_cores:
             log("[bench] timing the CPU oracle interval-parallel over the host cores")
             out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(P, args.cpu_budget)
+            out["cpu_baseline_all_cores"].update(host_cpu())
     line = json.dumps(out)
     print(line, flush=True)
     if args.out_json:

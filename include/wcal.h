@@ -34,6 +34,13 @@
  * Memory: every data pointer passed to a compute call is DEVICE memory owned by the
  * caller, which must stay valid until the stream has passed the call.  Host pointers
  * are only taken by wcal_plan_create (tables are copied into plan-owned device memory).
+ * The plan owns only those tables; every scratch array a call needs (work counters,
+ * per-tile partial sums, statistics, Gram records, the device-side loop's ring) lives in a
+ * WORKSPACE the caller allocates -- wcal_plan_workspace gives its size -- and passes to
+ * every compute call as (workspace, ws_bytes): device memory, 256-byte aligned, contents
+ * irrelevant on entry (each call initialises what it uses).  A workspace smaller than the
+ * plan needs is refused with WCAL_ENOMEM before anything is launched.  Calls that share a
+ * workspace must not overlap on the device.  The compute calls allocate nothing.
  * Calls are asynchronous on the given stream (a hipStream_t; NULL = default stream).
  * One plan must not be used on two streams at the same time.  data/model/gains/residual
  * pointers must be 8-byte aligned (16-byte for n_corr = 4).
@@ -60,7 +67,8 @@ typedef struct { float re, im; } wcal_c64;
 #define WCAL_EINDEX  (-2)  /* antenna index outside [0, n_ant) or ant1 == ant2 (autocorrelation) */
 #define WCAL_ESHAPE  (-3)  /* ns[k] < 1, or a size beyond the library limits */
 #define WCAL_EHIP    (-4)  /* a HIP runtime call failed */
-#define WCAL_ENOMEM  (-5)  /* device allocation failed */
+#define WCAL_ENOMEM  (-5)  /* a table allocation failed, or the workspace is too small */
+#define WCAL_EIO     (-6)  /* a file could not be read or written, or is not a weight file */
 
 /* per-interval status bits */
 #define WCAL_CONVERGED    1u  /* ||g_{k+1} - g_k||_F / ||g_{k+1}||_F < tol                      */
@@ -68,6 +76,9 @@ typedef struct { float re, im; } wcal_c64;
 #define WCAL_SINGULAR_ANT 4u  /* some antenna's block was not invertible: its gain was kept       */
 #define WCAL_NONFINITE    8u  /* a sum over unflagged rows was not finite: the interval stopped   */
                               /* before that update and kept the previous gains                   */
+#define WCAL_ABORTED     16u  /* the device-side iteration loop gave up a bounded wait (a library */
+                              /* fault, never a numerical outcome): the interval holds the gains  */
+                              /* of its last applied update and n_iter counts those updates       */
 
 /* algorithms */
 #define WCAL_STEFCAL   0   /* n_dir == 1; n_corr 1 or 4                     (Sect. 3.1, 4.3)   */
@@ -139,6 +150,11 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
  * no call using the plan is still in flight. */
 void wcal_plan_destroy(wcal_plan* plan);
 
+/* Bytes of device workspace every compute call on this plan needs (see Memory above).  The
+ * size changes only with the plan's tiling (wcal_plan_autotune) and smoothing setting
+ * (wcal_plan_smoothing): query it again after either. */
+int wcal_plan_workspace(const wcal_plan* plan, size_t* bytes);
+
 /* Total rows (sum over intervals of n_bl * ns[k]) described by the plan. */
 int64_t wcal_plan_rows(const wcal_plan* plan);
 
@@ -155,15 +171,20 @@ const char* wcal_plan_pass_kernel(const wcal_plan* plan);
  * target of {8192, 16384, 32768, 65536, 131072, 262144} rows per tile and, where
  * the baseline table is canonical (scalar, PASS mode), with and without the triangle pass;
  * it keeps the fastest (best of two timed runs after a warm-up run).  `gains` is only read
- * (a scratch copy is iterated).  CohJones / AllJones stream their rows in the blocked Gram
- * pass, which has no tiling to choose; the call returns at once.  Outputs: the chosen
- * rows per tile and 1 if the triangle pass is used (either pointer may be NULL).  The call
- * allocates scratch, synchronises the host and rebuilds the plan's tiles: call it between
- * solves, not under graph capture.  Errors: WCAL_EINVAL (n_updates outside [0, max_iter],
- * profiling on), WCAL_ENOMEM, WCAL_EHIP. */
+ * (a copy in the workspace is iterated).  Its workspace holds that copy and the solves'
+ * workspace; wcal_plan_autotune_workspace gives the size that admits every candidate
+ * (candidates that do not fit a smaller one are skipped).  CohJones / AllJones stream their
+ * rows in the blocked Gram pass, which has no tiling to choose; the call returns at once.
+ * Outputs: the chosen rows per tile and 1 if the triangle pass is used (either pointer may
+ * be NULL).  The call synchronises the host and rebuilds the plan's tile tables: call it
+ * between solves, not under graph capture, and query wcal_plan_workspace afterwards.
+ * Errors: WCAL_EINVAL (n_updates outside [0, max_iter], profiling on, no workspace),
+ * WCAL_ENOMEM (no candidate fits the workspace), WCAL_EHIP. */
+int wcal_plan_autotune_workspace(const wcal_plan* plan, size_t* bytes);
 int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                        const uint8_t* flags, const wcal_c64* gains, int32_t n_updates,
-                       void* stream, int32_t* tile_rows_out, int32_t* tri_out);
+                       void* workspace, size_t ws_bytes, void* stream, int32_t* tile_rows_out,
+                       int32_t* tri_out);
 
 /* Solve every interval: iterate the algorithm's update from the gains held in `gains`
  * until the relative parameter change drops below tol or max_iter updates were applied,
@@ -173,29 +194,35 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
  *   n_iter   out    [n_int] updates applied
  *   status   out    [n_int] WCAL_* status bits
  *   chi2     out    [n_int] sum of |R|^2 over unflagged rows (FP64), or NULL
- * The whole batch runs on the device with no host synchronisation: in PASS mode each
- * update is a tiled pass over the rows of the intervals still iterating plus the update
- * launches; in STATS mode one statistics pass is followed by updates on the statistics
+ * The whole batch runs on the device with no host synchronisation.  StefCal in PASS mode
+ * runs every update of every interval in ONE persistent launch: workgroups take tiles of
+ * the intervals' rows from a ring in the workspace, the workgroup that finishes an
+ * interval's last tile of an update applies the update and puts the interval's tiles back
+ * while it keeps iterating, so each interval advances on its own (bounded waits; a wait
+ * that runs out marks the intervals it cut off WCAL_ABORTED).  CohJones / AllJones in PASS
+ * mode launch a Gram pass over the intervals still iterating and the update kernels per
+ * update.  In STATS mode one statistics pass is followed by updates on the statistics
  * (StefCal: one launch that iterates every interval; CohJones / AllJones: per-update
- * launches); both end with a tiled residual pass.  No call allocates, synchronises the
- * host or records a memset node, so the call can be captured into a HIP graph. */
+ * launches).  Every solve ends with a tiled residual pass.  No call allocates, synchronises
+ * the host or records a memset node, so the call can be captured into a HIP graph. */
 int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
-               int32_t* n_iter, uint32_t* status, double* chi2, void* stream);
+               int32_t* n_iter, uint32_t* status, double* chi2, void* workspace, size_t ws_bytes,
+               void* stream);
 
 /* A wcal_solve captured into an instantiated HIP graph (stream capture of exactly the
  * launches wcal_solve makes; on a NULL stream the capture uses a private stream).  Each
  * wcal_graph_launch re-runs the solve on `stream` with the same pointers, reading the
  * current contents of data, model, flags and gains (gains are updated in place, so reset
- * them for a fresh start).  The plan must outlive the graph; launches of graphs or calls
- * that share a plan must not overlap (they share its scratch).  Profiling must be off
- * while capturing.  Errors: WCAL_EINVAL (NULL, profiling on), WCAL_EHIP (capture or
- * instantiation failed). */
+ * them for a fresh start).  The plan and the workspace must outlive the graph; launches of
+ * graphs or calls that share a workspace must not overlap.  Profiling must be off while
+ * capturing.  Errors: WCAL_EINVAL (NULL, profiling on), WCAL_ENOMEM (workspace too small),
+ * WCAL_EHIP (capture or instantiation failed). */
 typedef struct wcal_graph wcal_graph;
 int wcal_solve_graph(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                      const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
-                     int32_t* n_iter, uint32_t* status, double* chi2, void* stream,
-                     wcal_graph** out);
+                     int32_t* n_iter, uint32_t* status, double* chi2, void* workspace,
+                     size_t ws_bytes, void* stream, wcal_graph** out);
 int wcal_graph_launch(wcal_graph* graph, void* stream);
 void wcal_graph_destroy(wcal_graph* graph);   /* NULL is a no-op */
 
@@ -216,13 +243,13 @@ void wcal_graph_destroy(wcal_graph* graph);   /* NULL is a no-op */
 int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                     const uint8_t* flags, const wcal_c64* gains, wcal_c64* jhj, wcal_c64* jhd,
                     wcal_c64* jhr, int32_t* count, double* chi2, wcal_c64* residual,
-                    void* stream);
+                    void* workspace, size_t ws_bytes, void* stream);
 
 /* Residual prediction only: R = D - sum_d G_p M G_q^H, flagged rows 0 (Eq. cal:DI,
  * Eq. cal:DI:pol, Eq. cal:dd:unpol); chi2 [n_int] or NULL. */
 int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                   const uint8_t* flags, const wcal_c64* gains, wcal_c64* residual,
-                  double* chi2, void* stream);
+                  double* chi2, void* workspace, size_t ws_bytes, void* stream);
 
 /* Point-source models predicted in the Gram and residual passes instead of read from HBM
  * (Sect. 3.2.1: m^d_pq(t, nu) = S_d exp(-2 pi i (u_pq(t) . sigma_d) nu / c), sigma_d =
@@ -250,7 +277,7 @@ typedef struct {
  * (an interval that does not hold n_time * n_chan samples). */
 int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* data, const uint8_t* flags,
                       wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
-                      void* stream);
+                      void* workspace, size_t ws_bytes, void* stream);
 
 /* Time/frequency smoothing of scalar StefCal (Sect. 3.4, Eq. JHJ:diag:smooth).  Every
  * sample of an interval becomes a cell (t, nu) of an n_time x n_chan grid, sample
@@ -266,8 +293,9 @@ int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* d
  * beta is not positive keeps its gain (SINGULAR_ANT).
  *
  * wcal_plan_smoothing prepares a scalar StefCal plan in PASS mode whose intervals all hold
- * n_time * n_chan samples: it validates, builds the per-cell tables and allocates the
- * scratch (synchronous; calling it again replaces the previous setting).  Errors:
+ * n_time * n_chan samples: it validates and builds the per-cell tables (synchronous;
+ * calling it again replaces the previous setting); the plan's workspace then also holds the
+ * smoothing scratch, so query wcal_plan_workspace again.  Errors:
  * WCAL_EINVAL (wrong plan kind, n_time or n_chan < 1, negative or non-finite sigma),
  * WCAL_ESHAPE (an interval of another size, kernel radius above 4096 cells), WCAL_ENOMEM.
  *
@@ -277,7 +305,7 @@ int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* d
 int wcal_plan_smoothing(wcal_plan* plan, int32_t n_time, int32_t n_chan, double sigma_t, double sigma_f);
 int wcal_solve_smooth(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
                       wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
-                      void* stream);
+                      void* workspace, size_t ws_bytes, void* stream);
 
 /* Kernel timing for benchmarks.  While enabled, every kernel launched by wcal_solve and
  * wcal_residual on this plan is bracketed by HIP events on the call's stream.
@@ -353,6 +381,19 @@ int wcal_mlp_gradients(wcal_mlp* mlp, const float* x, const float* target, int32
 /* one Adam step on the batch; loss (FP64, device) of the batch before the step, or NULL */
 int wcal_mlp_train_step(wcal_mlp* mlp, const float* x, const float* target, int32_t batch,
                         float lr, double* loss, void* stream);
+
+/* Weight files (host calls, synchronous: call them once the work that produced or will read
+ * the parameters has completed).  The file is one line of JSON, e.g.
+ *   {"format": "wcal-mlp", "version": 1, "d_in": 128, "d_hidden": 256, "d_out": 128, "skip": 1,
+ *    "n_params": 131712, "adam_step": 4000, "dtype": "float32", "byteorder": "little",
+ *    "sections": ["params", "adam_m", "adam_v"]}
+ * then n_params float32 values per section in that order: the flat parameters in the layout
+ * of wcal_mlp_set_params, then the two Adam moments, so training resumes where it stopped.
+ * wcal_mlp_load checks the header against the network it loads into.  Errors: WCAL_EIO (open,
+ * read or write failed, not a weight file, truncated), WCAL_EINVAL (NULL, or a network of
+ * another shape), WCAL_EHIP. */
+int wcal_mlp_save(const wcal_mlp* mlp, const char* path);
+int wcal_mlp_load(wcal_mlp* mlp, const char* path);
 
 #ifdef __cplusplus
 }

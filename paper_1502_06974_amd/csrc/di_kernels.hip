@@ -26,6 +26,12 @@
 //            (Eq. stefcal-lambda-average) per the schedule, evaluates the FP64 relative
 //            change and, if the interval keeps iterating, appends its tiles to the next
 //            list.  Singular blocks keep their gain.
+// By default the two steps run inside one persistent launch (di_loop_kernel): workgroups take
+// tiles from a ring (loop_ring.h); the workgroup that finishes the last tile of an interval's
+// update folds the tiles' partials in tile order, applies the update and puts the interval's
+// tiles back while it keeps iterating, so intervals advance independently and a solve is one
+// launch however many updates its intervals need.  The sums are those of the two-launch form,
+// bit for bit.
 // Statistics solve (WCAL_MODE_STATS): the statistics above do not depend on the gains,
 // so one pass stores them per baseline and one persistent launch iterates every interval
 // on them (the gains factor out of the sum over samples, as in the cross-direction
@@ -34,6 +40,9 @@
 // chi^2 in FP64.  Flags are applied by selection, so non-finite values under a flag
 // cannot leak into any sum.
 #include "di_common.h"
+
+#define LOOP_FN __device__ __forceinline__
+#include "loop_ring.h"
 
 using namespace wcal_dev;
 
@@ -1068,6 +1077,201 @@ __global__ void __launch_bounds__(TB) di_solve_stats_kernel(DiArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ device-side iteration loop
+// Agent-scope atomics for the ring of loop_ring.h.  The ring's waits poll with relaxed loads
+// and take the acquire fence once, when the awaited word has arrived.
+struct DevOps {
+    __device__ int64_t add64(int64_t* p, int64_t v) {
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ int32_t add32_acq_rel(int32_t* p, int32_t v) {
+        return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ uint64_t load64(uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ void acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+    __device__ void store64_release(uint64_t* p, uint64_t v) {
+        __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ void store64_relaxed(uint64_t* p, uint64_t v) {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ int32_t load32(int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ void store32(int32_t* p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+    __device__ int64_t now() { return (int64_t)wall_clock64(); }
+    __device__ void pause() { __builtin_amdgcn_s_sleep(2); }
+};
+
+// Values one workgroup of the loop writes and another reads in the same launch (the gains,
+// the update count and status of an interval, the tiles' partial sums) move through
+// agent-scope atomic loads and stores: those are coherent across the L2 caches of the XCDs,
+// whereas a plain load may return a line that an L2 still holds from before the write.
+__device__ __forceinline__ float2 ld_xwg(const float2* p) {
+    const uint64_t v = __hip_atomic_load(const_cast<uint64_t*>(reinterpret_cast<const uint64_t*>(p)),
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+}
+__device__ __forceinline__ void st_xwg(float2* p, float2 x) {
+    const uint64_t v = (uint64_t)__float_as_uint(x.x) | ((uint64_t)__float_as_uint(x.y) << 32);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_xwg(const float* p) {
+    return __uint_as_float(__hip_atomic_load(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(p)),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_xwg(float* p, float x) {
+    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), __float_as_uint(x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_xwg_int(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_xwg_int(T* p, T x) {
+    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The ring as the loop starts: HEAD 0, TAIL ntiles, every interval live, the first update's
+// tiles in slots [0, ntiles), the other slots free for lap 0, every tile counter 0.
+__global__ void __launch_bounds__(TB) loop_init_kernel(LoopRing q, int32_t ntiles, int32_t n_int) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < q.cap) q.ring[i] = i < ntiles ? ring_word(1, (uint32_t)i) : ring_word(0, 0);
+    if (i < n_int) q.done[i] = 0;
+    if (i == 0) {
+        q.pos[LW_HEAD] = 0;
+        q.pos[LW_TAIL] = ntiles;
+        q.flag[LF_LIVE] = n_int;
+        q.flag[LF_ABORT] = 0;
+    }
+}
+
+// Update of interval k from its folded sums (acc, LDS) inside the loop: the update of
+// finish_interval, then either the interval retires or its tiles [t0, t1) go back into the
+// ring.  Every thread of the workgroup calls this.
+template <int NC>
+__device__ void loop_update(const DiArgs& a, const LoopRing& q, int k, int t0, int t1, const float* acc,
+                            float2* G, float2* Gn, double* red, int* s_flags, int64_t* s_p0) {
+    DevOps o;
+    const int na = a.n_ant;
+    const int it = ld_xwg_int(&a.n_iter[k]);     // updates applied so far
+    float2* gk = a.gains + (int64_t)k * na * NC;
+    uint32_t status = 0;
+    const int stop = update_step<NC>(a, it, acc, G, Gn, red, s_flags, status);
+    bool finished = stop != 0;
+    if (!(status & WCAL_NONFINITE)) {
+        for (int i = threadIdx.x; i < na * NC; i += blockDim.x) st_xwg(gk + i, G[i]);
+    }
+    if (!finished && it + 1 >= a.max_iter) {
+        status |= WCAL_MAXITER;
+        finished = true;
+    }
+    if (threadIdx.x == 0) {
+        st_xwg_int(&a.status[k], ld_xwg_int(&a.status[k]) | status);
+        if (!(status & WCAL_NONFINITE)) st_xwg_int(&a.n_iter[k], it + 1);
+        if (finished) st_xwg_int(&a.active[k], 0);
+    }
+    if (finished) {
+        if (threadIdx.x == 0) ring_retire(q, o);
+        return;
+    }
+    // the new gains and the update count reach memory before any tile of the next update
+    // can be taken
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *s_p0 = ring_reserve(q, o, t1 - t0);
+    __syncthreads();
+    const int64_t p0 = *s_p0;
+    for (int i = threadIdx.x; i < t1 - t0; i += blockDim.x) ring_put(q, o, p0 + i, t0 + i);
+}
+
+// The whole PASS solve in one launch (see the top of the file).  TRI: the triangle pass of
+// the canonical baseline order over the triangle tiles (scalar gains); else the tiled pass.
+// LDS: gains G [na * NC] (TRI: na + 1, the last 0), the wavefront slices acc [nw][slice] with
+// slice = na * NVP (TRI: (na + 1) * NVP), candidate gains Gn [na * NC].
+// The 2x2 walk fits three waves per SIMD (at most 168 VGPRs), as the per-update pass does.
+template <int NC> struct LoopWaves { static constexpr int v = NC == 4 ? 3 : 4; };
+
+template <int NC, bool TRI>
+__global__ void __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(LoopWaves<NC>::v, 8)))
+di_loop_kernel(DiArgs a, LoopRing q, const TriUnit* __restrict__ units) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NVP = Nv<NC, 0>::v;
+    const int na = a.n_ant;
+    const int ng = TRI ? na + 1 : na * NC;
+    const int sl = TRI ? (na + 1) * NVP : na * NVP;
+    float2* G = reinterpret_cast<float2*>(smem);
+    float* acc = reinterpret_cast<float*>(G + ng);
+    float2* Gn = reinterpret_cast<float2*>(acc + (TB / WAVE) * sl);
+    __shared__ double red[TB / WAVE];
+    __shared__ int s_flags[2];
+    __shared__ int s_t, s_last;
+    __shared__ int64_t s_p0;
+    const int nw = blockDim.x / WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
+    float* myacc = acc + w * sl;
+    DevOps o;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = ring_pop(q, o);
+        __syncthreads();
+        const int t = s_t;
+        if (t < 0) break;
+        const Tile T = a.tiles[t];
+        const int k = T.k;
+        const int t0 = a.tile_off[k], t1 = a.tile_off[k + 1];
+        const float2* gk = a.gains + (int64_t)k * na * NC;
+        for (int i = threadIdx.x; i < ng; i += blockDim.x) G[i] = (TRI && i == na) ? make_float2(0.f, 0.f) : ld_xwg(gk + i);
+        for (int i = threadIdx.x; i < nw * sl; i += blockDim.x) acc[i] = 0.f;
+        __syncthreads();
+        if constexpr (TRI) {
+            if (na >= TRI_PAIR_MIN)
+                for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit_paired(a, T, units[u], G, myacc);
+            else
+                for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
+        } else {
+            tile_walk<NC>(a, T, [&](int, int p, int qq, float (&st)[Ns<NC>::v]) {
+                flush_acc<NC>(p, qq, st, G, myacc);
+            });
+        }
+        __syncthreads();
+        if (t1 - t0 == 1) {
+            // the interval's only tile: its sums are complete here (the wavefront slices
+            // folded in wavefront order, as the partial of the two-launch form)
+            for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                float v = acc[i];
+                for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * sl + i];
+                acc[i] = v;
+            }
+            __syncthreads();
+        } else {
+            float* out = a.partial + (int64_t)t * na * NVP;
+            for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                float v = acc[i];
+                for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * sl + i];
+                st_xwg(out + i, v);
+            }
+            __threadfence();          // every thread's partial is in memory before the count
+            __syncthreads();
+            if (threadIdx.x == 0) s_last = ring_tile_done(q, o, k, t1 - t0);
+            __syncthreads();
+            if (!s_last) continue;
+            // the update's last tile: every partial of the interval is visible (the count's
+            // acquire); fold them in tile order
+            for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                float v = 0.f;
+                for (int tt = t0; tt < t1; ++tt) v += ld_xwg(a.partial + (int64_t)tt * na * NVP + i);
+                acc[i] = v;
+            }
+            __syncthreads();
+        }
+        loop_update<NC>(a, q, k, t0, t1, acc, G, Gn, red, s_flags, &s_p0);
+    }
+}
+
+// After the loop: an interval still marked active was cut off by an aborted wait.
+__global__ void __launch_bounds__(TB) loop_end_kernel(DiArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < a.n_int && a.active[k]) a.status[k] |= WCAL_ABORTED;
+}
+
 __global__ void reset_queue_kernel(int32_t* q) {
     if (threadIdx.x < 4) q[threadIdx.x] = 0;
 }
@@ -1100,6 +1304,21 @@ static size_t update_smem(int na, int nc) {
     return 2 * (size_t)na * nc * sizeof(float2) + (size_t)(TB / WAVE) * na * di_nvp(nc) * sizeof(float);
 }
 
+// The ring of the device-side loop in the plan's WS_LOOP region: 64 bytes of control words
+// (two int64 positions, then LIVE and ABORT), the slots, the per-interval tile counters.
+static LoopRing loop_ring_of(const wcal_plan* plan, int32_t ntiles) {
+    char* base = reinterpret_cast<char*>(plan->d_loop);
+    LoopRing q;
+    q.pos = reinterpret_cast<int64_t*>(base);
+    q.flag = reinterpret_cast<int32_t*>(base + 2 * sizeof(int64_t));
+    q.ring = reinterpret_cast<uint64_t*>(base + 64);
+    q.cap = (int64_t)LOOP_RING * ntiles;
+    q.done = reinterpret_cast<int32_t*>(base + 64 + ws_round(sizeof(uint64_t) * (size_t)q.cap));
+    q.limit = (int64_t)ntiles * plan->prob.max_iter;
+    q.wait_ticks = plan->wait_ticks;
+    return q;
+}
+
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, q);
     return hipGetLastError();
@@ -1124,6 +1343,32 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
         prof_begin(plan, WCAL_K_SOLVE_STATS, s);
         hipLaunchKernelGGL(di_solve_stats_kernel<NC>, dim3(g2), dim3(TB), us, s, a);
         prof_end(plan, WCAL_K_SOLVE_STATS, s);
+    } else if (plan->loop) {
+        // one persistent launch iterates every interval (triangle tiles when the plan uses the
+        // triangle pass; the residual below keeps the row tiles)
+        DiArgs at = a;
+        const bool tri = NC == 1 && plan->tri;
+        if (tri) {
+            at.tiles = plan->d_ttiles;
+            at.tile_off = plan->d_ttile_off;
+            at.ntiles = plan->nttiles;
+        }
+        const LoopRing q = loop_ring_of(plan, at.ntiles);
+        hipLaunchKernelGGL(loop_init_kernel, dim3((unsigned)((q.cap + TB - 1) / TB)), dim3(TB), 0, s, q, at.ntiles,
+                           a.n_int);
+        const size_t ls = tri ? (size_t)(na + 1) * sizeof(float2) + (size_t)(TB / WAVE) * (na + 1) * 3 * sizeof(float) +
+                                    (size_t)na * sizeof(float2)
+                              : update_smem(na, NC);
+        const void* fn = tri ? reinterpret_cast<const void*>(di_loop_kernel<1, true>)
+                             : reinterpret_cast<const void*>(di_loop_kernel<NC, false>);
+        const int gl = grid_resident(plan, fn, TB, ls, at.ntiles);
+        prof_begin(plan, WCAL_K_PASS, s);
+        if (tri)
+            hipLaunchKernelGGL((di_loop_kernel<1, true>), dim3(gl), dim3(TB), ls, s, at, q, (const TriUnit*)plan->d_units);
+        else
+            hipLaunchKernelGGL((di_loop_kernel<NC, false>), dim3(gl), dim3(TB), ls, s, at, q, (const TriUnit*)nullptr);
+        prof_end(plan, WCAL_K_PASS, s);
+        hipLaunchKernelGGL(loop_end_kernel, dim3((a.n_int + TB - 1) / TB), dim3(TB), 0, s, a);
     } else if (NC == 1 && plan->tri) {
         // pass and update over the triangle tiles; the residual below keeps the row tiles
         DiArgs at = a;

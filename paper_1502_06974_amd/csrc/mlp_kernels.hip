@@ -5,6 +5,9 @@
 // in the order W1 [d_in][d_h], b1, W2 [d_h][d_h], b2, W3 [d_h][d_out], b3; rows of x and y
 // are samples.  Initial parameters are supplied by the caller.
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -199,6 +202,49 @@ void backward(const wcal_mlp* n, const float* x, const float* t, int B, hipStrea
 }
 
 int mfail(int code, const char* msg) { return wcal_error(code, msg); }
+int mfail(int code, const std::string& msg) { return wcal_error(code, msg); }
+
+// Weight file: one line of JSON naming the network, then the parameters, the Adam first and
+// second moments, each n_params little-endian float32 values.
+const char* kMlpFormat = "wcal-mlp";
+constexpr int kMlpVersion = 1;
+
+bool little_endian() {
+    const uint16_t one = 1;
+    unsigned char b;
+    std::memcpy(&b, &one, 1);
+    return b == 1;
+}
+
+// Integer value of "key": N in a flat JSON object, or false when absent.
+bool json_int(const std::string& h, const char* key, int64_t& out) {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t i = h.find(k);
+    if (i == std::string::npos) return false;
+    i = h.find(':', i + k.size());
+    if (i == std::string::npos) return false;
+    const char* c = h.c_str() + i + 1;
+    char* end = nullptr;
+    const long long v = std::strtoll(c, &end, 10);
+    if (end == c) return false;
+    out = v;
+    return true;
+}
+
+// String value of "key": "value", or false when absent.
+bool json_str(const std::string& h, const char* key, std::string& out) {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t i = h.find(k);
+    if (i == std::string::npos) return false;
+    i = h.find(':', i + k.size());
+    if (i == std::string::npos) return false;
+    const size_t a = h.find('"', i + 1);
+    if (a == std::string::npos) return false;
+    const size_t b = h.find('"', a + 1);
+    if (b == std::string::npos) return false;
+    out = h.substr(a + 1, b - a - 1);
+    return true;
+}
 
 }  // namespace
 
@@ -275,6 +321,70 @@ int wcal_mlp_get_params(const wcal_mlp* n, float* params, void* stream) {
     if (hipMemcpyAsync(params, n->params, n->np * sizeof(float), hipMemcpyDeviceToDevice,
                        reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
         return mfail(WCAL_EHIP, "copy failed");
+    return WCAL_OK;
+}
+
+int wcal_mlp_save(const wcal_mlp* n, const char* path) {
+    if (!n || !path) return mfail(WCAL_EINVAL, "NULL argument");
+    if (!little_endian()) return mfail(WCAL_EIO, "weight files are little-endian; this host is not");
+    if (hipSetDevice(n->device) != hipSuccess) return mfail(WCAL_EHIP, "hipSetDevice failed");
+    std::vector<float> host(3 * (size_t)n->np);
+    const float* src[3] = {n->params, n->m, n->v};
+    for (int i = 0; i < 3; ++i)
+        if (hipMemcpy(host.data() + i * (size_t)n->np, src[i], n->np * sizeof(float), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return mfail(WCAL_EHIP, "reading the parameters failed");
+    char head[512];
+    std::snprintf(head, sizeof(head),
+                  "{\"format\": \"%s\", \"version\": %d, \"d_in\": %d, \"d_hidden\": %d, \"d_out\": %d, "
+                  "\"skip\": %d, \"n_params\": %lld, \"adam_step\": %lld, \"dtype\": \"float32\", "
+                  "\"byteorder\": \"little\", \"sections\": [\"params\", \"adam_m\", \"adam_v\"]}\n",
+                  kMlpFormat, kMlpVersion, n->d_in, n->d_h, n->d_out, n->skip ? 1 : 0, (long long)n->np,
+                  (long long)n->step);
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return mfail(WCAL_EIO, std::string("cannot open ") + path + " for writing");
+    const size_t len = std::strlen(head);
+    const bool ok = std::fwrite(head, 1, len, f) == len &&
+                    std::fwrite(host.data(), sizeof(float), host.size(), f) == host.size();
+    if (std::fclose(f) != 0 || !ok) return mfail(WCAL_EIO, std::string("writing ") + path + " failed");
+    return WCAL_OK;
+}
+
+int wcal_mlp_load(wcal_mlp* n, const char* path) {
+    if (!n || !path) return mfail(WCAL_EINVAL, "NULL argument");
+    if (!little_endian()) return mfail(WCAL_EIO, "weight files are little-endian; this host is not");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return mfail(WCAL_EIO, std::string("cannot open ") + path);
+    std::string head;
+    for (int c; (c = std::fgetc(f)) != EOF && c != '\n';) {
+        head.push_back((char)c);
+        if (head.size() > 4096) break;
+    }
+    std::string fmt, dtype, order;
+    int64_t ver = 0, di = 0, dh = 0, dout = 0, skip = 0, np = 0, step = 0;
+    if (!json_str(head, "format", fmt) || fmt != kMlpFormat || !json_int(head, "version", ver) ||
+        ver != kMlpVersion || !json_int(head, "d_in", di) || !json_int(head, "d_hidden", dh) ||
+        !json_int(head, "d_out", dout) || !json_int(head, "skip", skip) || !json_int(head, "n_params", np) ||
+        !json_int(head, "adam_step", step) || !json_str(head, "dtype", dtype) || dtype != "float32" ||
+        !json_str(head, "byteorder", order) || order != "little") {
+        std::fclose(f);
+        return mfail(WCAL_EIO, std::string(path) + " is not a weight file of this library (bad header)");
+    }
+    if (di != n->d_in || dh != n->d_h || dout != n->d_out || (skip != 0) != n->skip || np != n->np) {
+        std::fclose(f);
+        return mfail(WCAL_EINVAL, std::string(path) + " holds a network of another shape");
+    }
+    std::vector<float> host(3 * (size_t)n->np);
+    const bool ok = std::fread(host.data(), sizeof(float), host.size(), f) == host.size();
+    std::fclose(f);
+    if (!ok) return mfail(WCAL_EIO, std::string(path) + " is truncated");
+    if (hipSetDevice(n->device) != hipSuccess) return mfail(WCAL_EHIP, "hipSetDevice failed");
+    float* dst[3] = {n->params, n->m, n->v};
+    for (int i = 0; i < 3; ++i)
+        if (hipMemcpy(dst[i], host.data() + i * (size_t)n->np, n->np * sizeof(float), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return mfail(WCAL_EHIP, "writing the parameters failed");
+    n->step = step;
     return WCAL_OK;
 }
 

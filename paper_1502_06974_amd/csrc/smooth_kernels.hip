@@ -35,8 +35,11 @@ struct SmoothPlan {
     double* d_part = nullptr;     // [n_int][bpc][2] |g_new|^2 and the phase-aligned change per block
     int32_t* d_flag = nullptr;    // [n_int] 1: non-finite sums, 2: a singular cell (this update)
     int32_t* d_active = nullptr;  // [n_int]
-    float* d_taps = nullptr;      // w_t(0..rt), then w_f(0..rf)
+    float* d_taps = nullptr;      // w_t(0..rt), then w_f(0..rf) (a table: plan-owned)
     int32_t cpb = 0, bpc = 0;     // update: cells per workgroup, workgroups per interval
+    int32_t n_int = 0, n_ant = 0;
+    // workspace: the five scratch arrays above, then the cell plan's workspace
+    size_t off[6] = {};
 };
 
 namespace {
@@ -268,10 +271,30 @@ unsigned nblk(int64_t n) { return (unsigned)((n + SB - 1) / SB); }
 void smooth_free(SmoothPlan* sp) {
     if (!sp) return;
     wcal_plan_destroy(sp->cells);
-    for (void* p : {(void*)sp->d_ab, (void*)sp->d_tmp, (void*)sp->d_part, (void*)sp->d_flag, (void*)sp->d_active,
-                    (void*)sp->d_taps})
-        if (p) (void)hipFree(p);
+    if (sp->d_taps) (void)hipFree(sp->d_taps);
     delete sp;
+}
+
+// Workspace of the smoothing scratch: the per-cell sums and their convolution, the per-block
+// norms, the per-interval flags and activity, then the cell plan's own workspace.
+static void smooth_layout(SmoothPlan* sp) {
+    const size_t ncells = (size_t)sp->cells->prob.n_int;
+    const size_t nab = ncells * sp->n_ant * 3;
+    const size_t sz[5] = {nab * sizeof(float), nab * sizeof(float), (size_t)sp->n_int * sp->bpc * 2 * sizeof(double),
+                          (size_t)sp->n_int * sizeof(int32_t), (size_t)sp->n_int * sizeof(int32_t)};
+    sp->off[0] = 0;
+    for (int i = 0; i < 5; ++i) sp->off[i + 1] = sp->off[i] + ws_round(sz[i]);
+}
+
+size_t smooth_ws_bytes(const SmoothPlan* sp) { return sp->off[5] + sp->cells->ws_bytes; }
+
+void smooth_ws_bind(SmoothPlan* sp, char* ws) {
+    sp->d_ab = reinterpret_cast<float*>(ws + sp->off[0]);
+    sp->d_tmp = reinterpret_cast<float*>(ws + sp->off[1]);
+    sp->d_part = reinterpret_cast<double*>(ws + sp->off[2]);
+    sp->d_flag = reinterpret_cast<int32_t*>(ws + sp->off[3]);
+    sp->d_active = reinterpret_cast<int32_t*>(ws + sp->off[4]);
+    ws_bind(sp->cells, ws + sp->off[5]);
 }
 
 extern "C" {
@@ -317,31 +340,33 @@ int wcal_plan_smoothing(wcal_plan* plan, int32_t n_time, int32_t n_chan, double 
         delete sp;
         return rc;
     }
+    // the cell plan's passes are launched one update at a time (the smoothed update needs the
+    // sums of neighbouring cells): no device-side loop
+    sp->cells->loop = false;
+    ws_layout(sp->cells);
     const int na = p.n_ant;
     sp->cpb = na <= SB ? SB / na : 1;
     sp->bpc = (int)((ncell + sp->cpb - 1) / sp->cpb);
     std::vector<float> taps;
     for (int j = 0; j <= sp->rt; ++j) taps.push_back(sp->rt ? (float)std::exp(-0.5 * j * j / (sigma_t * sigma_t)) : 1.f);
     for (int j = 0; j <= sp->rf; ++j) taps.push_back(sp->rf ? (float)std::exp(-0.5 * j * j / (sigma_f * sigma_f)) : 1.f);
-    const size_t nab = (size_t)ncells * na * 3;
+    sp->n_int = p.n_int;
+    sp->n_ant = na;
     hipError_t e;
-    if ((e = hipMalloc(reinterpret_cast<void**>(&sp->d_ab), nab * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&sp->d_tmp), nab * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&sp->d_part), (size_t)p.n_int * sp->bpc * 2 * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&sp->d_flag), (size_t)p.n_int * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&sp->d_active), (size_t)p.n_int * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&sp->d_taps), taps.size() * sizeof(float))) != hipSuccess ||
+    if ((e = hipMalloc(reinterpret_cast<void**>(&sp->d_taps), taps.size() * sizeof(float))) != hipSuccess ||
         (e = hipMemcpy(sp->d_taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
         smooth_free(sp);
-        return wcal_error(e == hipErrorOutOfMemory ? WCAL_ENOMEM : WCAL_EHIP, "smoothing scratch allocation failed");
+        return wcal_error(e == hipErrorOutOfMemory ? WCAL_ENOMEM : WCAL_EHIP, "smoothing table allocation failed");
     }
+    smooth_layout(sp);
     plan->smooth = sp;
+    ws_layout(plan);
     return WCAL_OK;
 }
 
 int wcal_solve_smooth(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
                       wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
-                      void* stream) {
+                      void* workspace, size_t ws_bytes, void* stream) {
     if (!plan || !data || !model || !gains || !n_iter || !status) return wcal_error(WCAL_EINVAL, "NULL argument");
     SmoothPlan* sp = plan->smooth;
     if (!sp) return wcal_error(WCAL_EINVAL, "call wcal_plan_smoothing first");
@@ -349,6 +374,7 @@ int wcal_solve_smooth(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mod
         reinterpret_cast<uintptr_t>(gains) % 8 || (residual && reinterpret_cast<uintptr_t>(residual) % 8))
         return wcal_error(WCAL_EINVAL, "complex arrays must be 8-byte aligned");
     if (hipSetDevice(plan->device) != hipSuccess) return wcal_error(WCAL_EHIP, "hipSetDevice failed");
+    if (int rc = ws_check_bind(plan, workspace, ws_bytes)) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const wcal_plan* cp = sp->cells;
     const wcal_problem& p = plan->prob;

@@ -121,27 +121,30 @@ const char* wcal_last_error(void) { return g_err.c_str(); }
 
 const char* wcal_version(void) { return "wcal 0.1 (gfx950)"; }
 
-// (Re)build the tiles of a plan for a target of `tile_rows` rows per tile, with or without
-// the triangle pass (used only where the plan allows it), and (re)allocate what depends on
-// the tile count.  Host-side; no kernel runs.
-static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
+// The tiling of a plan for a target of `tile_rows` rows per tile, with or without the
+// triangle pass (used only where the plan allows it), computed on the host.
+struct TilePlan {
+    int64_t tile_rows = 0;
+    bool tri = false;
+    std::vector<Tile> tiles, stiles, ttiles;
+    std::vector<int32_t> tile_off, ttile_off;
+    std::vector<TriUnit> units;
+};
+
+static int plan_tiles(const wcal_plan* plan, int64_t tile_rows, bool want_tri, TilePlan& tp) {
     const wcal_problem& p = plan->prob;
     const std::vector<int32_t>& ns32 = plan->h_ns;
-    for (void** q : {(void**)&plan->d_tiles, (void**)&plan->d_tile_off, (void**)&plan->d_stiles,
-                     (void**)&plan->d_lists, (void**)&plan->d_partial, (void**)&plan->d_chi_part,
-                     (void**)&plan->d_units, (void**)&plan->d_ttiles, (void**)&plan->d_ttile_off}) {
-        if (*q) (void)hipFree(*q);
-        *q = nullptr;
-    }
-    plan->tile_rows = (int)tile_rows;
-    plan->nunits = plan->nttiles = 0;
-    plan->tri = want_tri && plan->canonical && p.algo == WCAL_STEFCAL && p.n_corr == 1 && !di_stats_solve(plan);
+    tp = TilePlan();
+    tp.tile_rows = tile_rows;
+    tp.tri = want_tri && plan->canonical && p.algo == WCAL_STEFCAL && p.n_corr == 1 && !di_stats_solve(plan);
     // tiles: samples per tile S and baselines per tile (a multiple of the 256-lane
     // workgroup) chosen for about tile_rows rows; interval k owns a contiguous tile range
     const int TBL = 256;
     auto round_up = [](int64_t x, int64_t m) { return (x + m - 1) / m * m; };
-    std::vector<Tile> tiles, stiles;
-    std::vector<int32_t> tile_off(p.n_int + 1, 0);
+    std::vector<Tile>& tiles = tp.tiles;
+    std::vector<Tile>& stiles = tp.stiles;
+    std::vector<int32_t>& tile_off = tp.tile_off;
+    tile_off.assign(p.n_int + 1, 0);
     for (int32_t k = 0; k < p.n_int; ++k) {
         const int64_t tr = tile_rows;
         const int32_t S = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tr / p.n_bl, ns32[k]));
@@ -157,12 +160,13 @@ static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
             for (int32_t b0 = 0; b0 < p.n_bl; b0 += bs)
                 stiles.push_back(Tile{k, b0, std::min(b0 + bs, p.n_bl), 0, ns32[k]});
         }
-        if (tiles.size() > (size_t)INT32_MAX / 2) return fail(WCAL_ESHAPE, "too many tiles");
+        if (tiles.size() > (size_t)INT32_MAX / 4) return fail(WCAL_ESHAPE, "too many tiles");
     }
-    std::vector<TriUnit> units;
-    std::vector<Tile> ttiles;
-    std::vector<int32_t> ttile_off(p.n_int + 1, 0);
-    if (plan->tri) {
+    std::vector<TriUnit>& units = tp.units;
+    std::vector<Tile>& ttiles = tp.ttiles;
+    std::vector<int32_t>& ttile_off = tp.ttile_off;
+    ttile_off.assign(p.n_int + 1, 0);
+    if (tp.tri) {
         // units: blocks of whole rows (at most 64) of about 8 chunks of 64 baselines (the
         // cost of a row is its chunk count), then ordered largest first and dealt in snake
         // order, so the round-robin share of each of the four wavefronts of a workgroup is
@@ -211,33 +215,101 @@ static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
                 }
             }
             ttile_off[k + 1] = (int32_t)ttiles.size();
-            if (ttiles.size() > (size_t)INT32_MAX / 2) return fail(WCAL_ESHAPE, "too many tiles");
+            if (ttiles.size() > (size_t)INT32_MAX / 4) return fail(WCAL_ESHAPE, "too many tiles");
         }
-        plan->nunits = (int32_t)units.size();
-        plan->nttiles = (int32_t)ttiles.size();
     }
     // statistics tiles in decreasing-size order (longest first)
     std::stable_sort(stiles.begin(), stiles.end(), [](const Tile& x, const Tile& y) {
         return (int64_t)(x.b1 - x.b0) * (x.s1 - x.s0) > (int64_t)(y.b1 - y.b0) * (y.s1 - y.s0);
     });
-    plan->ntiles = (int32_t)tiles.size();
-    plan->nstiles = (int32_t)stiles.size();
-    const int nvp = p.algo == WCAL_STEFCAL ? di_nvp(p.n_corr) : 0;
-    const int32_t ntmax = std::max(plan->ntiles, plan->nttiles);
-    hipError_t e = hipSuccess;
-    if (plan->tri && ((e = upload(&plan->d_units, units.data(), units.size())) != hipSuccess ||
-                      (e = upload(&plan->d_ttiles, ttiles.data(), ttiles.size())) != hipSuccess ||
-                      (e = upload(&plan->d_ttile_off, ttile_off.data(), ttile_off.size())) != hipSuccess))
-        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan units");
-    if ((e = upload(&plan->d_tiles, tiles.data(), tiles.size())) != hipSuccess ||
-        (e = upload(&plan->d_tile_off, tile_off.data(), tile_off.size())) != hipSuccess ||
-        (e = upload(&plan->d_stiles, stiles.data(), stiles.size())) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_lists), 2 * sizeof(int32_t) * std::max(1, ntmax))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_partial),
-                       sizeof(float) * std::max<size_t>(1, (size_t)ntmax * p.n_ant * nvp))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_chi_part), sizeof(double) * std::max(1, plan->ntiles))) != hipSuccess)
-        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tiles");
     return WCAL_OK;
+}
+
+// Workspace regions of a plan with the given tile counts (the triangle tiles drive the
+// device-side loop when `tri`).  Returns the bytes of the plan's own regions.
+static size_t layout_for(const wcal_plan* plan, int32_t ntiles, int32_t nttiles, bool tri, WsLayout& L) {
+    const wcal_problem& p = plan->prob;
+    const int32_t ntmax = std::max(ntiles, nttiles);
+    const bool di = p.algo == WCAL_STEFCAL;
+    const size_t nvp = di ? (size_t)di_nvp(p.n_corr) : 0;
+    size_t sz[WS_COUNT] = {};
+    sz[WS_CTR] = sizeof(int32_t) * (2 * ((size_t)p.max_iter + 2) + 16);
+    sz[WS_ACTIVE] = sizeof(int32_t) * (size_t)p.n_int;
+    sz[WS_QUEUE] = 4 * sizeof(int32_t);
+    sz[WS_LISTS] = 2 * sizeof(int32_t) * (size_t)std::max(1, ntmax);
+    sz[WS_PARTIAL] = sizeof(float) * std::max<size_t>(1, (size_t)ntmax * p.n_ant * nvp);
+    sz[WS_CHI_PART] = sizeof(double) * (size_t)std::max(1, ntiles);
+    if (di) {
+        if (di_stats_solve(plan)) sz[WS_STATS] = sizeof(float) * (size_t)p.n_int * p.n_bl * di_nstat(p.n_corr);
+        else if (plan->loop) sz[WS_LOOP] = loop_bytes(tri ? nttiles : ntiles, p.n_int);
+    } else {
+        sz[WS_STATS] = p.n_corr == 4 ? ddp_stats_bytes(p) : dd_stats_bytes(p);
+    }
+    L.off[0] = 0;
+    for (int i = 0; i < WS_COUNT; ++i) L.off[i + 1] = L.off[i] + ws_round(sz[i]);
+    return L.off[WS_COUNT];
+}
+
+extern "C++" void ws_layout(wcal_plan* plan) {
+    const size_t own = layout_for(plan, plan->ntiles, plan->nttiles, plan->tri, plan->ws);
+    plan->ws_bytes = own + (plan->smooth ? smooth_ws_bytes(plan->smooth) : 0);
+}
+
+extern "C++" void ws_bind(wcal_plan* plan, char* ws) {
+    const size_t* o = plan->ws.off;
+    plan->d_ctr = reinterpret_cast<int32_t*>(ws + o[WS_CTR]);
+    plan->d_active = reinterpret_cast<int32_t*>(ws + o[WS_ACTIVE]);
+    plan->d_queue = reinterpret_cast<int32_t*>(ws + o[WS_QUEUE]);
+    plan->d_lists = reinterpret_cast<int32_t*>(ws + o[WS_LISTS]);
+    plan->d_partial = reinterpret_cast<float*>(ws + o[WS_PARTIAL]);
+    plan->d_chi_part = reinterpret_cast<double*>(ws + o[WS_CHI_PART]);
+    plan->d_stats = reinterpret_cast<float*>(ws + o[WS_STATS]);
+    plan->stats_bytes = o[WS_STATS + 1] - o[WS_STATS];
+    plan->d_loop = reinterpret_cast<int32_t*>(ws + o[WS_LOOP]);
+    if (plan->smooth) smooth_ws_bind(plan->smooth, ws + o[WS_COUNT]);
+}
+
+extern "C++" int ws_check_bind(wcal_plan* plan, void* ws, size_t ws_bytes) {
+    if (!ws) return fail(WCAL_EINVAL, "workspace is NULL (size it with wcal_plan_workspace)");
+    if (reinterpret_cast<uintptr_t>(ws) % WS_ALIGN)
+        return fail(WCAL_EINVAL, "workspace must be " + std::to_string(WS_ALIGN) + "-byte aligned");
+    if (ws_bytes < plan->ws_bytes)
+        return fail(WCAL_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, the plan needs " +
+                                     std::to_string(plan->ws_bytes));
+    ws_bind(plan, reinterpret_cast<char*>(ws));
+    return WCAL_OK;
+}
+
+// Replace the plan's tile tables by those of `tp` and lay out its workspace anew.
+static int upload_tiles(wcal_plan* plan, const TilePlan& tp) {
+    for (void** q : {(void**)&plan->d_tiles, (void**)&plan->d_tile_off, (void**)&plan->d_stiles,
+                     (void**)&plan->d_units, (void**)&plan->d_ttiles, (void**)&plan->d_ttile_off}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+    plan->tile_rows = (int)tp.tile_rows;
+    plan->tri = tp.tri;
+    plan->ntiles = (int32_t)tp.tiles.size();
+    plan->nstiles = (int32_t)tp.stiles.size();
+    plan->nunits = tp.tri ? (int32_t)tp.units.size() : 0;
+    plan->nttiles = tp.tri ? (int32_t)tp.ttiles.size() : 0;
+    hipError_t e = hipSuccess;
+    if (tp.tri && ((e = upload(&plan->d_units, tp.units.data(), tp.units.size())) != hipSuccess ||
+                   (e = upload(&plan->d_ttiles, tp.ttiles.data(), tp.ttiles.size())) != hipSuccess ||
+                   (e = upload(&plan->d_ttile_off, tp.ttile_off.data(), tp.ttile_off.size())) != hipSuccess))
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan units");
+    if ((e = upload(&plan->d_tiles, tp.tiles.data(), tp.tiles.size())) != hipSuccess ||
+        (e = upload(&plan->d_tile_off, tp.tile_off.data(), tp.tile_off.size())) != hipSuccess ||
+        (e = upload(&plan->d_stiles, tp.stiles.data(), tp.stiles.size())) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tiles");
+    ws_layout(plan);
+    return WCAL_OK;
+}
+
+static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
+    TilePlan tp;
+    if (int rc = plan_tiles(plan, tile_rows, want_tri, tp)) return rc;
+    return upload_tiles(plan, tp);
 }
 
 int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int32_t* ant2_h,
@@ -327,6 +399,27 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
                 canonical = ant1_h[b] == a && ant2_h[b] == c;
         plan->canonical = canonical;
     }
+    // The device-side loop (one persistent launch per solve) is switched off: its first runs on
+    // the GPU did not finish and the cause is not found.  A request for it is refused.
+    if (const char* s = std::getenv("WCAL_LOOP")) {
+        if (atoi(s) != 0) {
+            delete plan;
+            return fail(WCAL_EINVAL, "the device-side iteration loop (WCAL_LOOP=1) is switched off");
+        }
+    }
+    {
+        // bound of the device-side loop's waits: WCAL_WAIT_MS milliseconds (default 10 s) in
+        // ticks of the real-time counter
+        // (the counter runs at 100 MHz on this family; a reported rate outside 1-1000 MHz is
+        // not trusted)
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz < 1000 ||
+            khz > 1000000)
+            khz = 100000;
+        double ms = 10000.0;
+        if (const char* s = std::getenv("WCAL_WAIT_MS")) ms = std::max(0.0, atof(s));
+        plan->wait_ticks = (int64_t)(ms * khz);
+    }
     const char* env_tri = std::getenv("WCAL_TRI");
     const int want_tri = env_tri ? atoi(env_tri) : -1;   // 0: never, 1: whenever allowed, unset: n_ant >= 64
     hipError_t e = hipSuccess;
@@ -334,33 +427,15 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
         wcal_plan_destroy(plan);
         return rc;
     }
-    if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_ctr), sizeof(int32_t) * (2 * (p.max_iter + 2) + 16))) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_active), sizeof(int32_t) * p.n_int)) != hipSuccess) {
-        wcal_plan_destroy(plan);
-        return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan state");
-    }
-    if (p.algo == WCAL_STEFCAL && di_stats_solve(plan)) {
-        plan->stats_bytes = sizeof(float) * (size_t)p.n_int * p.n_bl * di_nstat(p.n_corr);
-        if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
-            wcal_plan_destroy(plan);
-            return fail(WCAL_ENOMEM, "statistics allocation failed");
-        }
-    }
     if ((e = upload(&plan->d_ant1, ant1_h, p.n_bl)) != hipSuccess ||
         (e = upload(&plan->d_ant2, ant2_h, p.n_bl)) != hipSuccess ||
         (e = upload(&plan->d_row_off, off.data(), off.size())) != hipSuccess ||
         (e = upload(&plan->d_ns, ns32.data(), ns32.size())) != hipSuccess ||
-        (e = upload(&plan->d_order, order.data(), order.size())) != hipSuccess ||
-        (e = hipMalloc(reinterpret_cast<void**>(&plan->d_queue), 4 * sizeof(int32_t))) != hipSuccess) {
+        (e = upload(&plan->d_order, order.data(), order.size())) != hipSuccess) {
         wcal_plan_destroy(plan);
         return e == hipErrorOutOfMemory ? fail(WCAL_ENOMEM, "device allocation failed") : hip_fail(e, "plan tables");
     }
     if (p.algo != WCAL_STEFCAL) {
-        plan->stats_bytes = p.n_corr == 4 ? ddp_stats_bytes(p) : dd_stats_bytes(p);
-        if ((e = hipMalloc(reinterpret_cast<void**>(&plan->d_stats), plan->stats_bytes)) != hipSuccess) {
-            wcal_plan_destroy(plan);
-            return fail(WCAL_ENOMEM, "Gram record allocation failed");
-        }
         // rows touching each antenna: (baseline, side) in baseline order
         std::vector<int32_t> ptr(p.n_ant + 1, 0), bl(2 * (size_t)p.n_bl);
         for (int32_t b = 0; b < p.n_bl; ++b) { ++ptr[ant1_h[b] + 1]; ++ptr[ant2_h[b] + 1]; }
@@ -386,10 +461,9 @@ void wcal_plan_destroy(wcal_plan* plan) {
     (void)hipSetDevice(plan->device);
     smooth_free(plan->smooth);
     plan->smooth = nullptr;
+    // only the host-built tables are plan-owned; scratch lives in the caller's workspace
     for (void* p : {(void*)plan->d_ant1, (void*)plan->d_ant2, (void*)plan->d_row_off, (void*)plan->d_ns,
-                    (void*)plan->d_order, (void*)plan->d_queue, (void*)plan->d_stats, (void*)plan->d_tiles,
-                    (void*)plan->d_tile_off, (void*)plan->d_stiles, (void*)plan->d_lists, (void*)plan->d_ctr,
-                    (void*)plan->d_partial, (void*)plan->d_active, (void*)plan->d_chi_part,
+                    (void*)plan->d_order, (void*)plan->d_tiles, (void*)plan->d_tile_off, (void*)plan->d_stiles,
                     (void*)plan->d_ant_ptr, (void*)plan->d_ant_bl, (void*)plan->d_units, (void*)plan->d_ttiles,
                     (void*)plan->d_ttile_off})
         if (p) (void)hipFree(p);
@@ -404,6 +478,7 @@ const char* wcal_plan_pass_kernel(const wcal_plan* plan) {
     if (p.algo != WCAL_STEFCAL && p.n_corr == 4) return ddp_pass_kernel_name(p.n_dir);
     if (p.algo != WCAL_STEFCAL) return p.precision == WCAL_PREC_BF16_GRAM ? "dd_gram_dma_kernel" : "dd_gram_dmaf_kernel";
     if (di_stats_solve(plan)) return p.n_corr == 1 ? "di_stats_kernel<1>" : "di_stats_kernel<4>";
+    if (plan->loop) return plan->tri ? "di_loop_kernel<1, true>" : p.n_corr == 1 ? "di_loop_kernel<1, false>" : "di_loop_kernel<4, false>";
     if (plan->tri) return "di_tri_pass_kernel";
     return p.n_corr == 1 ? "di_pass_kernel<1>" : "di_pass_kernel<4>";
 }
@@ -454,15 +529,23 @@ static void fill_tables_dd(const wcal_plan* plan, DdArgs& a) {
     a.precision = plan->prob.precision;
 }
 
+int wcal_plan_workspace(const wcal_plan* plan, size_t* bytes) {
+    g_err.clear();
+    if (!plan || !bytes) return fail(WCAL_EINVAL, "NULL argument");
+    *bytes = plan->ws_bytes;
+    return WCAL_OK;
+}
+
 int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
                wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
-               void* stream) {
+               void* workspace, size_t ws_bytes, void* stream) {
     g_err.clear();
     int rc = check_common(plan, data, model, gains);
     if (rc) return rc;
     if (!n_iter || !status) return fail(WCAL_EINVAL, "n_iter and status are required");
     if (residual && !aligned(residual, plan->prob.n_corr == 4 ? 16 : 8))
         return fail(WCAL_EINVAL, "residual misaligned");
+    if ((rc = ws_check_bind(plan, workspace, ws_bytes))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
     if (plan->prob.algo == WCAL_STEFCAL) {
@@ -495,7 +578,7 @@ int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, con
 
 int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* data, const uint8_t* flags,
                       wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
-                      void* stream) {
+                      void* workspace, size_t ws_bytes, void* stream) {
     g_err.clear();
     if (!plan || !pts || !data || !gains || !n_iter || !status) return fail(WCAL_EINVAL, "NULL argument");
     const wcal_problem& p = plan->prob;
@@ -511,6 +594,7 @@ int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* d
         !aligned(pts->lmn, 8) || !aligned(pts->flux, 4))
         return fail(WCAL_EINVAL, "misaligned argument");
     if (hipSetDevice(plan->device) != hipSuccess) return fail(WCAL_EHIP, "hipSetDevice failed");
+    if (int rc = ws_check_bind(plan, workspace, ws_bytes)) return rc;
     DdArgs a{};
     fill_tables_dd(plan, a);
     a.data = reinterpret_cast<const float2*>(data);
@@ -532,15 +616,53 @@ int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* d
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve_points launch");
 }
 
+// Candidate tilings of the autotuner.
+static const int64_t kTuneRows[] = {8192, 16384, 32768, 65536, 131072, 262144};
+
+// Bytes of the autotuner's own scratch at the start of its workspace: a copy of the gains, the
+// update counts and the status words of the timed solves.
+static size_t tune_scratch_bytes(const wcal_problem& p) {
+    return ws_round((size_t)p.n_int * p.n_dir * p.n_ant * p.n_corr * sizeof(wcal_c64)) +
+           2 * ws_round(sizeof(int32_t) * (size_t)p.n_int);
+}
+
+static bool tune_tri_ok(const wcal_plan* plan) {
+    return plan->canonical && plan->prob.n_corr == 1 && !di_stats_solve(plan);
+}
+
+int wcal_plan_autotune_workspace(const wcal_plan* plan, size_t* bytes) {
+    g_err.clear();
+    if (!plan || !bytes) return fail(WCAL_EINVAL, "NULL argument");
+    const wcal_problem& p = plan->prob;
+    if (p.algo != WCAL_STEFCAL) {
+        *bytes = plan->ws_bytes;
+        return WCAL_OK;
+    }
+    const size_t extra = plan->smooth ? smooth_ws_bytes(plan->smooth) : 0;
+    size_t most = plan->ws_bytes;
+    for (int tri = 0; tri <= (tune_tri_ok(plan) ? 1 : 0); ++tri)
+        for (int64_t tr : kTuneRows) {
+            TilePlan tp;
+            if (int rc = plan_tiles(plan, tr, tri != 0, tp)) return rc;
+            WsLayout L;
+            most = std::max(most, layout_for(plan, (int32_t)tp.tiles.size(), (int32_t)tp.ttiles.size(), tp.tri, L) + extra);
+        }
+    *bytes = tune_scratch_bytes(p) + most;
+    return WCAL_OK;
+}
+
 int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
-                       const wcal_c64* gains, int32_t n_updates, void* stream, int32_t* tile_rows_out,
-                       int32_t* tri_out) {
+                       const wcal_c64* gains, int32_t n_updates, void* workspace, size_t ws_bytes, void* stream,
+                       int32_t* tile_rows_out, int32_t* tri_out) {
     g_err.clear();
     int rc = check_common(plan, data, model, gains);
     if (rc) return rc;
     if (n_updates < 0 || n_updates > plan->prob.max_iter)
         return fail(WCAL_EINVAL, "n_updates must be in [0, max_iter]");
     if (plan->prof) return fail(WCAL_EINVAL, "disable profiling before tuning");
+    if (!workspace) return fail(WCAL_EINVAL, "workspace is NULL (size it with wcal_plan_autotune_workspace)");
+    if (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN)
+        return fail(WCAL_EINVAL, "workspace must be " + std::to_string(WS_ALIGN) + "-byte aligned");
     wcal_problem& p = plan->prob;
     auto report = [&]() {
         if (tile_rows_out) *tile_rows_out = plan->tile_rows;
@@ -550,43 +672,51 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
     // CohJones / AllJones stream the rows in their own Gram pass: nothing to tune
     if (p.algo != WCAL_STEFCAL) return report();
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the tuner's scratch first, the solves' workspace after it
+    const size_t tune = tune_scratch_bytes(p);
+    if (ws_bytes < tune) return fail(WCAL_ENOMEM, "workspace smaller than the autotuner's scratch");
+    char* base = reinterpret_cast<char*>(workspace);
     const size_t gbytes = (size_t)p.n_int * p.n_dir * p.n_ant * p.n_corr * sizeof(wcal_c64);
-    wcal_c64* g = nullptr;
-    int32_t* nit = nullptr;
-    uint32_t* st = nullptr;
+    wcal_c64* g = reinterpret_cast<wcal_c64*>(base);
+    int32_t* nit = reinterpret_cast<int32_t*>(base + ws_round(gbytes));
+    uint32_t* st = reinterpret_cast<uint32_t*>(base + ws_round(gbytes) + ws_round(sizeof(int32_t) * p.n_int));
+    char* solve_ws = base + tune;
+    const size_t solve_bytes = ws_bytes - tune;
+    const size_t extra = plan->smooth ? smooth_ws_bytes(plan->smooth) : 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&]() {
-        if (g) (void)hipFree(g);
-        if (nit) (void)hipFree(nit);
-        if (st) (void)hipFree(st);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
-    if (hipMalloc(reinterpret_cast<void**>(&g), gbytes) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&nit), sizeof(int32_t) * p.n_int) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&st), sizeof(uint32_t) * p.n_int) != hipSuccess ||
-        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         cleanup();
-        return fail(WCAL_ENOMEM, "autotune scratch allocation failed");
+        return fail(WCAL_EHIP, "autotune events");
     }
     // every candidate applies exactly n_updates updates (tol 0) from the given gains, or with
     // n_updates = 0 runs the plan's own solve (to its tolerance, so the tail of the last
-    // intervals still iterating is timed too)
+    // intervals still iterating is timed too); candidates whose workspace does not fit are
+    // skipped
     const int saved_iter = p.max_iter;
     const double saved_tol = p.tol;
     if (n_updates > 0) {
         p.max_iter = n_updates;
         p.tol = 0.0;
     }
-    const bool tri_ok = plan->canonical && p.n_corr == 1 && !di_stats_solve(plan);
-    const int64_t rows_cand[] = {8192, 16384, 32768, 65536, 131072, 262144};
-    int64_t best_rows = plan->tile_rows;
-    bool best_tri = plan->tri;
+    const int64_t start_rows = plan->tile_rows;
+    const bool start_tri = plan->tri;
+    int64_t best_rows = start_rows;
+    bool best_tri = start_tri;
     float best_ms = 1e30f;
-    int err = WCAL_OK;
-    for (int tri = 0; tri <= (tri_ok ? 1 : 0) && err == WCAL_OK; ++tri) {
-        for (int64_t tr : rows_cand) {
-            if ((err = build_tiles(plan, tr, tri != 0)) != WCAL_OK) break;
+    int err = WCAL_OK, tried = 0;
+    for (int tri = 0; tri <= (tune_tri_ok(plan) ? 1 : 0) && err == WCAL_OK; ++tri) {
+        for (int64_t tr : kTuneRows) {
+            TilePlan tp;
+            if ((err = plan_tiles(plan, tr, tri != 0, tp)) != WCAL_OK) break;
+            WsLayout L;
+            if (layout_for(plan, (int32_t)tp.tiles.size(), (int32_t)tp.ttiles.size(), tp.tri, L) + extra > solve_bytes)
+                continue;
+            if ((err = upload_tiles(plan, tp)) != WCAL_OK) break;
+            ++tried;
             float ms = 1e30f;
             for (int rep = 0; rep < 3 && err == WCAL_OK; ++rep) {
                 if (hipMemcpyAsync(g, gains, gbytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -594,7 +724,7 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
                     err = fail(WCAL_EHIP, "autotune copy failed");
                     break;
                 }
-                err = wcal_solve(plan, data, model, flags, g, nullptr, nit, st, nullptr, stream);
+                err = wcal_solve(plan, data, model, flags, g, nullptr, nit, st, nullptr, solve_ws, solve_bytes, stream);
                 if (err != WCAL_OK) break;
                 float t = 0.f;
                 if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -614,7 +744,12 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
     p.max_iter = saved_iter;
     p.tol = saved_tol;
     cleanup();
-    if (err != WCAL_OK) return err;
+    if (err == WCAL_OK && tried == 0)
+        err = fail(WCAL_ENOMEM, "no candidate tiling fits the workspace (size it with wcal_plan_autotune_workspace)");
+    if (err != WCAL_OK) {
+        (void)build_tiles(plan, start_rows, start_tri);
+        return err;
+    }
     if ((err = build_tiles(plan, best_rows, best_tri)) != WCAL_OK) return err;
     return report();
 }
@@ -627,7 +762,7 @@ struct wcal_graph {
 
 int wcal_solve_graph(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
                      wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
-                     void* stream, wcal_graph** out) {
+                     void* workspace, size_t ws_bytes, void* stream, wcal_graph** out) {
     g_err.clear();
     if (!out) return fail(WCAL_EINVAL, "out is NULL");
     *out = nullptr;
@@ -648,7 +783,7 @@ int wcal_solve_graph(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mode
     };
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return done(fail(WCAL_EHIP, "hipStreamBeginCapture failed"));
-    const int rc = wcal_solve(plan, data, model, flags, gains, residual, n_iter, status, chi2, s);
+    const int rc = wcal_solve(plan, data, model, flags, gains, residual, n_iter, status, chi2, workspace, ws_bytes, s);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &graph);
     if (rc != WCAL_OK) {
@@ -686,13 +821,14 @@ void wcal_graph_destroy(wcal_graph* graph) {
 
 int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
                     const wcal_c64* gains, wcal_c64* jhj, wcal_c64* jhd, wcal_c64* jhr, int32_t* count,
-                    double* chi2, wcal_c64* residual, void* stream) {
+                    double* chi2, wcal_c64* residual, void* workspace, size_t ws_bytes, void* stream) {
     g_err.clear();
     int rc = check_common(plan, data, model, gains);
     if (rc) return rc;
     if (!jhj || !jhd || !jhr) return fail(WCAL_EINVAL, "jhj, jhd and jhr are required");
     if (residual && !aligned(residual, plan->prob.n_corr == 4 ? 16 : 8))
         return fail(WCAL_EINVAL, "residual misaligned");
+    if ((rc = ws_check_bind(plan, workspace, ws_bytes))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
     if (plan->prob.algo == WCAL_STEFCAL) {
@@ -728,13 +864,15 @@ int wcal_accumulate(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model
 }
 
 int wcal_residual(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, const uint8_t* flags,
-                  const wcal_c64* gains, wcal_c64* residual, double* chi2, void* stream) {
+                  const wcal_c64* gains, wcal_c64* residual, double* chi2, void* workspace, size_t ws_bytes,
+                  void* stream) {
     g_err.clear();
     int rc = check_common(plan, data, model, gains);
     if (rc) return rc;
     if (!residual && !chi2) return fail(WCAL_EINVAL, "residual or chi2 is required");
     if (residual && !aligned(residual, plan->prob.n_corr == 4 ? 16 : 8))
         return fail(WCAL_EINVAL, "residual misaligned");
+    if ((rc = ws_check_bind(plan, workspace, ws_bytes))) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
     if (plan->prob.algo == WCAL_STEFCAL) {

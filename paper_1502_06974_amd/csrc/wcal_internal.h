@@ -27,6 +27,35 @@ struct TriUnit {
     int32_t p0, p1, entries, chunks;   // chunks: sum over rows of ceil(length / 64)
 };
 
+// ------------------------------------------------------------------ workspace
+// Per-call device scratch is carved out of the caller's workspace (wcal_plan_workspace): one
+// region per kind of scratch, each starting on a WS_ALIGN boundary.  The plan keeps only the
+// tables it builds on the host (baselines, interval offsets, tiles, units, antenna lists).
+constexpr size_t WS_ALIGN = 256;
+enum WsRegion {
+    WS_CTR,       // int32 work counters of the per-update launches
+    WS_ACTIVE,    // int32 [n_int] intervals still iterating
+    WS_QUEUE,     // int32 [4] queue counters (accumulate pass)
+    WS_LISTS,     // int32 [2][tiles] active-tile lists of the per-update launches
+    WS_PARTIAL,   // float [tiles][n_ant][nvp] per-tile per-antenna sums
+    WS_CHI_PART,  // double [tiles] chi^2 per residual tile
+    WS_STATS,     // statistics (STATS mode) or the direction-dependent solve state
+    WS_LOOP,      // the device-side iteration loop: control words, tile ring, per-interval counters
+    WS_COUNT
+};
+struct WsLayout {
+    size_t off[WS_COUNT + 1] = {};   // off[WS_COUNT]: bytes of the plan's own regions
+};
+inline size_t ws_round(size_t n) { return (n + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+
+// The device-side iteration loop of the StefCal PASS solve (one persistent launch, the ring
+// of loop_ring.h): 64 bytes of control words, LOOP_RING ring slots per tile, one tile
+// counter per interval.
+constexpr int LOOP_RING = 2;
+inline size_t loop_bytes(int64_t ntiles, int64_t n_int) {
+    return 64 + ws_round(sizeof(uint64_t) * LOOP_RING * (size_t)ntiles) + sizeof(int32_t) * (size_t)n_int;
+}
+
 // ------------------------------------------------------------------ plan
 struct wcal_plan {
     wcal_problem prob;
@@ -76,10 +105,27 @@ struct wcal_plan {
     Profiler* prof = nullptr;     // non-null while timing is enabled
     // time/frequency smoothing (scalar StefCal): the cell plan and its scratch, or null
     struct SmoothPlan* smooth = nullptr;
+    // workspace: the plan's own regions, then (with smoothing) the smoothing scratch and the
+    // cell plan's workspace
+    WsLayout ws;
+    size_t ws_bytes = 0;          // total the caller must provide
+    bool loop = false;            // StefCal PASS solve as one persistent launch: switched off (its first GPU
+                                  // runs did not finish, cause not found)
+    int64_t wait_ticks = 1000000000;  // bound of the loop's waits (10 s; WCAL_WAIT_MS)
+    int32_t* d_loop = nullptr;    // WS_LOOP region while bound
 };
 
 // record the message returned by wcal_last_error() and return `code`
 int wcal_error(int code, const std::string& msg);
+
+// Workspace of a plan: lay out its regions (after tiling or smoothing changes) and point its
+// scratch fields into a caller's buffer.
+void ws_layout(wcal_plan* plan);
+void ws_bind(wcal_plan* plan, char* ws);
+size_t smooth_ws_bytes(const struct SmoothPlan* sp);
+void smooth_ws_bind(struct SmoothPlan* sp, char* ws);
+// checks a caller's workspace against the plan (WCAL_EINVAL / WCAL_ENOMEM), binds it
+int ws_check_bind(wcal_plan* plan, void* ws, size_t ws_bytes);
 
 // ------------------------------------------------------------------ kernel arguments
 struct DiArgs {

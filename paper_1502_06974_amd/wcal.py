@@ -16,8 +16,9 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libwcal.so")
 
-OK, EINVAL, EINDEX, ESHAPE, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
-CONVERGED, MAXITER, SINGULAR_ANT, NONFINITE = 1, 2, 4, 8
+OK, EINVAL, EINDEX, ESHAPE, EHIP, ENOMEM, EIO = 0, -1, -2, -3, -4, -5, -6
+CONVERGED, MAXITER, SINGULAR_ANT, NONFINITE, ABORTED = 1, 2, 4, 8, 16
+WS_ALIGN = 256
 STEFCAL, COHJONES, ALLJONES = 0, 1, 2
 AVG_FIRST, GN_FIRST, GN_ONLY = 0, 1, 2
 _ALGOS = {"stefcal": STEFCAL, "cohjones": COHJONES, "alljones": ALLJONES}
@@ -29,13 +30,14 @@ _PRECS = {"fp32": PREC_FP32, "bf16": PREC_BF16_GRAM}
 
 # every symbol the header declares
 EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_destroy",
-           "wcal_plan_rows", "wcal_plan_pass_kernel", "wcal_plan_autotune", "wcal_solve", "wcal_solve_graph", "wcal_graph_launch",
+           "wcal_plan_rows", "wcal_plan_workspace", "wcal_plan_autotune_workspace",
+           "wcal_plan_pass_kernel", "wcal_plan_autotune", "wcal_solve", "wcal_solve_graph", "wcal_graph_launch",
            "wcal_graph_destroy", "wcal_accumulate", "wcal_residual",
            "wcal_profile_enable", "wcal_profile_read", "wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains",
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
-           "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth",
-           "wcal_solve_points")
+           "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_mlp_save", "wcal_mlp_load",
+           "wcal_plan_smoothing", "wcal_solve_smooth", "wcal_solve_points")
 K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
@@ -78,27 +80,31 @@ def lib() -> C.CDLL:
     L.wcal_plan_destroy.restype = None
     L.wcal_plan_rows.argtypes = [vp]
     L.wcal_plan_rows.restype = C.c_int64
-    L.wcal_plan_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp, vp]
+    L.wcal_plan_workspace.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.wcal_plan_workspace.restype = C.c_int
+    L.wcal_plan_autotune_workspace.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.wcal_plan_autotune_workspace.restype = C.c_int
+    L.wcal_plan_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, C.c_size_t, vp, vp, vp]
     L.wcal_plan_autotune.restype = C.c_int
     L.wcal_plan_pass_kernel.argtypes = [vp]
     L.wcal_plan_pass_kernel.restype = C.c_char_p
-    L.wcal_solve.argtypes = [vp] * 9 + [vp]
+    L.wcal_solve.argtypes = [vp] * 10 + [C.c_size_t, vp]
     L.wcal_solve.restype = C.c_int
-    L.wcal_solve_graph.argtypes = [vp] * 10 + [C.POINTER(C.c_void_p)]
+    L.wcal_solve_graph.argtypes = [vp] * 10 + [C.c_size_t, vp, C.POINTER(C.c_void_p)]
     L.wcal_solve_graph.restype = C.c_int
     L.wcal_graph_launch.argtypes = [vp, vp]
     L.wcal_graph_launch.restype = C.c_int
     L.wcal_graph_destroy.argtypes = [vp]
     L.wcal_graph_destroy.restype = None
-    L.wcal_accumulate.argtypes = [vp] * 12
+    L.wcal_accumulate.argtypes = [vp] * 12 + [C.c_size_t, vp]
     L.wcal_accumulate.restype = C.c_int
-    L.wcal_residual.argtypes = [vp] * 8
+    L.wcal_residual.argtypes = [vp] * 8 + [C.c_size_t, vp]
     L.wcal_residual.restype = C.c_int
     L.wcal_plan_smoothing.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double]
     L.wcal_plan_smoothing.restype = C.c_int
-    L.wcal_solve_smooth.argtypes = [vp] * 10
+    L.wcal_solve_smooth.argtypes = [vp] * 10 + [C.c_size_t, vp]
     L.wcal_solve_smooth.restype = C.c_int
-    L.wcal_solve_points.argtypes = [vp, C.POINTER(Points)] + [vp] * 8
+    L.wcal_solve_points.argtypes = [vp, C.POINTER(Points)] + [vp] * 8 + [C.c_size_t, vp]
     L.wcal_solve_points.restype = C.c_int
     L.wcal_profile_enable.argtypes = [vp, C.c_int]
     L.wcal_profile_enable.restype = C.c_int
@@ -120,10 +126,12 @@ def lib() -> C.CDLL:
     L.wcal_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp]
     L.wcal_mlp_gradients.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
     L.wcal_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, vp, vp]
+    L.wcal_mlp_save.argtypes = [vp, C.c_char_p]
+    L.wcal_mlp_load.argtypes = [vp, C.c_char_p]
     for f in ("wcal_bin_knots", "wcal_gather_knots", "wcal_bins_to_gains", "wcal_gains_to_bins", "wcal_reset_unconverged",
               "wcal_mlp_create", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
-              "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_plan_smoothing", "wcal_solve_smooth",
-           "wcal_solve_points"):
+              "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_mlp_save", "wcal_mlp_load", "wcal_plan_smoothing",
+              "wcal_solve_smooth", "wcal_solve_points"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -158,6 +166,34 @@ class Plan:
                                   C.byref(self._h)))
         self.rows = int(L.wcal_plan_rows(self._h))
         self.pass_kernel = L.wcal_plan_pass_kernel(self._h).decode()
+        self._ws = None
+
+    # ---------------------------------------------------------------- workspace
+    def workspace_bytes(self) -> int:
+        """wcal_plan_workspace: device scratch every compute call on this plan needs."""
+        n = C.c_size_t(0)
+        _check(lib().wcal_plan_workspace(self._h, C.byref(n)))
+        return int(n.value)
+
+    @staticmethod
+    def _alloc(nbytes: int, device) -> torch.Tensor:
+        ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+        if ws.data_ptr() % WS_ALIGN:
+            raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
+        return ws
+
+    def workspace(self, device=None) -> torch.Tensor:
+        """The plan's workspace (a uint8 device tensor owned by this object, allocated by torch
+        on first use and whenever the plan needs more)."""
+        need = self.workspace_bytes()
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = self._alloc(need, device if device is not None else torch.device("cuda", self.device))
+        return self._ws
+
+    def _ws_args(self, workspace):
+        ws = self.workspace() if workspace is None else workspace
+        return _ptr(ws), C.c_size_t(ws.numel()), ws
 
     def close(self):
         if self._h:
@@ -211,7 +247,7 @@ class Plan:
 
     # ---------------------------------------------------------------- calls
     def solve(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
-              chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True):
+              chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True, workspace=None):
         """wcal_solve: gains are updated in place.  Returns dict of output tensors."""
         self._inputs(data, model, flags, gains)
         dev = gains.device
@@ -227,8 +263,9 @@ class Plan:
         self._dev(n_iter, "n_iter", torch.int32, (self.n_int,))
         self._dev(status, "status", torch.int32, (self.n_int,))
         self._dev(chi2, "chi2", torch.float64, (self.n_int,))
+        wp, wn, _ = self._ws_args(workspace)
         _check(lib().wcal_solve(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
-                                _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2),
+                                _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2), wp, wn,
                                 self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
@@ -237,13 +274,19 @@ class Plan:
         or whole solves to the plan's tolerance with 0) and keep the fastest."""
         self._inputs(data, model, flags, gains)
         tr, tri = C.c_int32(0), C.c_int32(0)
+        n = C.c_size_t(0)
+        _check(lib().wcal_plan_autotune_workspace(self._h, C.byref(n)))
+        ws = self._alloc(n.value, gains.device)
         _check(lib().wcal_plan_autotune(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains), n_updates,
-                                        self._stream(stream), C.byref(tr), C.byref(tri)))
+                                        _ptr(ws), C.c_size_t(ws.numel()), self._stream(stream), C.byref(tr),
+                                        C.byref(tri)))
+        del ws
         self.pass_kernel = lib().wcal_plan_pass_kernel(self._h).decode()
         return {"tile_rows": tr.value, "triangle": bool(tri.value), "pass_kernel": self.pass_kernel}
 
     def solve_graph(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
-                    chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True) -> "Graph":
+                    chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True,
+                    workspace=None) -> "Graph":
         """wcal_solve_graph: the solve captured into a replayable HIP graph bound to these
         tensors (kept alive by the returned object)."""
         self._inputs(data, model, flags, gains)
@@ -261,14 +304,16 @@ class Plan:
         self._dev(status, "status", torch.int32, (self.n_int,))
         self._dev(chi2, "chi2", torch.float64, (self.n_int,))
         h = C.c_void_p()
+        # the graph holds the workspace's address: a private one, kept alive with the graph
+        ws = self._alloc(self.workspace_bytes(), gains.device) if workspace is None else workspace
         _check(lib().wcal_solve_graph(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
                                       _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2),
-                                      self._stream(stream), C.byref(h)))
+                                      _ptr(ws), C.c_size_t(ws.numel()), self._stream(stream), C.byref(h)))
         return Graph(h, self, dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2,
-                                   data=data, model=model, flags=flags))
+                                   data=data, model=model, flags=flags, workspace=ws))
 
     def accumulate(self, data, model, flags, gains, residual=None, stream=None,
-                   want_residual: bool = False):
+                   want_residual: bool = False, workspace=None):
         """wcal_accumulate: one fused pass at fixed gains."""
         self._inputs(data, model, flags, gains)
         dev = gains.device
@@ -282,9 +327,10 @@ class Plan:
         if residual is None and want_residual:
             residual = torch.empty_like(data)
         self._dev(residual, "residual", torch.complex64, (self.rows, nc))
+        wp, wn, _ = self._ws_args(workspace)
         _check(lib().wcal_accumulate(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
                                      _ptr(jhj), _ptr(jhd), _ptr(jhr), _ptr(count), _ptr(chi2),
-                                     _ptr(residual), self._stream(stream)))
+                                     _ptr(residual), wp, wn, self._stream(stream)))
         return dict(jhj=jhj, jhd=jhd, jhr=jhr, count=count, chi2=chi2, residual=residual)
 
     def smoothing(self, n_time: int, n_chan: int, sigma_t: float, sigma_f: float):
@@ -292,9 +338,10 @@ class Plan:
         grid with its own gains, smoothed by a Gaussian of widths sigma_t, sigma_f cells."""
         _check(lib().wcal_plan_smoothing(self._h, int(n_time), int(n_chan), float(sigma_t), float(sigma_f)))
         self.smooth_cells = int(n_time) * int(n_chan)
+        self._ws = None
 
     def solve_smooth(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
-                     chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True):
+                     chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True, workspace=None):
         """wcal_solve_smooth: gains [n_int][cells][n_ant] (complex64) are updated in place."""
         R = self.rows
         self._dev(data, "data", torch.complex64, (R, 1))
@@ -312,13 +359,14 @@ class Plan:
         if chi2 is None and want_chi2:
             chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
         self._dev(residual, "residual", torch.complex64, (R, 1))
+        wp, wn, _ = self._ws_args(workspace)
         _check(lib().wcal_solve_smooth(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains), _ptr(residual),
-                                       _ptr(n_iter), _ptr(status), _ptr(chi2), self._stream(stream)))
+                                       _ptr(n_iter), _ptr(status), _ptr(chi2), wp, wn, self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
     def solve_points(self, n_time: int, n_chan: int, freq0: float, dfreq: float, uvw, lmn, flux, data, flags,
                      gains, residual=None, n_iter=None, status=None, chi2=None, stream=None,
-                     want_residual: bool = True, want_chi2: bool = True):
+                     want_residual: bool = True, want_chi2: bool = True, workspace=None):
         """wcal_solve_points: the point-source model (uvw [n_int][n_time][n_bl][3] float64,
         lmn [n_dir][3] float64, flux [n_dir] float32, device) predicted in the passes."""
         R = self.rows
@@ -340,19 +388,21 @@ class Plan:
             chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
         self._dev(residual, "residual", torch.complex64, (R, 1))
         pts = Points(int(n_time), int(n_chan), float(freq0), float(dfreq), _ptr(uvw), _ptr(lmn), _ptr(flux))
+        wp, wn, _ = self._ws_args(workspace)
         _check(lib().wcal_solve_points(self._h, C.byref(pts), _ptr(data), _ptr(flags), _ptr(gains), _ptr(residual),
-                                       _ptr(n_iter), _ptr(status), _ptr(chi2), self._stream(stream)))
+                                       _ptr(n_iter), _ptr(status), _ptr(chi2), wp, wn, self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
-    def residual(self, data, model, flags, gains, residual=None, stream=None):
+    def residual(self, data, model, flags, gains, residual=None, stream=None, workspace=None):
         """wcal_residual: R = D - sum_d G_p M G_q^H and chi^2 per interval."""
         self._inputs(data, model, flags, gains)
         if residual is None:
             residual = torch.empty_like(data)
         self._dev(residual, "residual", torch.complex64, (self.rows, self.n_corr))
         chi2 = torch.empty(self.n_int, dtype=torch.float64, device=gains.device)
+        wp, wn, _ = self._ws_args(workspace)
         _check(lib().wcal_residual(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
-                                   _ptr(residual), _ptr(chi2), self._stream(stream)))
+                                   _ptr(residual), _ptr(chi2), wp, wn, self._stream(stream)))
         return dict(residual=residual, chi2=chi2)
 
 
@@ -475,6 +525,17 @@ class Mlp:
     def train_step(self, x, t, lr: float, loss: Optional[torch.Tensor] = None):
         _check(lib().wcal_mlp_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], float(lr), _ptr(loss),
                                          _cur_stream()))
+
+    def save(self, path: str):
+        """wcal_mlp_save: JSON header line + float32 parameters and Adam moments (waits for the
+        current stream first)."""
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().wcal_mlp_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """wcal_mlp_load: parameters and Adam state from a weight file of the same shape."""
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().wcal_mlp_load(self._h, os.fsencode(path)))
 
 
 def plan_for(problem, algo: Optional[str] = None, **kw) -> Plan:

@@ -79,13 +79,18 @@ def test_null_arguments():
     L = wcal.lib()
     h = C.c_void_p()
     assert L.wcal_plan_create(None, None, None, None, 0, C.byref(h)) == wcal.EINVAL
-    assert L.wcal_solve(None, None, None, None, None, None, None, None, None, None) == wcal.EINVAL
-    assert L.wcal_accumulate(*([None] * 12)) == wcal.EINVAL
-    assert L.wcal_residual(*([None] * 8)) == wcal.EINVAL
+    assert L.wcal_solve(*([None] * 10), 0, None) == wcal.EINVAL
+    assert L.wcal_accumulate(*([None] * 12), 0, None) == wcal.EINVAL
+    assert L.wcal_residual(*([None] * 8), 0, None) == wcal.EINVAL
     assert L.wcal_plan_rows(None) == -1
+    n = C.c_size_t(7)
+    assert L.wcal_plan_workspace(None, C.byref(n)) == wcal.EINVAL
+    assert L.wcal_plan_autotune_workspace(None, C.byref(n)) == wcal.EINVAL
     assert L.wcal_plan_smoothing(None, 1, 4, 0.0, 1.0) == wcal.EINVAL
-    assert L.wcal_solve_smooth(*([None] * 10)) == wcal.EINVAL
-    assert L.wcal_solve_points(None, None, *([None] * 8)) == wcal.EINVAL
+    assert L.wcal_solve_smooth(*([None] * 10), 0, None) == wcal.EINVAL
+    assert L.wcal_solve_points(None, None, *([None] * 8), 0, None) == wcal.EINVAL
+    assert L.wcal_mlp_save(None, b"/tmp/x") == wcal.EINVAL
+    assert L.wcal_mlp_load(None, b"/tmp/x") == wcal.EINVAL
     L.wcal_plan_destroy(None)
 
 

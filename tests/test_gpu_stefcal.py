@@ -15,6 +15,7 @@ import torch
 from oracle import calib as oc
 from paper_1502_06974_amd import synth, wcal
 from oracle import driver as glue
+from gains_check import gain_err, oracle_stop, stop_decision_is_clear
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -23,10 +24,6 @@ DEV = "cuda"
 def log(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
 def perturbed_gains(P, scale=0.3, seed=0):
@@ -90,9 +87,10 @@ MODES = ["pass", "stats"]
 
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("kind", ["scalar", "pol"])
-@pytest.mark.parametrize("schedule", ["avg_first", "gn_first"])
+@pytest.mark.parametrize("schedule", ["avg_first", "gn_first", "gn_only"])
 def test_solve_lockstep(kind, schedule, mode):
-    """Both sides apply exactly 8 updates from the same start (tol = 0)."""
+    """Both sides apply exactly 8 updates from the same start (tol = 0).  gn_only is the plain
+    GN iteration that Sect. 3.1 says oscillates; it is compared update for update too."""
     log(f"[lockstep] kind={kind} schedule={schedule} mode={mode}")
     P = make(kind, 40, [2, 9, 33, 70], flag_frac=0.05, seed=2)
     g0 = P.unit_gains()
@@ -103,7 +101,8 @@ def test_solve_lockstep(kind, schedule, mode):
     for k in range(P.n_int):
         o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=8, schedule=schedule)
         go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
-        assert rel(g[k], go) <= 1e-5, (k, rel(g[k], go))
+        e = gain_err(g[k], go, P.n_corr)
+        assert e <= 1e-5, (k, e)
         assert int(out["n_iter"][k]) == 8 and int(out["status"][k]) == oc.MAXITER
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
@@ -123,8 +122,11 @@ def test_solve_converged(kind, mode):
         o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=1e-12, max_iter=2000)
         go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
         assert st[k] & oc.CONVERGED
-        e = rel(glue.align(g[k], go, 1), go)
+        e = gain_err(glue.align(g[k], go, 1), go, P.n_corr)
         assert e <= 1e-5, (k, e)
+        n_stop = oracle_stop(o["history"], 1e-6, 200)
+        if stop_decision_is_clear(o["history"], 1e-6, n_stop):
+            assert int(out["n_iter"][k]) == n_stop, (k, int(out["n_iter"][k]), n_stop)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -211,17 +213,21 @@ def test_residual_entry_point():
 
 
 # ------------------------------------------------------------------ full-size workloads
-def _check_sampled(P, out, ks, tol_oracle=1e-10):
+def _check_sampled(P, out, ks, tol_oracle=1e-10, max_iter=100):
     g = out["gains"].cpu().numpy()
     st = out["status"].cpu().numpy()
     for k in ks:
         o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=tol_oracle, max_iter=2000)
         go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
-        e = rel(glue.align(g[k], go, 1), go)
+        e = gain_err(glue.align(g[k], go, 1), go, P.n_corr)
+        n_stop = oracle_stop(o["history"], 1e-6, max_iter)
+        clear = stop_decision_is_clear(o["history"], 1e-6, n_stop)
         log(f"  interval {k}: ns={int(P.ns[k])} gpu_iter={int(out['n_iter'][k])} "
-            f"oracle_iter={o['n_iter']} status={st[k]} err={e:.2e}")
+            f"oracle_stop={n_stop} (clear={clear}) status={st[k]} err={e:.2e}")
         assert st[k] & oc.CONVERGED
         assert e <= 1e-5
+        if clear:
+            assert int(out["n_iter"][k]) == n_stop
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
 
@@ -233,7 +239,7 @@ def test_scalar_na27_full(mode):
     plan = wcal.plan_for(P, tol=1e-6, max_iter=200, mode=mode)
     out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
     torch.cuda.synchronize()
-    _check_sampled(P, out, [0])
+    _check_sampled(P, out, [0], max_iter=200)
 
 
 def test_pol2x2_na64_full_size_sampled():
@@ -281,7 +287,7 @@ def test_pass_and_stats_modes_agree():
         outs[mode] = plan.solve(P.data, P.model, P.flags, P.unit_gains())
     torch.cuda.synchronize()
     a, b = outs["pass"]["gains"].cpu().numpy(), outs["stats"]["gains"].cpu().numpy()
-    assert rel(a, b) < 1e-5
+    assert gain_err(a, b, P.n_corr) < 1e-5
     assert torch.equal(outs["pass"]["status"].cpu(), outs["stats"]["status"].cpu())
 
 
@@ -298,7 +304,7 @@ def test_small_tiles_split_intervals(tile_rows, monkeypatch):
     for k in range(P.n_int):
         o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=6)
         go = glue.gains_from_oracle(o["g"], P.n_corr, 1)
-        assert rel(g[k], go) <= 1e-5
+        assert gain_err(g[k], go, P.n_corr) <= 1e-5
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
 
@@ -322,7 +328,8 @@ def test_triangle_pass_lockstep(n_ant, ns, monkeypatch):
     for k in range(P.n_int):
         o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=6)
         go = glue.gains_from_oracle(o["g"], 1, 1)
-        assert rel(g[k], go) <= 1e-5, (k, rel(g[k], go))
+        e = gain_err(g[k], go, 1)
+        assert e <= 1e-5, (k, e)
         assert int(out["n_iter"][k]) == 6 and int(out["status"][k]) == oc.MAXITER
         assert abs(float(out["chi2"][k]) - o["chi2"]) <= 1e-4 * o["chi2"]
 
@@ -331,7 +338,12 @@ def test_triangle_pass_lockstep(n_ant, ns, monkeypatch):
 @pytest.mark.parametrize("n_ant", [2, 3])
 def test_smallest_arrays_lockstep(n_ant, tri, monkeypatch):
     """Two antennas (one baseline: a triangle of one row of length 1) and three, through the
-    triangle pass and the generic pass, scalar and 2x2: six updates on both sides."""
+    triangle pass and the generic pass, scalar and 2x2: six updates on both sides.  Two
+    antennas leave the gains free along directions the data cannot see (scalar: the ratio of
+    the two amplitudes; 2x2 with one sample: four equations for eight unknowns), and the
+    iterates drift along them with the rounding; there the unique result, the fitted
+    visibilities G_p M G_q^H = D - R of every row, is compared, and the gains of three
+    antennas, which are determined, are compared directly."""
     log(f"[smallest arrays] n_ant={n_ant} triangle={tri}")
     monkeypatch.setenv("WCAL_TRI", tri)
     for kind in ("scalar", "pol"):
@@ -344,7 +356,15 @@ def test_smallest_arrays_lockstep(n_ant, tri, monkeypatch):
         for k in range(P.n_int):
             o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=6)
             go = glue.gains_from_oracle(o["g"], nc, 1)
-            assert rel(g[k], go) <= 1e-5, (kind, k, rel(g[k], go))
+            if n_ant > 2:
+                e = gain_err(g[k], go, nc)
+            else:
+                a, b = int(P.row_off[k]), int(P.row_off[k + 1])
+                d = P.interval(k)["d"].reshape(-1, nc)
+                fit = d - out["residual"][a:b].cpu().numpy().astype(np.complex128)
+                fit_o = d - o["residual"].reshape(-1, nc)
+                e = gain_err(fit, fit_o, nc)
+            assert e <= 1e-5, (kind, k, e)
             assert int(out["n_iter"][k]) == 6 and int(out["status"][k]) == o["status"]
             # one baseline can be fitted exactly: chi^2 then sits at the FP32 rounding of the
             # residual, so the bound has a floor at 1e-9 of the data power
@@ -364,7 +384,7 @@ def test_triangle_pass_split_tiles(monkeypatch):
     g = out["gains"].cpu().numpy()
     for k in range(P.n_int):
         o = glue.solve(P, k, P.unit_gains()[k].cpu().numpy(), tol=0.0, max_iter=5)
-        assert rel(g[k], glue.gains_from_oracle(o["g"], 1, 1)) <= 1e-5
+        assert gain_err(g[k], glue.gains_from_oracle(o["g"], 1, 1), 1) <= 1e-5
 
 
 def test_triangle_pass_matches_generic_and_is_reproducible(monkeypatch):
@@ -377,7 +397,7 @@ def test_triangle_pass_matches_generic_and_is_reproducible(monkeypatch):
         outs[tri] = [plan.solve(P.data, P.model, P.flags, P.unit_gains()) for _ in range(2)]
     torch.cuda.synchronize()
     a, b = outs["0"][0]["gains"].cpu().numpy(), outs["1"][0]["gains"].cpu().numpy()
-    assert rel(b, a) <= 1e-5
+    assert gain_err(b, a, 1) <= 1e-5
     assert np.all(outs["1"][0]["status"].cpu().numpy() & oc.CONVERGED)
     for key in ("gains", "n_iter", "chi2"):
         x, y = outs["1"][0][key].cpu(), outs["1"][1][key].cpu()
@@ -385,13 +405,15 @@ def test_triangle_pass_matches_generic_and_is_reproducible(monkeypatch):
                            y.view(torch.uint8) if y.is_complex() else y), key
 
 
-def test_triangle_pass_flags_and_status(monkeypatch):
+@pytest.mark.parametrize("n_ant", [70, 130])
+def test_triangle_pass_flags_and_status(n_ant, monkeypatch):
     """Garbage under flags leaves every output bit-identical; a fully flagged antenna is
     SINGULAR_ANT with its gain kept; NaN in an unflagged row stops the interval before any
-    update; status bits equal the oracle's."""
-    log("[triangle flags/status]")
+    update; status bits equal the oracle's.  130 antennas run the packed-row walk (row
+    n_ant - 2 - r with row r, the middle row without partner)."""
+    log(f"[triangle flags/status] n_ant={n_ant}")
     monkeypatch.setenv("WCAL_TRI", "1")
-    P = make("scalar", 70, [2, 3, 1], flag_frac=0.15, seed=14)
+    P = make("scalar", n_ant, [2, 3, 1], flag_frac=0.15, seed=14)
     plan = wcal.plan_for(P, tol=1e-6, max_iter=100)
     clean = plan.solve(P.data, P.model, P.flags, P.unit_gains())
     d2, m2 = P.data.clone(), P.model.clone()
