@@ -76,9 +76,9 @@ typedef struct { float re, im; } wcal_c64;
 #define WCAL_SINGULAR_ANT 4u  /* some antenna's block was not invertible: its gain was kept       */
 #define WCAL_NONFINITE    8u  /* a sum over unflagged rows was not finite: the interval stopped   */
                               /* before that update and kept the previous gains                   */
-#define WCAL_ABORTED     16u  /* the device-side iteration loop gave up a bounded wait (a library */
-                              /* fault, never a numerical outcome): the interval holds the gains  */
-                              /* of its last applied update and n_iter counts those updates       */
+#define WCAL_ABORTED     16u  /* reserved for a device-side iteration loop that gives up a bounded */
+                              /* wait; that loop is switched off (plan creation refuses it), so   */
+                              /* no solve sets this bit                                            */
 
 /* algorithms */
 #define WCAL_STEFCAL   0   /* n_dir == 1; n_corr 1 or 4                     (Sect. 3.1, 4.3)   */
@@ -194,14 +194,11 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
  *   n_iter   out    [n_int] updates applied
  *   status   out    [n_int] WCAL_* status bits
  *   chi2     out    [n_int] sum of |R|^2 over unflagged rows (FP64), or NULL
- * The whole batch runs on the device with no host synchronisation.  StefCal in PASS mode
- * runs every update of every interval in ONE persistent launch: workgroups take tiles of
- * the intervals' rows from a ring in the workspace, the workgroup that finishes an
- * interval's last tile of an update applies the update and puts the interval's tiles back
- * while it keeps iterating, so each interval advances on its own (bounded waits; a wait
- * that runs out marks the intervals it cut off WCAL_ABORTED).  CohJones / AllJones in PASS
- * mode launch a Gram pass over the intervals still iterating and the update kernels per
- * update.  In STATS mode one statistics pass is followed by updates on the statistics
+ * The whole batch runs on the device with no host synchronisation.  In PASS mode each
+ * update is a pass over the rows of the intervals still iterating (StefCal: the tiles on the
+ * device-built active list; CohJones / AllJones: the Gram pass) followed by the update
+ * kernels; the launches of all max_iter updates are issued up front and an update with no
+ * interval left iterating returns at once.  In STATS mode one statistics pass is followed by updates on the statistics
  * (StefCal: one launch that iterates every interval; CohJones / AllJones: per-update
  * launches).  Every solve ends with a tiled residual pass.  No call allocates, synchronises
  * the host or records a memset node, so the call can be captured into a HIP graph. */

@@ -222,6 +222,42 @@ __device__ __forceinline__ float2 cis_quarter(double x) {
 // z = (1, 1) and takes P = the data value, and lanes past column Nd keep z = 0.  The
 // wavefronts of a task meet only at the task pop.
 constexpr int PREBASE = 16;
+// The FP32 MFMA accumulators of the Gram passes hold the sums of one block of samples; every
+// block the sums move into a second set of accumulators and the MFMA ones start again from
+// zero.  A single FP32 chain over a whole interval (1920 samples) loses the gains of faint
+// directions: their model-data sums are small against the running sums, which the bright
+// sources make large, so their rounding grows with the chain; 128-sample blocks keep it near
+// the level of the inputs' own rounding.  The predicted-model pass keeps the block totals in
+// FP64; the read-model pass, whose occupancy sets its HBM rate, keeps them in FP32 (half the
+// registers; the chain of at most 128 samples inside a block dominates the rounding either
+// way).
+constexpr int FOLD_SAMPLES = 128;
+template <int NB>
+__device__ __forceinline__ void fold_block(floatx4 (&crr)[NB], floatx4 (&cri)[NB], double (&drr)[NB][4],
+                                           double (&dri)[NB][4]) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            drr[j][r] += (double)crr[j][r];
+            dri[j][r] += (double)cri[j][r];
+        }
+        crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+template <int NB>
+__device__ __forceinline__ void fold_block(floatx4 (&crr)[NB], floatx4 (&cri)[NB], floatx4 (&trr)[NB],
+                                           floatx4 (&tri)[NB]) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        trr[j] += crr[j];
+        tri[j] += cri[j];
+        crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
 constexpr int PCH = 64;   // samples per staged chunk: one per lane
 constexpr int PBW = 2;    // baselines per wavefront
 constexpr int PGB = (DT / WAVE) * PBW;   // baselines per task
@@ -268,13 +304,16 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
         const double* uvk = a.pt.uvw + (int64_t)k * nt * nbl * 3;
-        floatx4 crr[PBW], cri[PBW];
+        floatx4 crr[PBW], cri[PBW];          // FP32 sums of the current block of samples
+        double drr[PBW][4], dri[PBW][4];     // FP64 sums of the finished blocks
         int cnt[PBW];
         float2 z[PBW], stp[PBW];
 #pragma unroll
         for (int j = 0; j < PBW; ++j) {
             crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { drr[j][r] = 0.0; dri[j][r] = 0.0; }
             cnt[j] = 0;
             z[j] = is_d ? make_float2(1.f, 1.f) : make_float2(0.f, 0.f);
             stp[j] = is_d ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
@@ -390,6 +429,7 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                 left -= seg;
                 f += 4 * seg;
             }
+            if ((c + 1) % (FOLD_SAMPLES / PCH) == 0 || c + 1 == nchunk) fold_block<PBW>(crr, cri, drr, dri);
         }
         // records of the wavefront's baselines, through its own LDS slice
         __builtin_amdgcn_wave_barrier();
@@ -403,8 +443,8 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 4 * kk + r;
-                tile[i * 16 + col] = crr[j][r];
-                tile[256 + i * 16 + col] = cri[j][r];
+                tile[i * 16 + col] = (float)drr[j][r];
+                tile[256 + i * 16 + col] = (float)dri[j][r];
             }
             __builtin_amdgcn_wave_barrier();
             if (b < nbl) {
@@ -594,6 +634,7 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
 }
 
 constexpr int GSF = 16;   // samples per chunk of dd_gram_dmaf_kernel
+constexpr int GFOLD = FOLD_SAMPLES / GSF;   // chunks per FP64 fold
 // dynamic LDS of dd_gram_dmaf_kernel: a chunk's model rows, at least the 4 x 512-float
 // epilogue tiles
 inline size_t dmaf_smem_bytes(int nd) {
@@ -646,13 +687,18 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
         const int nch = (ns + GSF - 1) / GSF;
-        floatx4 crr[4], cri[4];
+        floatx4 crr[4], cri[4];   // sums of the current block of GFOLD chunks
+        floatx4 trr[4], tri4[4];  // sums of the finished blocks
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            trr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            tri4[j] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-        for (int c = 0; c < nch; ++c) {
+        for (int cb = 0; cb < nch; cb += GFOLD) {
+        const int ce = min(nch, cb + GFOLD);
+        for (int c = cb; c < ce; ++c) {
             const int s0 = c * GSF;
             // model: pieces p = p0 + lane of the chunk, p0 uniform per wavefront; piece p lands
             // at byte p * PIECE of mbuf
@@ -699,6 +745,8 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
             }
             __syncthreads();     // every wavefront is done with this chunk before the next lands
         }
+        fold_block<4>(crr, cri, trr, tri4);
+        }
         // epilogue through each wavefront's own 2 x 256 floats of mbuf (free now)
         float* tile = reinterpret_cast<float*>(mbuf) + w * 512;
         for (int j = 0; j < 4; ++j) {
@@ -706,8 +754,8 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 4 * (lane >> 4) + r;
-                tile[i * 16 + col] = crr[j][r];
-                tile[256 + i * 16 + col] = cri[j][r];
+                tile[i * 16 + col] = trr[j][r];
+                tile[256 + i * 16 + col] = tri4[j][r];
             }
             __builtin_amdgcn_wave_barrier();
             if (b < nbl) {

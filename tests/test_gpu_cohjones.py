@@ -276,14 +276,20 @@ def test_cohjones_na64_nd10_full_size(mode):
 def test_bf16_gram_error_against_oracle(algo):
     """BF16 products with FP32 accumulation in the Gram pass, with the FP32 residual column
     and the residual-form update: the converged gains of the 64-antenna, 10-direction problem
-    (2 x 8 samples) against the FP64 oracle's, beside the FP32 path on the same problem."""
+    (2 x 8 samples) against the FP64 oracle's, beside the FP32 path on the same problem.
+
+    The oracle's solution is converged to 1e-10.  The FP32 solve stops at 1e-7: on this
+    problem the oracle itself, stopped at a relative change of 1e-6, is still 9e-6 (CohJones)
+    and 1.2e-5 (AllJones) from its fixed point, and 1.1e-6 / 1.5e-6 at 1e-7, so only the
+    tighter stop separates precision from the distance left to the fixed point.  The BF16
+    solve stops at 1e-6 (its bound, 1e-4, is far above that distance)."""
     log(f"[bf16 gram] algo={algo}")
     P = synth.workload("cohjones_na64", device=DEV, n_time=2, n_chan=8, n_int=1)
     o = glue.solve(P, 0, P.unit_gains()[0].cpu().numpy(), algo="cohjones", tol=1e-10, max_iter=3000)
     go = glue.gains_from_oracle(o["g"], 1, P.n_dir)[:, :, 0]
     errs = {}
-    for prec in ("fp32", "bf16"):
-        plan = wcal.plan_for(P, algo=algo, tol=1e-6, max_iter=500, precision=prec)
+    for prec, tol in (("fp32", 1e-7), ("bf16", 1e-6)):
+        plan = wcal.plan_for(P, algo=algo, tol=tol, max_iter=500, precision=prec)
         out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
         torch.cuda.synchronize()
         assert int(out["status"][0]) & oc.CONVERGED, (prec, int(out["status"][0]))
