@@ -223,6 +223,21 @@ int wcal_solve_graph(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mode
 int wcal_graph_launch(wcal_graph* graph, void* stream);
 void wcal_graph_destroy(wcal_graph* graph);   /* NULL is a no-op */
 
+/* wcal_solve for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same solve, arguments as in
+ * wcal_solve, with its workspace in a static device array of WCAL_STATIC_WORKSPACE_BYTES
+ * that the library holds on every GPU it runs on until the process ends.  The call
+ * allocates nothing (the array's device address is looked up once per device, on the first
+ * call there).  Every call on one GPU shares that array: calls that overlap on the device
+ * (two streams, two threads, two graphs) race; consecutive calls do not (each initialises
+ * what it reads).  Errors: as wcal_solve, and WCAL_ENOMEM before any launch when the plan's
+ * workspace (wcal_plan_workspace) exceeds the static array, WCAL_EINVAL while profiling is
+ * on (its events are created on demand). */
+#define WCAL_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int wcal_solve_static(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
+                      const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
+                      int32_t* n_iter, uint32_t* status, double* chi2, void* stream);
+
 /* One fused pass at fixed gains, no iteration: per interval and antenna the blocks of
  * the approximate J^H J that the algorithm inverts, the top half of J^H D and of J^H r,
  * the number of unflagged stored rows touching the antenna, chi^2 and optionally R.

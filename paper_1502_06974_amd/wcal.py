@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libwcal.so")
 OK, EINVAL, EINDEX, ESHAPE, EHIP, ENOMEM, EIO = 0, -1, -2, -3, -4, -5, -6
 CONVERGED, MAXITER, SINGULAR_ANT, NONFINITE, ABORTED = 1, 2, 4, 8, 16
 WS_ALIGN = 256
+STATIC_WORKSPACE_BYTES = 64 << 20   # WCAL_STATIC_WORKSPACE_BYTES
 STEFCAL, COHJONES, ALLJONES = 0, 1, 2
 AVG_FIRST, GN_FIRST, GN_ONLY = 0, 1, 2
 _ALGOS = {"stefcal": STEFCAL, "cohjones": COHJONES, "alljones": ALLJONES}
@@ -37,7 +38,7 @@ EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_des
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
            "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_mlp_save", "wcal_mlp_load",
-           "wcal_plan_smoothing", "wcal_solve_smooth", "wcal_solve_points")
+           "wcal_plan_smoothing", "wcal_solve_smooth", "wcal_solve_points", "wcal_solve_static")
 K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
@@ -90,6 +91,8 @@ def lib() -> C.CDLL:
     L.wcal_plan_pass_kernel.restype = C.c_char_p
     L.wcal_solve.argtypes = [vp] * 10 + [C.c_size_t, vp]
     L.wcal_solve.restype = C.c_int
+    L.wcal_solve_static.argtypes = [vp] * 10
+    L.wcal_solve_static.restype = C.c_int
     L.wcal_solve_graph.argtypes = [vp] * 10 + [C.c_size_t, vp, C.POINTER(C.c_void_p)]
     L.wcal_solve_graph.restype = C.c_int
     L.wcal_graph_launch.argtypes = [vp, vp]
@@ -267,6 +270,29 @@ class Plan:
         _check(lib().wcal_solve(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
                                 _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2), wp, wn,
                                 self._stream(stream)))
+        return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
+
+    def solve_static(self, data, model, flags, gains, residual=None, n_iter=None, status=None,
+                     chi2=None, stream=None, want_residual: bool = True, want_chi2: bool = True):
+        """wcal_solve_static: wcal_solve with the library's static device workspace (the call
+        itself allocates nothing; outputs not passed in are allocated here, before it)."""
+        self._inputs(data, model, flags, gains)
+        dev = gains.device
+        if residual is None and want_residual:
+            residual = torch.empty_like(data)
+        if n_iter is None:
+            n_iter = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if status is None:
+            status = torch.empty(self.n_int, dtype=torch.int32, device=dev)
+        if chi2 is None and want_chi2:
+            chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
+        self._dev(residual, "residual", torch.complex64, (self.rows, self.n_corr))
+        self._dev(n_iter, "n_iter", torch.int32, (self.n_int,))
+        self._dev(status, "status", torch.int32, (self.n_int,))
+        self._dev(chi2, "chi2", torch.float64, (self.n_int,))
+        _check(lib().wcal_solve_static(self._h, _ptr(data), _ptr(model), _ptr(flags), _ptr(gains),
+                                       _ptr(residual), _ptr(n_iter), _ptr(status), _ptr(chi2),
+                                       self._stream(stream)))
         return dict(gains=gains, residual=residual, n_iter=n_iter, status=status, chi2=chi2)
 
     def autotune(self, data, model, flags, gains, n_updates: int = 0, stream=None) -> dict:

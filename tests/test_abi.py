@@ -80,6 +80,7 @@ def test_null_arguments():
     h = C.c_void_p()
     assert L.wcal_plan_create(None, None, None, None, 0, C.byref(h)) == wcal.EINVAL
     assert L.wcal_solve(*([None] * 10), 0, None) == wcal.EINVAL
+    assert L.wcal_solve_static(*([None] * 10)) == wcal.EINVAL
     assert L.wcal_accumulate(*([None] * 12), 0, None) == wcal.EINVAL
     assert L.wcal_residual(*([None] * 8), 0, None) == wcal.EINVAL
     assert L.wcal_plan_rows(None) == -1
