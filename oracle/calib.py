@@ -543,8 +543,7 @@ def stefcal_smooth(d, m, p, q, cell, flags, g0, n_time, n_chan, sigma_t, sigma_f
                 status |= SINGULAR_ANT
             ghat = np.where(sing, g, sa / np.where(sing, 1.0, sb))
             g_new = 0.5 * (g + ghat) if _is_average_step(k, schedule) else ghat
-            aligned = np.stack([align_phase(g_new[c], g[c]) for c in range(n_cells)])
-            rel = rel_change(aligned, g)
+            rel = cell_rel_change(g_new, g)
             hist.append(rel)
             g = g_new
             n_iter = k + 1
@@ -557,6 +556,16 @@ def stefcal_smooth(d, m, p, q, cell, flags, g0, n_time, n_chan, sigma_t, sigma_f
     r[kr] = d[kr] - g[cell[kr], p[kr]] * m[kr] * np.conj(g[cell[kr], q[kr]])
     return dict(g=g, n_iter=n_iter, status=status, residual=r, chi2=float(np.sum(np.abs(r[kr]) ** 2)),
                 history=hist)
+
+
+def cell_rel_change(g_new, g_old):
+    """Convergence measure of the smoothed iteration (a reading; Sect. 3.4 does not test
+    convergence): ||g_new' - g_old||_F / ||g_new||_F over every cell and antenna, where g_new'
+    is g_new with each cell turned by its own least-squares phase onto g_old.  Each cell's
+    weighted problem (Eq. cal:DI:smooth) involves only that cell's gains, so it is defined up
+    to one phase per cell.  g [n_cells, Na]."""
+    aligned = np.stack([align_phase(g_new[c], g_old[c]) for c in range(g_new.shape[0])])
+    return rel_change(aligned, g_old)
 
 
 # ------------------------------------------------------------------ gauge

@@ -701,6 +701,61 @@ def test_smooth_iterates_rotate_rigidly_along_the_gauge():
     assert raw > 1e-5 and aligned < 1e-3 * raw, (raw, aligned)
 
 
+def test_smooth_objective_has_one_phase_per_cell():
+    """Eq. cal:DI:smooth written out: the weighted objective of cell (t0, f0) sums
+    w(t - t0, f - f0) |d - g_p(t0, f0) m conj(g_q(t0, f0))|^2 over every row, so it involves
+    that cell's gains only.  Turning each cell's gains by its own phase leaves every cell's
+    objective unchanged; turning antennas by their own phases does not."""
+    na, nt, nf, st, sf = 5, 2, 4, 0.9, 1.4
+    d, m, p, q, cell, _ = _cells(na, nt, nf, sigma=0.2)
+    g = cn(nt * nf, na) + 1.0
+
+    def w(dt, df):
+        return np.exp(-dt * dt / (2 * st * st)) * np.exp(-df * df / (2 * sf * sf))
+
+    def objective(gg):
+        out = np.zeros(nt * nf)
+        for c0 in range(nt * nf):
+            t0, f0 = divmod(c0, nf)
+            for r in range(d.size):
+                t, f = divmod(int(cell[r]), nf)
+                out[c0] += w(t - t0, f - f0) * abs(d[r] - gg[c0, p[r]] * m[r] * np.conj(gg[c0, q[r]])) ** 2
+        return out
+    base = objective(g)
+    phi = rng.uniform(-np.pi, np.pi, nt * nf)
+    assert np.allclose(objective(g * np.exp(1j * phi)[:, None]), base, rtol=1e-12)
+    psi = rng.uniform(-np.pi, np.pi, na)
+    assert not np.allclose(objective(g * np.exp(1j * psi)[None, :]), base, rtol=1e-3)
+
+
+def test_smooth_stop_rule_removes_one_phase_per_cell():
+    """The smoothed iteration's stopping measure, by hand: two cells of two antennas,
+    g_old = [[1, 1], [i, i]], g_new = [[1, 2], [i, i]]: no phase helps cell 0 ((1, 2) against
+    (1, 1): sum conj(g_new) g_old = 3 > 0), cell 1 is unchanged, so the change is (0, 1, 0, 0)
+    over ||g_new|| = sqrt(7).  Turning cell 1 of g_new by a quarter turn changes nothing; the
+    same turn read by the plain relative change does.  Random phases per cell give 0, and
+    the solver's history is this measure of its own successive iterates."""
+    g_old = np.array([[1, 1], [1j, 1j]], dtype=complex)
+    g_new = np.array([[1, 2], [1j, 1j]], dtype=complex)
+    assert oc.cell_rel_change(g_new, g_old) == pytest.approx(1 / np.sqrt(7), rel=1e-15)
+    turned = g_new.copy()
+    turned[1] *= 1j
+    assert oc.cell_rel_change(turned, g_old) == pytest.approx(1 / np.sqrt(7), rel=1e-15)
+    assert oc.rel_change(turned, g_old) > 0.5
+    g = cn(6, 4) + 1.0
+    phi = rng.uniform(-np.pi, np.pi, 6)
+    assert oc.cell_rel_change(g * np.exp(1j * phi)[:, None], g) < 1e-15
+    na, nt, nf = 6, 1, 8
+    d, m, p, q, cell, _ = _cells(na, nt, nf, sigma=0.3)
+    g0 = np.ones((nf, na), complex)
+    its = [g0]
+    for k in range(1, 4):
+        its.append(oc.stefcal_smooth(d, m, p, q, cell, None, g0, nt, nf, 0.0, 2.0, tol=0, max_iter=k)["g"])
+    hist = oc.stefcal_smooth(d, m, p, q, cell, None, g0, nt, nf, 0.0, 2.0, tol=0, max_iter=3)["history"]
+    for k in range(3):
+        assert hist[k] == pytest.approx(oc.cell_rel_change(its[k + 1], its[k]), rel=1e-12)
+
+
 def test_smooth_lowers_the_error_of_noisy_solutions():
     """Low SNR, gains constant across channels: smoothing over channels gives solutions
     closer to the truth than solving every channel alone (the motivation of Sect. 3.4)."""
