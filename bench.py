@@ -525,7 +525,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": tfs / peak,
-            "traffic": None,
+            "traffic": measured_traffic(f"{kname}/{args.workload}"),
             "kernel": kname,
             "kernel_ms_per_launch": kms / max(klaunch, 1),
             "launches_per_step": klaunch / args.steps,

@@ -284,9 +284,16 @@ typedef struct {
 } wcal_points;
 
 /* wcal_solve with the model given by `pts` (data, flags, gains, residual, n_iter, status, chi2
- * as in wcal_solve; PASS or STATS mode).  Errors: WCAL_EINVAL (plan not scalar CohJones /
- * AllJones with the FP32 Gram, NULL or misaligned arrays, n_time or n_chan < 1), WCAL_ESHAPE
- * (an interval that does not hold n_time * n_chan samples). */
+ * as in wcal_solve; PASS or STATS mode).  The solve forms a phasor table once (per interval,
+ * time slot, baseline and direction: the phasors where the passes start or re-base their
+ * channel walk, and the step over four channels) and every pass reads it, so its workspace is
+ * the plan's plus the table: wcal_points_workspace gives the size for this grid
+ * (n_int * n_time * n_bl * n_dir * (4 * ceil(n_chan / 64) + 1) * 8 bytes, 387 MB for 16
+ * intervals of 30 x 64 samples, 2016 baselines and 10 directions).  Errors: WCAL_EINVAL (plan
+ * not scalar CohJones / AllJones with the FP32 Gram, NULL or misaligned arrays, n_time or
+ * n_chan < 1), WCAL_ESHAPE (an interval that does not hold n_time * n_chan samples),
+ * WCAL_ENOMEM (workspace smaller than wcal_points_workspace). */
+int wcal_points_workspace(const wcal_plan* plan, const wcal_points* pts, size_t* bytes);
 int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* data, const uint8_t* flags,
                       wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
                       void* workspace, size_t ws_bytes, void* stream);

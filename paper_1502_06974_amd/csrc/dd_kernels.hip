@@ -212,9 +212,12 @@ __device__ __forceinline__ float2 cis_quarter(double x) {
 // the MFMA operand layout.  Wavefront w of a task owns PBW consecutive baselines and walks
 // their samples four at a time, lane l holding column l % 16 of sample 4g + l / 16 (as in the
 // read-model passes).  A lane of model column d keeps one phasor per baseline for its own sample and
-// steps it by exp(-2 pi i phi 4 dfreq) from one group to the next; the phasor is re-based from
-// the FP64 phase whenever the lane's sample enters a new time slot and after PREBASE steps, so
-// the walk runs in segments between re-bases with a branch-free inner loop.  Data and flags
+// steps it by exp(-2 pi i phi 4 dfreq) from one group to the next; the phasor is re-based
+// whenever the lane's sample enters a new time slot and after PREBASE steps, so the walk runs in
+// segments between re-bases with a branch-free inner loop.  A re-base reads the phasor and the
+// step from the solve's phasor table (dd_phasor_kernel, formed once per solve from the FP64
+// phase): a lane enters a slot at a channel below 4 and re-bases every 64 channels, so the
+// table holds channels 64 j + r, r < 4, of every (interval, slot, baseline, direction).  Data and flags
 // pass through the wavefront's own LDS slice, PCH samples at a time (each lane loads one
 // sample of the wavefront's baselines, a chunk ahead): the slice holds the data value, zeroed
 // where the row is flagged or absent, and a weight 1 or 0.  Every lane then forms its operand
@@ -222,30 +225,47 @@ __device__ __forceinline__ float2 cis_quarter(double x) {
 // z = (1, 1) and takes P = the data value, and lanes past column Nd keep z = 0.  The
 // wavefronts of a task meet only at the task pop.
 constexpr int PREBASE = 16;
-// The FP32 MFMA accumulators of the Gram passes hold the sums of one block of samples; every
-// block the sums move into a second set of accumulators and the MFMA ones start again from
-// zero.  A single FP32 chain over a whole interval (1920 samples) loses the gains of faint
-// directions: their model-data sums are small against the running sums, which the bright
-// sources make large, so their rounding grows with the chain; 128-sample blocks keep it near
-// the level of the inputs' own rounding.  The predicted-model pass keeps the block totals in
-// FP64; the read-model pass, whose occupancy sets its HBM rate, keeps them in FP32 (half the
-// registers; the chain of at most 128 samples inside a block dominates the rounding either
-// way).
-constexpr int FOLD_SAMPLES = 128;
-template <int NB>
-__device__ __forceinline__ void fold_block(floatx4 (&crr)[NB], floatx4 (&cri)[NB], double (&drr)[NB][4],
-                                           double (&dri)[NB][4]) {
+static_assert(PREBASE * 4 == 64, "the phasor table holds one segment per 64 channels");
+
+// The phasor table of a predicted-model solve: one thread per (interval, time slot, baseline,
+// direction) forms the FP64 phase phi = -2 pi (u . sigma_d) / c once and writes the step
+// exp(i phi 4 dfreq) and, for every 64-channel segment j, S_d exp(i phi nu) at channels 64 j + r,
+// r < 4 (zero past the last channel), each exp(i x) by cis_quarter.
+__global__ void __launch_bounds__(DT) dd_phasor_kernel(DdArgs a) {
+    const int nd = a.n_dir, nch = a.pt.n_chan, nseg = a.pt.nseg;
+    const int64_t n = (int64_t)a.n_int * a.pt.n_time * a.n_bl * nd;
+    const double sc = -6.283185307179586 / 299792458.0;
+    for (int64_t i = (int64_t)blockIdx.x * DT + threadIdx.x; i < n; i += (int64_t)gridDim.x * DT) {
+        const int d = (int)(i % nd);
+        const int64_t tb = i / nd;   // (k * n_time + t) * n_bl + b
+        const double* u = a.pt.uvw + tb * 3;
+        const double sg0 = sc * a.pt.lmn[3 * d], sg1 = sc * a.pt.lmn[3 * d + 1], sg2 = sc * a.pt.lmn[3 * d + 2];
+        const double ph = u[0] * sg0 + u[1] * sg1 + u[2] * sg2;
+        const float flux = a.pt.flux[d];
+        a.pt.st[i] = cis_quarter(ph * (4.0 * a.pt.dfreq));
+        float2* zo = a.pt.zt + tb * nseg * 4 * nd + d;
+        for (int j = 0; j < nseg; ++j) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            drr[j][r] += (double)crr[j][r];
-            dri[j][r] += (double)cri[j][r];
+            for (int r = 0; r < 4; ++r) {
+                const int f = 64 * j + r;
+                float2 z = make_float2(0.f, 0.f);
+                if (f < nch) {
+                    const float2 e = cis_quarter(ph * (a.pt.freq0 + f * a.pt.dfreq));
+                    z = make_float2(flux * e.x, flux * e.y);
+                }
+                zo[(4 * j + r) * nd] = z;
+            }
         }
-        crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-        cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
 }
+// The FP32 MFMA accumulators of the Gram passes hold the sums of one block of samples; every
+// block the sums move into a second set of FP32 accumulators and the MFMA ones start again
+// from zero.  A single FP32 chain over a whole interval (1920 samples) loses the gains of faint
+// directions: their model-data sums are small against the running sums, which the bright
+// sources make large, so their rounding grows with the chain; 128-sample blocks keep it near
+// the level of the inputs' own rounding (the chain of at most 128 samples inside a block
+// dominates the rounding; FP64 block totals would double the registers for ~30% less error).
+constexpr int FOLD_SAMPLES = 128;
 template <int NB>
 __device__ __forceinline__ void fold_block(floatx4 (&crr)[NB], floatx4 (&cri)[NB], floatx4 (&trr)[NB],
                                            floatx4 (&tri)[NB]) {
@@ -259,9 +279,9 @@ __device__ __forceinline__ void fold_block(floatx4 (&crr)[NB], floatx4 (&cri)[NB
 }
 
 constexpr int PCH = 64;   // samples per staged chunk: one per lane
-constexpr int PBW = 2;    // baselines per wavefront
+constexpr int PBW = 4;    // baselines per wavefront
 constexpr int PGB = (DT / WAVE) * PBW;   // baselines per task
-__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8))) dd_gram_pts_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8))) dd_gram_pts_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
     // per wavefront: [0] [sample][baseline] data, [1] [sample][baseline] (weight, weight),
     // each followed by two groups of padding that the read-ahead after a chunk's last two
     // groups lands in (its values are never used); the slice also holds the 512-float record tile
@@ -278,18 +298,7 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
     const bool has_flags = a.flags != nullptr;
     const bool is_m = col < nd, is_d = col == nd;
-    const int nch = a.pt.n_chan, nt = a.pt.n_time;
-    const double f0 = a.pt.freq0, df4 = 4.0 * a.pt.dfreq, df = a.pt.dfreq;
-    // this lane's direction: -2 pi sigma / c with sigma = (l, m, n - 1), and its flux
-    double sg0 = 0.0, sg1 = 0.0, sg2 = 0.0;
-    float flux = 0.f;
-    if (is_m) {
-        const double sc = -6.283185307179586 / 299792458.0;
-        sg0 = sc * a.pt.lmn[3 * col];
-        sg1 = sc * a.pt.lmn[3 * col + 1];
-        sg2 = sc * a.pt.lmn[3 * col + 2];
-        flux = a.pt.flux[col];
-    }
+    const int nch = a.pt.n_chan, nt = a.pt.n_time, nseg = a.pt.nseg;
     const float2* src = sbuf[w][is_d ? 0 : 1];   // this lane's operand factors
     for (;;) {
         __syncthreads();
@@ -303,17 +312,16 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
         if (nv <= 0) continue;
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
-        const double* uvk = a.pt.uvw + (int64_t)k * nt * nbl * 3;
         floatx4 crr[PBW], cri[PBW];          // FP32 sums of the current block of samples
-        double drr[PBW][4], dri[PBW][4];     // FP64 sums of the finished blocks
+        floatx4 trr[PBW], tri4[PBW];         // sums of the finished blocks
         int cnt[PBW];
         float2 z[PBW], stp[PBW];
 #pragma unroll
         for (int j = 0; j < PBW; ++j) {
             crr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cri[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) { drr[j][r] = 0.0; dri[j][r] = 0.0; }
+            trr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+            tri4[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cnt[j] = 0;
             z[j] = is_d ? make_float2(1.f, 1.f) : make_float2(0.f, 0.f);
             stp[j] = is_d ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
@@ -368,18 +376,21 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                         ++t;
                     }
                     if (is_m && 4 * (c * (PCH / 4) + gg) + kk < ns) {
-                        const double nu = f0 + f * df;
+                        // phasors of the solve's table: segment f / 64, channel f % 64 < 4
+                        const int64_t tb = ((int64_t)k * nt + t) * nbl + bw;
+                        const float2* zr = a.pt.zt + ((tb * nseg + (f >> 6)) * 4 + (f & 63)) * nd + col;
+                        const float2* sr = a.pt.st + tb * nd + col;
 #pragma unroll
                         for (int j = 0; j < PBW; ++j) {
                             if (j < nv) {
-                                const double* u = uvk + ((int64_t)t * nbl + bw + j) * 3;
-                                const double ph = u[0] * sg0 + u[1] * sg1 + u[2] * sg2;
-                                stp[j] = cis_quarter(ph * df4);
-                                const float2 e = cis_quarter(ph * nu);
-                                z[j] = make_float2(flux * e.x, flux * e.y);
+                                z[j] = zr[(int64_t)j * nseg * 4 * nd];
+                                stp[j] = sr[j * nd];
                             }
                         }
                     }
+                    // the phasors have arrived before the chunk read-ahead below is issued:
+                    // a wait for them inside the walk would also wait for the read-ahead
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
                     left = min(PREBASE, (nch - f + 3) / 4);
                 }
                 // groups until the first of the wavefront's four sample rows needs a re-base
@@ -429,7 +440,7 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                 left -= seg;
                 f += 4 * seg;
             }
-            if ((c + 1) % (FOLD_SAMPLES / PCH) == 0 || c + 1 == nchunk) fold_block<PBW>(crr, cri, drr, dri);
+            if ((c + 1) % (FOLD_SAMPLES / PCH) == 0 || c + 1 == nchunk) fold_block<PBW>(crr, cri, trr, tri4);
         }
         // records of the wavefront's baselines, through its own LDS slice
         __builtin_amdgcn_wave_barrier();
@@ -443,8 +454,8 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 4 * kk + r;
-                tile[i * 16 + col] = (float)drr[j][r];
-                tile[256 + i * 16 + col] = (float)dri[j][r];
+                tile[i * 16 + col] = trr[j][r];
+                tile[256 + i * 16 + col] = tri4[j][r];
             }
             __builtin_amdgcn_wave_barrier();
             if (b < nbl) {
@@ -1115,7 +1126,7 @@ __global__ void __launch_bounds__(DT) dd_reduce_kernel(DdArgs a, DdState st) {
 // Residual rows of one tile: lane <-> baseline, weights g^c_p conj(g^c_q) per round.
 // PRED: the point-source model of a.pt, its phasors taken from an FP64 phase at every new time
 // slot and every 16 channels, and stepped from channel to channel in between.
-template <bool PRED>
+template <bool PRED, bool V4>
 __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int ctr_slot) {
     __shared__ double red[DT / WAVE];
     __shared__ int s_t;
@@ -1170,11 +1181,22 @@ __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int 
                             if (c < nd) r = csub(r, cmul(w[c], z[c]));
                     } else {
                         // every model value of the row is requested before the first is used
-                        // (indices past the last direction repeat it and are not summed)
+                        // (indices past the last direction repeat it and are not summed); with
+                        // V4 (Nd even, model 16-byte aligned) two values per 16-byte load
                         const float2* m = a.model + row * nd;
                         float2 mv[NDMAX];
+                        if constexpr (V4) {
+                            const float4* m4 = reinterpret_cast<const float4*>(m);
 #pragma unroll
-                        for (int c = 0; c < NDMAX; ++c) mv[c] = m[min(c, nd - 1)];
+                            for (int c = 0; c < NDMAX / 2; ++c) {
+                                const float4 v = m4[min(c, nd / 2 - 1)];
+                                mv[2 * c] = make_float2(v.x, v.y);
+                                mv[2 * c + 1] = make_float2(v.z, v.w);
+                            }
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < NDMAX; ++c) mv[c] = m[min(c, nd - 1)];
+                        }
 #pragma unroll
                         for (int c = 0; c < NDMAX; ++c)
                             if (c < nd) r = csub(r, cmul(w[c], mv[c]));
@@ -1194,6 +1216,12 @@ __global__ void __launch_bounds__(DT) dd_resid_kernel(DdArgs a, DdState st, int 
 
 size_t dd_stats_bytes(const wcal_problem& p) { return dd_state_bytes(p, rec_floats(p.n_dir)); }
 
+size_t points_table_bytes(const wcal_problem& p, int32_t n_time, int32_t n_chan) {
+    const size_t n = (size_t)p.n_int * n_time * p.n_bl * p.n_dir;
+    const size_t nseg = ((size_t)n_chan + 63) / 64;
+    return ws_round(n * nseg * 4 * sizeof(float2)) + ws_round(n * sizeof(float2));
+}
+
 size_t dd_smem_bytes(int nd, int na) { return dd_smem_size(nd, na); }
 
 int dd_max_dir() { return NDMAX; }
@@ -1201,12 +1229,12 @@ int dd_max_dir() { return NDMAX; }
 static void launch_residual_tiles(const wcal_plan* plan, const DdArgs& a, const DdState& st, hipStream_t s,
                                   int slot) {
     const bool pred = a.pt.uvw != nullptr;
-    const void* fn = pred ? reinterpret_cast<const void*>(dd_resid_kernel<true>)
-                          : reinterpret_cast<const void*>(dd_resid_kernel<false>);
-    const int g = dd_grid(plan, fn, 0, st.ntiles);
+    const bool v4 = !pred && a.n_dir % 2 == 0 && reinterpret_cast<uintptr_t>(a.model) % 16 == 0;
+    typedef void (*ResidFn)(DdArgs, DdState, int);
+    const ResidFn fn = pred ? dd_resid_kernel<true, false> : v4 ? dd_resid_kernel<false, true> : dd_resid_kernel<false, false>;
+    const int g = dd_grid(plan, reinterpret_cast<const void*>(fn), 0, st.ntiles);
     prof_begin(plan, WCAL_K_RESID, s);
-    if (pred) hipLaunchKernelGGL(dd_resid_kernel<true>, dim3(g), dim3(DT), 0, s, a, st, slot);
-    else hipLaunchKernelGGL(dd_resid_kernel<false>, dim3(g), dim3(DT), 0, s, a, st, slot);
+    hipLaunchKernelGGL(fn, dim3(g), dim3(DT), 0, s, a, st, slot);
     prof_end(plan, WCAL_K_RESID, s);
     hipLaunchKernelGGL(dd_chi2_kernel, dim3((a.n_int + DT - 1) / DT), dim3(DT), 0, s, a, st);
 }
@@ -1228,6 +1256,10 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const size_t asm_ = ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
     prof_begin(plan, WCAL_K_OTHER, s);
     hipLaunchKernelGGL(dd_init_kernel, dim3((std::max(a.n_int, nctr) + DT - 1) / DT), dim3(DT), 0, s, a, st, 1, nctr);
+    if (pred) {
+        const int64_t n = (int64_t)a.n_int * a.pt.n_time * a.n_bl * nd;
+        hipLaunchKernelGGL(dd_phasor_kernel, dim3((unsigned)std::min<int64_t>((n + DT - 1) / DT, 8192)), dim3(DT), 0, s, a);
+    }
     prof_end(plan, WCAL_K_OTHER, s);
     const bool stats = plan->prob.mode == WCAL_MODE_STATS;
     if (stats) {

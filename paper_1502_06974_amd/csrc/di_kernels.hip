@@ -750,7 +750,7 @@ __device__ __forceinline__ void tri_unit(const DiArgs& a, const Tile& T, const T
     }
 }
 
-// Paired rows (n_ant >= TRI_PAIR_MIN): packed row r holds triangle row b = n_ant - 2 - r
+// Paired rows (plans that pack rows; n_ant >= TRI_PAIR_MIN): packed row r holds triangle row b = n_ant - 2 - r
 // followed by row r, n_ant entries in all (row r alone when b == r), so every chunk but the
 // last of the middle row is full.  A lane's entry is in row b or row r; each row's sum builds
 // up in its own lane share (ra0..2, rb0..2), both reduced when the packed row ends; lane
@@ -883,7 +883,7 @@ __global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit
         for (int i = threadIdx.x; i <= na; i += blockDim.x) G[i] = i < na ? gk[i] : make_float2(0.f, 0.f);
         for (int i = threadIdx.x; i < nw * ns; i += blockDim.x) acc[i] = 0.f;
         __syncthreads();
-        if (na >= TRI_PAIR_MIN)
+        if (a.tri_paired)
             for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit_paired(a, T, units[u], G, myacc);
         else
             for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
@@ -1222,7 +1222,7 @@ di_loop_kernel(DiArgs a, LoopRing q, const TriUnit* __restrict__ units) {
         for (int i = threadIdx.x; i < nw * sl; i += blockDim.x) acc[i] = 0.f;
         __syncthreads();
         if constexpr (TRI) {
-            if (na >= TRI_PAIR_MIN)
+            if (a.tri_paired)
                 for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit_paired(a, T, units[u], G, myacc);
             else
                 for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);

@@ -343,6 +343,12 @@ int wcal_plan_smoothing(wcal_plan* plan, int32_t n_time, int32_t n_chan, double 
     // the cell plan's passes are launched one update at a time (the smoothed update needs the
     // sums of neighbouring cells): no device-side loop
     sp->cells->loop = false;
+    // its triangle tiles feed only the unfused pass: packed rows
+    sp->cells->tri_unfused = true;
+    if (sp->cells->tri && (rc = plan_retile(sp->cells)) != WCAL_OK) {
+        smooth_free(sp);
+        return rc;
+    }
     ws_layout(sp->cells);
     const int na = p.n_ant;
     sp->cpb = na <= SB ? SB / na : 1;

@@ -126,6 +126,7 @@ const char* wcal_version(void) { return "wcal 0.1 (gfx950)"; }
 struct TilePlan {
     int64_t tile_rows = 0;
     bool tri = false;
+    bool paired = false;
     std::vector<Tile> tiles, stiles, ttiles;
     std::vector<int32_t> tile_off, ttile_off;
     std::vector<TriUnit> units;
@@ -166,14 +167,15 @@ static int plan_tiles(const wcal_plan* plan, int64_t tile_rows, bool want_tri, T
     std::vector<Tile>& ttiles = tp.ttiles;
     std::vector<int32_t>& ttile_off = tp.ttile_off;
     ttile_off.assign(p.n_int + 1, 0);
-    if (tp.tri) {
-        // units: blocks of whole rows (at most 64) of about 8 chunks of 64 baselines (the
-        // cost of a row is its chunk count), then ordered largest first and dealt in snake
-        // order, so the round-robin share of each of the four wavefronts of a workgroup is
-        // even
+    // units: blocks of whole rows (at most 64) of about 8 chunks of 64 baselines (the cost of
+    // a row is its chunk count), then ordered largest first and dealt in snake order, so the
+    // round-robin share of each of the four wavefronts of a workgroup is even; rows, or packed
+    // rows (row n_ant - 2 - r with row r)
+    auto build_units = [&](bool paired) {
+        units.clear();
+        ttiles.clear();
+        ttile_off.assign(p.n_int + 1, 0);
         const int32_t target = 8;
-        // rows, or packed rows (row n_ant - 2 - r with row r) from TRI_PAIR_MIN antennas on
-        const bool paired = p.n_ant >= TRI_PAIR_MIN;
         const int32_t nrows = paired ? p.n_ant / 2 : p.n_ant - 1;
         std::vector<TriUnit> raw;
         for (int32_t r0 = 0; r0 < nrows;) {
@@ -215,8 +217,20 @@ static int plan_tiles(const wcal_plan* plan, int64_t tile_rows, bool want_tri, T
                 }
             }
             ttile_off[k + 1] = (int32_t)ttiles.size();
-            if (ttiles.size() > (size_t)INT32_MAX / 4) return fail(WCAL_ESHAPE, "too many tiles");
+            if (ttiles.size() > (size_t)INT32_MAX / 4) return false;
         }
+        return true;
+    };
+    if (tp.tri) {
+        // Packed rows fill the chunks of short rows (from TRI_PAIR_MIN antennas on), which pays
+        // in the unfused pass (9% on the smoothing cell plan) but not in the fused pass, whose
+        // per-lane row selection costs more than the fuller chunks save (1% slower on
+        // bandpass_na256): pairs are used unless every interval is one tile (the fused pass),
+        // or always for plans whose triangle tiles only feed the unfused pass.
+        if (!build_units(false)) return fail(WCAL_ESHAPE, "too many tiles");
+        const bool fused = (int32_t)ttiles.size() == p.n_int;
+        tp.paired = p.n_ant >= TRI_PAIR_MIN && (plan->tri_unfused || !fused);
+        if (tp.paired && !build_units(true)) return fail(WCAL_ESHAPE, "too many tiles");
     }
     // statistics tiles in decreasing-size order (longest first)
     std::stable_sort(stiles.begin(), stiles.end(), [](const Tile& x, const Tile& y) {
@@ -289,6 +303,7 @@ static int upload_tiles(wcal_plan* plan, const TilePlan& tp) {
     }
     plan->tile_rows = (int)tp.tile_rows;
     plan->tri = tp.tri;
+    plan->tri_paired = tp.tri && tp.paired;
     plan->ntiles = (int32_t)tp.tiles.size();
     plan->nstiles = (int32_t)tp.stiles.size();
     plan->nunits = tp.tri ? (int32_t)tp.units.size() : 0;
@@ -311,6 +326,9 @@ static int build_tiles(wcal_plan* plan, int64_t tile_rows, bool want_tri) {
     if (int rc = plan_tiles(plan, tile_rows, want_tri, tp)) return rc;
     return upload_tiles(plan, tp);
 }
+
+// Rebuild the plan's tiles with its current tiling (after a change of tri_unfused).
+extern "C++" int plan_retile(wcal_plan* plan) { return build_tiles(plan, plan->tile_rows, plan->tri); }
 
 int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int32_t* ant2_h,
                      const int64_t* ns_h, int device, wcal_plan** out) {
@@ -504,6 +522,7 @@ static void fill_tables_di(const wcal_plan* plan, DiArgs& a) {
     a.n_int = plan->prob.n_int;
     a.max_iter = plan->prob.max_iter;
     a.schedule = plan->prob.schedule;
+    a.tri_paired = plan->tri_paired ? 1 : 0;
     a.tol = plan->prob.tol;
 }
 
@@ -576,29 +595,55 @@ int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model, con
     return e == hipSuccess ? WCAL_OK : hip_fail(e, "wcal_solve launch");
 }
 
+// The checks of a points plan and grid shared by wcal_points_workspace and wcal_solve_points.
+static int points_check(const wcal_plan* plan, const wcal_points* pts) {
+    const wcal_problem& p = plan->prob;
+    if ((p.algo != WCAL_COHJONES && p.algo != WCAL_ALLJONES) || p.n_corr != 1 || p.precision != WCAL_PREC_FP32)
+        return fail(WCAL_EINVAL, "predicted point-source models need scalar CohJones / AllJones with the FP32 Gram");
+    if (pts->n_time < 1 || pts->n_chan < 1 || !std::isfinite(pts->freq0) || !std::isfinite(pts->dfreq))
+        return fail(WCAL_EINVAL, "n_time, n_chan >= 1 and finite frequencies required");
+    for (int32_t k = 0; k < p.n_int; ++k)
+        if (plan->h_ns[k] != (int64_t)pts->n_time * pts->n_chan)
+            return fail(WCAL_ESHAPE, "every interval must hold n_time * n_chan samples");
+    return WCAL_OK;
+}
+
+int wcal_points_workspace(const wcal_plan* plan, const wcal_points* pts, size_t* bytes) {
+    g_err.clear();
+    if (!plan || !pts || !bytes) return fail(WCAL_EINVAL, "NULL argument");
+    if (int rc = points_check(plan, pts)) return rc;
+    *bytes = ws_round(plan->ws_bytes) + points_table_bytes(plan->prob, pts->n_time, pts->n_chan);
+    return WCAL_OK;
+}
+
 int wcal_solve_points(wcal_plan* plan, const wcal_points* pts, const wcal_c64* data, const uint8_t* flags,
                       wcal_c64* gains, wcal_c64* residual, int32_t* n_iter, uint32_t* status, double* chi2,
                       void* workspace, size_t ws_bytes, void* stream) {
     g_err.clear();
     if (!plan || !pts || !data || !gains || !n_iter || !status) return fail(WCAL_EINVAL, "NULL argument");
     const wcal_problem& p = plan->prob;
-    if ((p.algo != WCAL_COHJONES && p.algo != WCAL_ALLJONES) || p.n_corr != 1 || p.precision != WCAL_PREC_FP32)
-        return fail(WCAL_EINVAL, "predicted point-source models need scalar CohJones / AllJones with the FP32 Gram");
+    if (int rc = points_check(plan, pts)) return rc;
     if (!pts->uvw || !pts->lmn || !pts->flux) return fail(WCAL_EINVAL, "uvw, lmn and flux are required");
-    if (pts->n_time < 1 || pts->n_chan < 1 || !std::isfinite(pts->freq0) || !std::isfinite(pts->dfreq))
-        return fail(WCAL_EINVAL, "n_time, n_chan >= 1 and finite frequencies required");
-    for (int32_t k = 0; k < p.n_int; ++k)
-        if (plan->h_ns[k] != (int64_t)pts->n_time * pts->n_chan)
-            return fail(WCAL_ESHAPE, "every interval must hold n_time * n_chan samples");
     if (!aligned(data, 8) || !aligned(gains, 8) || (residual && !aligned(residual, 8)) || !aligned(pts->uvw, 8) ||
         !aligned(pts->lmn, 8) || !aligned(pts->flux, 4))
         return fail(WCAL_EINVAL, "misaligned argument");
     if (hipSetDevice(plan->device) != hipSuccess) return fail(WCAL_EHIP, "hipSetDevice failed");
+    // the plan's regions, then the phasor table
+    const size_t base = ws_round(plan->ws_bytes);
+    const size_t tab = points_table_bytes(p, pts->n_time, pts->n_chan);
+    if (workspace && ws_bytes < base + tab)
+        return fail(WCAL_ENOMEM, "workspace of " + std::to_string(ws_bytes) + " bytes, the points solve needs " +
+                                     std::to_string(base + tab) + " (wcal_points_workspace)");
     if (int rc = ws_check_bind(plan, workspace, ws_bytes)) return rc;
     DdArgs a{};
     fill_tables_dd(plan, a);
     a.data = reinterpret_cast<const float2*>(data);
     a.model = nullptr;
+    a.pt.nseg = (pts->n_chan + 63) / 64;
+    a.pt.zt = reinterpret_cast<float2*>(static_cast<char*>(workspace) + base);
+    a.pt.st = reinterpret_cast<float2*>(static_cast<char*>(workspace) + base +
+                                        ws_round((size_t)p.n_int * pts->n_time * p.n_bl * p.n_dir * a.pt.nseg * 4 *
+                                                 sizeof(float2)));
     a.pt.uvw = pts->uvw;
     a.pt.lmn = pts->lmn;
     a.pt.flux = pts->flux;

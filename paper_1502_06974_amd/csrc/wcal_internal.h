@@ -20,8 +20,9 @@ void prof_begin(const wcal_plan* plan, int cls, hipStream_t s);
 void prof_end(const wcal_plan* plan, int cls, hipStream_t s);
 
 // A unit of the triangle pass (baselines in the canonical order: all pairs p < q,
-// p-major, q increasing): the whole rows p in [p0, p1) of the triangle, at most 64; from
-// TRI_PAIR_MIN antennas on, packed rows r in [p0, p1), each row n_ant - 2 - r and row r.
+// p-major, q increasing): the whole rows p in [p0, p1) of the triangle, at most 64; or, when
+// the plan packs rows (possible from TRI_PAIR_MIN antennas on), packed rows r in [p0, p1),
+// each row n_ant - 2 - r and row r.
 constexpr int TRI_PAIR_MIN = 127;
 struct TriUnit {
     int32_t p0, p1, entries, chunks;   // chunks: sum over rows of ceil(length / 64)
@@ -97,6 +98,8 @@ struct wcal_plan {
     // b0/b1 are unit ranges; the PASS solve uses these tiles for its pass and update
     bool canonical = false;       // baselines are every pair p < q in p-major order
     bool tri = false;
+    bool tri_paired = false;      // units are packed row pairs
+    bool tri_unfused = false;     // its triangle tiles only feed the unfused pass (cell plans)
     TriUnit* d_units = nullptr;
     int32_t nunits = 0;
     Tile* d_ttiles = nullptr;
@@ -161,6 +164,7 @@ struct DiArgs {
     double* chi_part;
     float* stats;
     int32_t n_ant, n_bl, n_int, max_iter, schedule;
+    int32_t tri_paired;      // triangle units are packed row pairs (see TriUnit)
     double tol;
 };
 
@@ -172,7 +176,20 @@ struct PointArgs {
     const float* flux = nullptr;   // [nd]
     double freq0 = 0.0, dfreq = 0.0;
     int32_t n_time = 0, n_chan = 0;
+    // phasor table of the solve, in the workspace (formed once per solve, read by every pass):
+    // zt [n_int][n_time][n_bl][nseg][4][nd]: S_d exp(-2 pi i phi nu) at channels 64 j + r,
+    // r < 4 (the channels where a lane's phasor walk starts or is re-based), and
+    // st [n_int][n_time][n_bl][nd]: exp(-2 pi i phi 4 dfreq), the step over four channels
+    float2* zt = nullptr;
+    float2* st = nullptr;
+    int32_t nseg = 0;              // ceil(n_chan / 64)
 };
+
+// Bytes of the phasor table for an n_time x n_chan grid (a multiple of WS_ALIGN).
+size_t points_table_bytes(const wcal_problem& p, int32_t n_time, int32_t n_chan);
+
+// Rebuild a plan's tiles with its current tiling (wcal_api.hip).
+int plan_retile(wcal_plan* plan);
 
 struct DdArgs {
     const float2* data;      // [rows]

@@ -264,19 +264,24 @@ def ragged_ns(n_int: int, t_max: int = 30, f_max: int = 16, seed: int = 0) -> li
 def bandpass_di(n_ant: int, n_chan: int, sigma: float = 0.05, seed: int = 0,
                 flag_frac: float = 0.0, device="cpu", dtype=torch.complex64,
                 nu_lo: float = 100e6, nu_hi: float = 200e6, noise: bool = True,
-                model: Optional[torch.Tensor] = None) -> Problem:
+                model: Optional[torch.Tensor] = None, channels: Optional[Sequence[int]] = None) -> Problem:
     """Scalar problem with one interval per channel (Ns = 1): per antenna, amplitude is a
     cubic polynomial c0 + c1 x + c2 x^2 + c3 x^3 over x in [-1, 1] across the band with
     c0 = exp(N(0, 0.1^2)), c1..c3 ~ N(0, 0.05^2); phase phi0 + 2 pi tau (nu - nu_mid)
     with phi0 ~ U(-pi, pi), tau ~ U(-50, 50) ns.  m ~ CN(0,1), noise CN(0, sigma^2).
     A given `model` [rows, 1, 1] is reused instead of drawing a new one (many observations
-    of the same sky with fresh gains and noise)."""
+    of the same sky with fresh gains and noise).  With `channels`, only those channels of
+    the n_chan-channel band are generated (one interval each, in the given order; `model`
+    then holds their rows only)."""
     gen = _gen(SEED_BASE * 16 + 3 + 7919 * seed, device)
     ant1, ant2 = baselines(n_ant, device)
-    ns = torch.ones(n_chan, dtype=torch.int64)
-    rows = n_chan * ant1.numel()
     f64 = torch.float64
     nu = nu_lo + (torch.arange(n_chan, device=device, dtype=f64) + 0.5) * (nu_hi - nu_lo) / n_chan
+    if channels is not None:
+        nu = nu[torch.as_tensor(channels, dtype=torch.int64, device=device)]
+    n_chan = nu.numel()
+    ns = torch.ones(n_chan, dtype=torch.int64)
+    rows = n_chan * ant1.numel()
     nu_mid = 0.5 * (nu_lo + nu_hi)
     x = 2 * (nu - nu_mid) / (nu_hi - nu_lo)
     c0 = torch.exp(0.1 * torch.randn(n_ant, generator=gen, device=device, dtype=f64))

@@ -51,6 +51,10 @@ class WarmStart:
         ns_k = plan.ns[self.knots.long()]
         self.coarse = wcal.Plan(plan.n_ant, plan.ant1, plan.ant2, ns_k, tol=coarse_tol,
                                 max_iter=coarse_max_iter, device=plan.device)
+        # the full plan's solve restricted to the knot channels (intervals are independent, so
+        # its solutions there are the full solve's): training targets without the other channels
+        self.fine = wcal.Plan(plan.n_ant, plan.ant1, plan.ant2, ns_k, tol=plan.prob.tol,
+                              max_iter=plan.prob.max_iter, device=plan.device)
         dev = torch.device("cuda", plan.device)
         rows = self.coarse.rows
         self._d = torch.empty(rows, 1, dtype=torch.complex64, device=dev)
@@ -107,6 +111,21 @@ class WarmStart:
         out = self.plan.solve(P.data, P.model, P.flags, P.unit_gains(), want_residual=False, want_chi2=False)
         t = wcal.gains_to_bins(out["gains"], self.bin_width, self.halfwidth)
         ok = bool(((out["status"] & wcal.CONVERGED) != 0).all())
+        return f, t, ok
+
+    def make_example_knots(self, K: synth.Problem):
+        """make_example from the knot channels alone (K holds only their rows, one interval per
+        knot in knot order, e.g. synth.bandpass_di(..., channels=knots)): the coarse pass and the
+        unit-start solve of the knots, which is what the full solve gives there.  Needs
+        halfwidth 0 (a wider target window reads channels between the knots)."""
+        assert self.halfwidth == 0 and K.ns.numel() == self.n_bins
+        g = torch.zeros(self.n_bins, 1, self.n_ant, 1, dtype=torch.complex64, device=K.data.device)
+        g[..., 0] = 1
+        co = self.coarse.solve(K.data, K.model, K.flags, g.clone(), want_residual=False, want_chi2=False)
+        fi = self.fine.solve(K.data, K.model, K.flags, g, want_residual=False, want_chi2=False)
+        f = wcal.gains_to_bins(co["gains"], 1, 0)
+        t = wcal.gains_to_bins(fi["gains"], 1, 0)
+        ok = bool(((fi["status"] & wcal.CONVERGED) != 0).all())
         return f, t, ok
 
     def train(self, X: torch.Tensor, T: torch.Tensor, epochs: int = 30, batch: int = 4096, lr: float = 1e-3,
@@ -178,6 +197,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=500)
+    ap.add_argument("--knots-only", action="store_true",
+                    help="generate the training observations at the knot channels only (the targets are "
+                         "the unit-start solutions there, as in a full solve; needs --halfwidth 0)")
     ap.add_argument("--out-json", default=None)
     a = ap.parse_args(argv)
 
@@ -193,9 +215,17 @@ def main(argv=None):
         f"{ws.n_bins} knots")
     t0 = time.perf_counter()
     X, T = [], []
+    n_bl = P0.ant1.numel()
+    knots = ws.knots.long().to(dev)
+    model_k = P0.model.view(a.n_chan, n_bl, 1, 1)[knots].reshape(-1, 1, 1).contiguous()
     for i in range(a.n_train):
-        P = P0 if i == 0 else synth.bandpass_di(a.n_ant, a.n_chan, seed=1000 + i, device=dev, model=P0.model)
-        f, t, ok = ws.make_example(P)
+        if a.knots_only:
+            P = synth.bandpass_di(a.n_ant, a.n_chan, seed=1000 + i, device=dev, model=model_k,
+                                  channels=ws.knots.tolist())
+            f, t, ok = ws.make_example_knots(P)
+        else:
+            P = P0 if i == 0 else synth.bandpass_di(a.n_ant, a.n_chan, seed=1000 + i, device=dev, model=P0.model)
+            f, t, ok = ws.make_example(P)
         if ok:
             X.append(f)
             T.append(t)
@@ -229,7 +259,12 @@ def main(argv=None):
         for k in r:
             r[k].pop("gains")
         del P
+    d_mc = [x["mean_iter"] - y["mean_iter"] for x, y in zip(rows["mlp"], rows["coarse"])]
     summary = dict(workload=f"bandpass_na{a.n_ant}", n_chan=a.n_chan, bin_width=a.bin_width,
+                   knots_only=a.knots_only,
+                   mlp_minus_coarse_iter=dict(mean=statistics.mean(d_mc),
+                                              stdev=statistics.stdev(d_mc) if len(d_mc) > 1 else 0.0,
+                                              min=min(d_mc), max=max(d_mc)),
                    n_knots=ws.n_bins, hidden=a.hidden, halfwidth=a.halfwidth, coarse_tol=a.coarse_tol,
                    n_train=a.n_train, n_test=a.n_test, epochs=a.epochs, examples=int(X.shape[0]),
                    data_s=round(t_data, 2), train_s=round(t_train, 2), loss_first=losses[0],
@@ -237,6 +272,7 @@ def main(argv=None):
                    warm_vs_unit_rel_diff_max=max(diff))
     for k, v in rows.items():
         summary[k] = dict(mean_iter=statistics.mean(x["mean_iter"] for x in v),
+                          stdev_iter=statistics.stdev(x["mean_iter"] for x in v) if len(v) > 1 else 0.0,
                           median_iter=statistics.median(x["median_iter"] for x in v),
                           coarse_iter=statistics.mean(x["coarse_iter"] for x in v),
                           ms_median=statistics.median(x["ms"] for x in v),

@@ -38,7 +38,7 @@ EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_des
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
            "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_mlp_save", "wcal_mlp_load",
-           "wcal_plan_smoothing", "wcal_solve_smooth", "wcal_solve_points", "wcal_solve_static")
+           "wcal_plan_smoothing", "wcal_solve_smooth", "wcal_solve_points", "wcal_points_workspace", "wcal_solve_static")
 K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
@@ -109,6 +109,8 @@ def lib() -> C.CDLL:
     L.wcal_solve_smooth.restype = C.c_int
     L.wcal_solve_points.argtypes = [vp, C.POINTER(Points)] + [vp] * 8 + [C.c_size_t, vp]
     L.wcal_solve_points.restype = C.c_int
+    L.wcal_points_workspace.argtypes = [vp, C.POINTER(Points), C.POINTER(C.c_size_t)]
+    L.wcal_points_workspace.restype = C.c_int
     L.wcal_profile_enable.argtypes = [vp, C.c_int]
     L.wcal_profile_enable.restype = C.c_int
     L.wcal_profile_read.argtypes = [vp, vp, vp]
@@ -170,6 +172,7 @@ class Plan:
         self.rows = int(L.wcal_plan_rows(self._h))
         self.pass_kernel = L.wcal_plan_pass_kernel(self._h).decode()
         self._ws = None
+        self._pws = None   # workspace of the points solve (the plan's plus the phasor table)
 
     # ---------------------------------------------------------------- workspace
     def workspace_bytes(self) -> int:
@@ -414,6 +417,13 @@ class Plan:
             chi2 = torch.empty(self.n_int, dtype=torch.float64, device=dev)
         self._dev(residual, "residual", torch.complex64, (R, 1))
         pts = Points(int(n_time), int(n_chan), float(freq0), float(dfreq), _ptr(uvw), _ptr(lmn), _ptr(flux))
+        if workspace is None:
+            nb = C.c_size_t(0)
+            _check(lib().wcal_points_workspace(self._h, C.byref(pts), C.byref(nb)))
+            if self._pws is None or self._pws.numel() < nb.value:
+                self._pws = None
+                self._pws = self._alloc(nb.value, dev)
+            workspace = self._pws
         wp, wn, _ = self._ws_args(workspace)
         _check(lib().wcal_solve_points(self._h, C.byref(pts), _ptr(data), _ptr(flags), _ptr(gains), _ptr(residual),
                                        _ptr(n_iter), _ptr(status), _ptr(chi2), wp, wn, self._stream(stream)))

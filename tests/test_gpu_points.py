@@ -156,3 +156,36 @@ def test_points_rejects_bad_grids():
     plan2 = wcal.plan_for(P, algo="cohjones", precision="bf16")
     with pytest.raises(wcal.WcalError):
         plan2.solve_points(**points_args(P), data=P.data, flags=P.flags, gains=P.unit_gains())
+
+
+def test_points_workspace_holds_the_phasor_table():
+    """wcal_points_workspace is the plan's workspace plus the phasor table (40 B per slot,
+    baseline and direction at up to 64 channels, 8 B more per 64 channels beyond); a
+    workspace one byte short is refused before anything is launched, and the call with
+    the exact size solves like the default one."""
+    import ctypes as C
+    P = problem(n_time=3, n_chan=8, seed=9)
+    plan = wcal.plan_for(P, algo="cohjones", tol=1e-6, max_iter=30)
+    a = points_args(P)
+    pts = wcal.Points(a["n_time"], a["n_chan"], a["freq0"], a["dfreq"], a["uvw"].data_ptr(),
+                      a["lmn"].data_ptr(), a["flux"].data_ptr())
+    n = C.c_size_t(0)
+    assert wcal.lib().wcal_points_workspace(plan._h, C.byref(pts), C.byref(n)) == wcal.OK
+    base = -(-plan.workspace_bytes() // wcal.WS_ALIGN) * wcal.WS_ALIGN
+    per = P.n_int * a["n_time"] * P.n_bl * P.n_dir
+    table = -(-per * 32 // wcal.WS_ALIGN) * wcal.WS_ALIGN + -(-per * 8 // wcal.WS_ALIGN) * wcal.WS_ALIGN
+    assert n.value == base + table, (n.value, base, table)
+    log(f"[points workspace] plan {plan.workspace_bytes()} B, with the table {n.value} B")
+    ws = torch.empty(n.value, dtype=torch.uint8, device=DEV)
+    status = torch.full((P.n_int,), 77, dtype=torch.int32, device=DEV)
+    with pytest.raises(wcal.WcalError) as ei:
+        plan.solve_points(**a, data=P.data, flags=P.flags, gains=P.unit_gains(), status=status,
+                          workspace=ws[:n.value - 1])
+    assert ei.value.code == wcal.ENOMEM
+    torch.cuda.synchronize()
+    assert torch.all(status == 77)
+    out = plan.solve_points(**a, data=P.data, flags=P.flags, gains=P.unit_gains(), workspace=ws)
+    ref = plan.solve_points(**a, data=P.data, flags=P.flags, gains=P.unit_gains())
+    torch.cuda.synchronize()
+    for key in ("gains", "n_iter", "status", "chi2", "residual"):
+        assert torch.equal(out[key], ref[key]), key
