@@ -675,6 +675,9 @@ constexpr int TRI_U = 4;    // chunks in flight per lane (4 measured best of 2..
 // One unit of a tile (samples [s0, s1) of interval k) into this wavefront's slice
 // acc[na + 1][3]; G holds na + 1 gains.  Lanes past the end of a row load the row's last
 // element (no extra memory traffic), contribute zeros, and add them to the spare slot na.
+// S1: the tile holds one sample (T.s1 == T.s0 + 1, every channel of the bandpass): each entry
+// is complete at once, so its sums need no state between chunks.
+template <bool S1>
 __device__ __forceinline__ void tri_unit(const DiArgs& a, const Tile& T, const TriUnit& U, const float2* G,
                                          float* acc) {
     const int na = a.n_ant;
@@ -704,16 +707,27 @@ __device__ __forceinline__ void tri_unit(const DiArgs& a, const Tile& T, const T
             use[u] = valid && !(has_flags && load_at(a.flags + base, cc) != 0);
             pu[u] = pr;
             qu[u] = valid ? pr + 1 + c : na;
-            end_e[u] = in && ss + 1 == T.s1;
-            end_r[u] = end_e[u] && 64 * (jj + 1) >= len;
-            if (in && ++ss == T.s1) {
-                ss = T.s0;
-                if (64 * (++jj) >= len) { jj = 0; ++pp; }
+            if constexpr (S1) {
+                end_e[u] = in;
+                end_r[u] = in && 64 * (jj + 1) >= len;
+                if (in && 64 * (++jj) >= len) { jj = 0; ++pp; }
+            } else {
+                end_e[u] = in && ss + 1 == T.s1;
+                end_r[u] = end_e[u] && 64 * (jj + 1) >= len;
+                if (in && ++ss == T.s1) {
+                    ss = T.s0;
+                    if (64 * (++jj) >= len) { jj = 0; ++pp; }
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < TRI_U; ++u) {
-            if (use[u]) {
+            if constexpr (S1) {
+                const float2 t = ccmul(m[u], d[u]);     // conj(m) d
+                m2 = use[u] ? nrm(m[u]) : 0.f;
+                tr = use[u] ? t.x : 0.f;
+                ti = use[u] ? t.y : 0.f;
+            } else if (use[u]) {
                 m2 += nrm(m[u]);
                 const float2 t = ccmul(m[u], d[u]);     // conj(m) d
                 tr += t.x;
@@ -886,7 +900,10 @@ __global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit
         if (a.tri_paired)
             for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit_paired(a, T, units[u], G, myacc);
         else
-            for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
+            for (int u = T.b0 + w; u < T.b1; u += nw) {
+                if (T.s1 - T.s0 == 1) tri_unit<true>(a, T, units[u], G, myacc);
+                else tri_unit<false>(a, T, units[u], G, myacc);
+            }
         __syncthreads();
         if constexpr (FUSED) {
             // fold the wavefront slices into the first, in wavefront order
@@ -1225,7 +1242,10 @@ di_loop_kernel(DiArgs a, LoopRing q, const TriUnit* __restrict__ units) {
             if (a.tri_paired)
                 for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit_paired(a, T, units[u], G, myacc);
             else
-                for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit(a, T, units[u], G, myacc);
+                for (int u = T.b0 + w; u < T.b1; u += nw) {
+                    if (T.s1 - T.s0 == 1) tri_unit<true>(a, T, units[u], G, myacc);
+                    else tri_unit<false>(a, T, units[u], G, myacc);
+                }
         } else {
             tile_walk<NC>(a, T, [&](int, int p, int qq, float (&st)[Ns<NC>::v]) {
                 flush_acc<NC>(p, qq, st, G, myacc);
