@@ -440,9 +440,13 @@ def main():
     value = vis_iter / (ms_step * 1e-3)
     bpr = bytes_per_row(P.n_corr, P.n_dir, P.flags is not None)
     if pts is not None:
-        # data and flag per row; the uvw of a (time, baseline), 24 B, serves n_chan rows
-        bpr = 8 * P.n_corr + (1 if P.flags is not None else 0) + 24.0 / pts["n_chan"]
-    resid_bytes = P.n_rows * (bpr + 8 * P.n_corr)
+        # data and flag per row; the phasor table of a (time slot, baseline), 40 B per direction
+        # per 64 channels (four re-base phasors and the step), serves n_chan rows
+        nseg = (pts["n_chan"] + 63) // 64
+        bpr = 8 * P.n_corr + (1 if P.flags is not None else 0) + 8.0 * P.n_dir * (4 * nseg + 1) / pts["n_chan"]
+    # the residual pass reads data, flags and model (or, predicting it, the uvw: 24 B per (time, baseline))
+    rbpr = bpr if pts is None else 8 * P.n_corr + (1 if P.flags is not None else 0) + 24.0 / pts["n_chan"]
+    resid_bytes = P.n_rows * (rbpr + 8 * P.n_corr)
     dd = P.n_dir > 1
     # wcal_solve_points runs its own Gram kernel, which predicts the model instead of reading it
     kname = "dd_gram_pts_kernel" if pts is not None else plan.pass_kernel
