@@ -101,8 +101,14 @@ def source_hash(family: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str):
-    """HBM bytes per launch from the committed counter runs, if the sources are unchanged."""
+def measured_traffic(key: str, default_solve: bool = True):
+    """HBM bytes per launch from the committed counter runs, if the sources are unchanged.
+
+    The counter runs solve each workload with its default settings (tolerance 1e-6, no update cap,
+    no smoothing); a run with other settings has other launches (a fixed number of full passes,
+    or the smoothed solve's passes over the whole grid), so no record applies to it."""
+    if not default_solve:
+        return None
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))[key]
     except (OSError, KeyError, ValueError):
@@ -325,6 +331,8 @@ def main():
                          "(a known-size reference for hardware byte counters)")
     args = ap.parse_args()
 
+    # the solve the counter runs measured: default tolerance and update cap, unsmoothed, PASS mode
+    default_run = args.max_iter is None and args.tol == 1e-6 and args.smooth is None and args.mode == "pass"
     if args.max_iter is None:
         args.max_iter = 300 if args.smooth else 100
     if args.gpus != 1:
@@ -512,7 +520,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(f"{kname}/{args.workload}"),
+            "traffic": measured_traffic(f"{kname}/{args.workload}", default_run),
             "kernel": kname,
             "kernel_ms_per_launch": kms / max(klaunch, 1),
             "launches_per_step": klaunch / args.steps,
@@ -529,7 +537,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": tfs / peak,
-            "traffic": measured_traffic(f"{kname}/{args.workload}"),
+            "traffic": measured_traffic(f"{kname}/{args.workload}", default_run),
             "kernel": kname,
             "kernel_ms_per_launch": kms / max(klaunch, 1),
             "launches_per_step": klaunch / args.steps,
