@@ -222,8 +222,12 @@ __device__ __forceinline__ float2 cis_quarter(double x) {
 // sample of the wavefront's baselines, a chunk ahead): the slice holds the data value, zeroed
 // where the row is flagged or absent, and a weight 1 or 0.  Every lane then forms its operand
 // as a product, v = z * P: model lanes take P = (weight, weight), the data lane keeps
-// z = (1, 1) and takes P = the data value, and lanes past column Nd keep z = 0.  The
-// wavefronts of a task meet only at the task pop.
+// z = (1, 1) and takes P = the data value, and lanes past column Nd keep z = 0.  Without
+// flags (PLAIN) no row inside the interval has weight 0, so z itself is the operand: the step
+// becomes z <- z * step + P, where model lanes read P = 0 (their slice holds zeros) and the
+// data lane, whose step is 0, reads the next group's data; only an interval's last group, when
+// it is partial, zeroes the z of its absent samples first.  The wavefronts of a task meet only
+// at the task pop.
 constexpr int PREBASE = 16;
 static_assert(PREBASE * 4 == 64, "the phasor table holds one segment per 64 channels");
 
@@ -281,11 +285,13 @@ __device__ __forceinline__ void fold_block(floatx4 (&crr)[NB], floatx4 (&cri)[NB
 constexpr int PCH = 64;   // samples per staged chunk: one per lane
 constexpr int PBW = 4;    // baselines per wavefront
 constexpr int PGB = (DT / WAVE) * PBW;   // baselines per task
+template <bool PLAIN>
 __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8))) dd_gram_pts_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
-    // per wavefront: [0] [sample][baseline] data, [1] [sample][baseline] (weight, weight),
-    // each followed by two groups of padding that the read-ahead after a chunk's last two
-    // groups lands in (its values are never used); the slice also holds the 512-float record tile
-    __shared__ float2 sbuf[DT / WAVE][2][(PCH + 8) * PBW];
+    // per wavefront: [0] [sample][baseline] data, [1] [sample][baseline] (weight, weight) (PLAIN:
+    // zeros), each followed by three groups of padding that the read-ahead after a chunk's last
+    // groups lands in (zero: PLAIN's step after a chunk's last group adds it to z); slice 0 also
+    // holds the 512-float record tile
+    __shared__ float2 sbuf[DT / WAVE][2][(PCH + 12) * PBW];
     __shared__ int s_task;
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -300,6 +306,10 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8)))
     const bool is_m = col < nd, is_d = col == nd;
     const int nch = a.pt.n_chan, nt = a.pt.n_time, nseg = a.pt.nseg;
     const float2* src = sbuf[w][is_d ? 0 : 1];   // this lane's operand factors
+    for (int e = lane; e < (PCH + 12) * PBW; e += WAVE) {
+        if (PLAIN || e >= PCH * PBW) sbuf[w][1][e] = make_float2(0.f, 0.f);
+        if (e >= PCH * PBW) sbuf[w][0][e] = make_float2(0.f, 0.f);
+    }
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_task = atomicAdd(&st.ctr[0], 1);
@@ -323,8 +333,8 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8)))
             trr[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             tri4[j] = floatx4{0.f, 0.f, 0.f, 0.f};
             cnt[j] = 0;
-            z[j] = is_d ? make_float2(1.f, 1.f) : make_float2(0.f, 0.f);
-            stp[j] = is_d ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
+            z[j] = is_d && !PLAIN ? make_float2(1.f, 1.f) : make_float2(0.f, 0.f);
+            stp[j] = is_d && !PLAIN ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
         }
         // the lane's sample (kk + 4g) sits at time slot t, channel f (f may run past the slot
         // until the next re-base); left counts the groups its phasor stays valid for
@@ -354,18 +364,21 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8)))
                     const bool ok = sv && j < nv && pf[j] == 0;
                     const float wv = ok ? 1.f : 0.f;
                     sbuf[w][0][lane * PBW + j] = ok ? pd[j] : make_float2(0.f, 0.f);
-                    sbuf[w][1][lane * PBW + j] = make_float2(wv, wv);
+                    if (!PLAIN) sbuf[w][1][lane * PBW + j] = make_float2(wv, wv);
                     cnt[j] += ok ? 1 : 0;
                 }
             }
             __builtin_amdgcn_wave_barrier();
             const int ng = min(PCH / 4, (ns - c * PCH + 3) / 4);
-            // operand factors of groups gg (Pa) and gg + 1 (Pb), read two groups ahead of their MFMAs
+            // staged factors, read two groups ahead of their use: operand factors of groups gg (Pa)
+            // and gg + 1 (Pb); PLAIN: the step's addends, of groups gg + 1 and gg + 2
+            constexpr int O = PLAIN ? 1 : 0;
             float2 Pa[PBW], Pb[PBW];
 #pragma unroll
             for (int j = 0; j < PBW; ++j) {
-                Pa[j] = src[kk * PBW + j];
-                Pb[j] = src[(4 + kk) * PBW + j];
+                Pa[j] = src[(4 * O + kk) * PBW + j];
+                Pb[j] = src[(4 * O + 4 + kk) * PBW + j];
+                if (PLAIN && is_d) z[j] = src[kk * PBW + j];   // the data lane's z: its own data
             }
             int gg = 0;
             while (gg < ng) {
@@ -398,28 +411,56 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8)))
                 int seg = min(__builtin_amdgcn_readlane(left, 0), __builtin_amdgcn_readlane(left, 16));
                 seg = min(seg, min(__builtin_amdgcn_readlane(left, 32), __builtin_amdgcn_readlane(left, 48)));
                 seg = min(seg, ng - gg);
+                if (PLAIN) {
+                    // an interval's partial last group runs alone, with the z of its absent samples zeroed
+                    const int gf = (ns - c * PCH) / 4;   // groups of the chunk that lie inside the interval
+                    if (gg < gf) {
+                        seg = min(seg, gf - gg);
+                    } else if (4 * (c * (PCH / 4) + gg) + kk >= ns) {
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) z[j] = make_float2(0.f, 0.f);
+                    }
+                }
                 if (gg == 0 && c + 1 < nchunk) fetch(c + 1);   // behind the re-base's uvw loads
                 // one group: operands from z and the staged factors P, which then take group
-                // g + 2's (after a chunk's last two groups: the padding), three MFMAs per
-                // baseline, step z
+                // g + 2's (after a chunk's last groups: the padding), three MFMAs per baseline,
+                // step z.  PLAIN: z is the operand, the step adds P (group g + 1's addend), and
+                // P then takes group g + 3's
                 auto group = [&](int g, float2 (&P)[PBW]) {
-                    float vx[PBW], vy[PBW];
+                    if constexpr (PLAIN) {
 #pragma unroll
-                    for (int j = 0; j < PBW; ++j) {
-                        vx[j] = z[j].x * P[j].x;
-                        vy[j] = z[j].y * P[j].y;
+                        for (int j = 0; j < PBW; ++j) {
+                            crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(z[j].x, z[j].x, crr[j], 0, 0, 0);
+                            crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(z[j].y, z[j].y, crr[j], 0, 0, 0);
+                            cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(z[j].x, z[j].y, cri[j], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) {
+                            z[j] = make_float2(fmaf(z[j].x, stp[j].x, fmaf(-z[j].y, stp[j].y, P[j].x)),
+                                               fmaf(z[j].x, stp[j].y, fmaf(z[j].y, stp[j].x, P[j].y)));
+                        }
+                        const float2* pr = src + (4 * g + 12 + kk) * PBW;
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) P[j] = pr[j];
+                    } else {
+                        float vx[PBW], vy[PBW];
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) {
+                            vx[j] = z[j].x * P[j].x;
+                            vy[j] = z[j].y * P[j].y;
+                        }
+                        const float2* pr = src + (4 * g + 8 + kk) * PBW;
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) P[j] = pr[j];
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) {
+                            crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx[j], vx[j], crr[j], 0, 0, 0);
+                            crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy[j], vy[j], crr[j], 0, 0, 0);
+                            cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx[j], vy[j], cri[j], 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int j = 0; j < PBW; ++j) z[j] = cmul(z[j], stp[j]);
                     }
-                    const float2* pr = src + (4 * g + 8 + kk) * PBW;
-#pragma unroll
-                    for (int j = 0; j < PBW; ++j) P[j] = pr[j];
-#pragma unroll
-                    for (int j = 0; j < PBW; ++j) {
-                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx[j], vx[j], crr[j], 0, 0, 0);
-                        crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vy[j], vy[j], crr[j], 0, 0, 0);
-                        cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(vx[j], vy[j], cri[j], 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int j = 0; j < PBW; ++j) z[j] = cmul(z[j], stp[j]);
                 };
                 // two groups per trip (a loop-carried z then needs no register copies); after an
                 // odd count the next group's factors are in Pb
@@ -1249,7 +1290,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
     const bool p16 = nd % 2 == 0 && reinterpret_cast<uintptr_t>(a.model) % 16 == 0;
     typedef void (*GramFn)(DdArgs, DdState, const int32_t*, const int32_t*);
     const bool pred = a.pt.uvw != nullptr;
-    GramFn gram = pred ? dd_gram_pts_kernel
+    GramFn gram = pred ? (a.flags ? dd_gram_pts_kernel<false> : dd_gram_pts_kernel<true>)
                        : !bf ? (p16 ? dd_gram_dmaf_kernel<16> : dd_gram_dmaf_kernel<4>) : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
     const size_t gsm = !pred && !bf ? dmaf_smem_bytes(nd) : 0;
     const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), gsm, pred ? (int64_t)a.n_int * ((a.n_bl + PGB - 1) / PGB) : nblk);
