@@ -87,6 +87,10 @@ def _code_only(text: str) -> str:
     return "".join(out)
 
 
+# update slots an eager solve keeps enqueued past the last convergence count it has read
+WATCH_DEPTH = 2
+
+
 def source_hash(family: str) -> str:
     """sha256 of what decides a kernel family's memory traffic: its kernel sources, the plan
     and launch code, and the public header, comments removed."""
@@ -105,8 +109,9 @@ def measured_traffic(key: str, default_solve: bool = True):
     """HBM bytes per launch from the committed counter runs, if the sources are unchanged.
 
     The counter runs solve each workload with its default settings (tolerance 1e-6, no update cap,
-    no smoothing); a run with other settings has other launches (a fixed number of full passes,
-    or the smoothed solve's passes over the whole grid), so no record applies to it."""
+    no smoothing, the default host watch); a run with other settings has other launches (a fixed
+    number of full passes, the smoothed solve's passes over the whole grid, or the empty slots an
+    unwatched solve launches), so no record applies to it."""
     if not default_solve:
         return None
     try:
@@ -326,13 +331,18 @@ def main():
     ap.add_argument("--points", action="store_true",
                     help="point-source workloads (cohjones_na64): predict the model in the passes "
                          "(wcal_solve_points) instead of reading it from HBM")
+    ap.add_argument("--watch", type=int, default=WATCH_DEPTH, metavar="DEPTH",
+                    help="host watch of the per-update launches (wcal_plan_watch): eager solves stop "
+                         "enqueuing update slots once every interval has stopped, DEPTH slots ahead; "
+                         "0: every slot is launched, and solves are timed as HIP graph replays")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(a known-size reference for hardware byte counters)")
     args = ap.parse_args()
 
     # the solve the counter runs measured: default tolerance and update cap, unsmoothed, PASS mode
-    default_run = args.max_iter is None and args.tol == 1e-6 and args.smooth is None and args.mode == "pass"
+    default_run = (args.max_iter is None and args.tol == 1e-6 and args.smooth is None and args.mode == "pass"
+                   and args.watch == WATCH_DEPTH)
     if args.max_iter is None:
         args.max_iter = 300 if args.smooth else 100
     if args.gpus != 1:
@@ -373,6 +383,10 @@ def main():
                    uvw=m["uvw"].contiguous(), lmn=m["lmn"].to(dev).contiguous(),
                    flux=m["flux"].to(dev, torch.float32).contiguous())
         args.no_graph, args.no_autotune = True, True
+    graph_too = args.watch > 0 and not args.no_graph    # also time graph replays (every slot)
+    if args.watch > 0:
+        plan.watch(args.watch)     # captured graphs record every slot: time eager calls
+        args.no_graph = True
     g0 = P.unit_gains() if smooth is None else torch.ones(1, P.n_int, P.n_ant, dtype=torch.complex64, device=dev)
     n_out = P.n_int if smooth is None else 1
     tuned = None
@@ -407,10 +421,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed steps (the headline time), each one solve replayed from a HIP graph capture of
-    # wcal_solve (or eager calls with --no-graph); then the same number of eager steps with
-    # HIP events on the launch stream around every kernel launch, for the per-kernel
-    # durations (an event pair costs a few microseconds per launch, kept out of the headline)
+    # timed steps (the headline time): eager solves under the host watch, which stop enqueuing
+    # update slots once every interval has stopped (with --watch 0: each solve replayed from a
+    # HIP graph capture of wcal_solve, or eager calls with --no-graph); then the same number of
+    # eager steps with HIP events on the launch stream around every kernel launch, for the
+    # per-kernel durations (an event pair costs a few microseconds per launch, kept out of the
+    # headline)
     timed = step
     if not args.no_graph:
         graph = plan.solve_graph(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter,
@@ -428,6 +444,22 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_graph = None
+    if graph_too:
+        # the same solve replayed from a HIP graph capture, which records all max_iter slots
+        graph = plan.solve_graph(P.data, P.model, P.flags, gains, residual=residual, n_iter=n_iter,
+                                 status=status, chi2=chi2)
+        gains.copy_(g0)
+        graph.launch()
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        for i in range(args.steps):
+            gains.copy_(g0)
+            graph.launch()
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - tg0) * 1e3 / args.steps
+        graph.close()
+        log(f"[bench] graph replays (every slot): {ms_graph:.3f} ms/solve")
     plan.profile(True)
     plan.profile_read()
     torch.cuda.synchronize()
@@ -505,9 +537,11 @@ def main():
         "smoothing": None if smooth is None else {"grid": [1, P.n_int], "sigma_t": smooth[0], "sigma_f": smooth[1]},
         "predicted_model": pts is not None,
         "timed_as": ("eager wcal_solve_points calls" if pts else "eager wcal_solve_smooth calls" if smooth else
-                     "eager wcal_solve calls" if args.no_graph else "HIP graph replays of wcal_solve"),
+                     "eager wcal_solve calls" if args.no_graph else "HIP graph replays of wcal_solve")
+                    + (f", host watch of depth {args.watch}" if args.watch > 0 else ""),
         "autotune": tuned,
         "solve_time_ms_with_kernel_events": ms_step_profiled,
+        "solve_time_ms_graph_every_slot": ms_graph,
         "mode": args.mode,
         "pass_form": ("every update streams the samples once and accumulates J^H J and J^H D per antenna "
                       "(data form, Eq. ghat; J^H r = J^H D - J^H J g); the residual R and chi^2 are formed "
@@ -557,6 +591,8 @@ def main():
         alt = "stats" if args.mode == "pass" else "pass"
         plan_alt = wcal.plan_for(P, algo=algo, tol=args.tol, max_iter=args.max_iter, mode=alt,
                                  precision=args.precision)
+        if args.watch > 0:
+            plan_alt.watch(args.watch)
         plan, plan_main = plan_alt, plan
         step()
         torch.cuda.synchronize()

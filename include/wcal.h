@@ -198,10 +198,12 @@ int wcal_plan_autotune(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mo
  * update is a pass over the rows of the intervals still iterating (StefCal: the tiles on the
  * device-built active list; CohJones / AllJones: the Gram pass) followed by the update
  * kernels; the launches of all max_iter updates are issued up front and an update with no
- * interval left iterating returns at once.  In STATS mode one statistics pass is followed by updates on the statistics
- * (StefCal: one launch that iterates every interval; CohJones / AllJones: per-update
- * launches).  Every solve ends with a tiled residual pass.  No call allocates, synchronises
- * the host or records a memset node, so the call can be captured into a HIP graph. */
+ * interval left iterating returns at once (with the plan's host watch on, wcal_plan_watch,
+ * the call stops issuing them once every interval has stopped).  In STATS mode one
+ * statistics pass is followed by updates on the statistics (StefCal: one launch that
+ * iterates every interval; CohJones / AllJones: per-update launches).  Every solve ends with
+ * a tiled residual pass.  No call allocates or records a memset node, and none synchronises
+ * the host unless the host watch is on, so the call can be captured into a HIP graph. */
 int wcal_solve(wcal_plan* plan, const wcal_c64* data, const wcal_c64* model,
                const uint8_t* flags, wcal_c64* gains, wcal_c64* residual,
                int32_t* n_iter, uint32_t* status, double* chi2, void* workspace, size_t ws_bytes,
@@ -222,6 +224,24 @@ int wcal_solve_graph(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mode
                      size_t ws_bytes, void* stream, wcal_graph** out);
 int wcal_graph_launch(wcal_graph* graph, void* stream);
 void wcal_graph_destroy(wcal_graph* graph);   /* NULL is a no-op */
+
+/* Host watch of the per-update launches.  A per-update solve (StefCal in PASS mode,
+ * CohJones / AllJones in either mode, the smoothed and the predicted-model solves) enqueues
+ * one group of launches per update slot, max_iter of them, and the intervals stop at
+ * different updates, each at its own convergence test: a slot after the last one has
+ * stopped finds nothing to do.  With a watch of depth > 0, wcal_solve, wcal_solve_static,
+ * wcal_solve_smooth and wcal_solve_points copy, after every slot, the device count of the
+ * work listed for the next update into pinned host memory on a side stream, keep at most
+ * `depth` slots enqueued past the last count read, and stop enqueuing once a count reads 0;
+ * the residual pass follows as usual.  The results are those of the unwatched call (the
+ * omitted slots would do nothing).  The call blocks the calling thread until the solve is
+ * within `depth` slots of its last update, so the stream must not wait on work that the
+ * caller submits after the call.  Under stream capture (wcal_solve_graph) every slot is
+ * recorded, as without the watch.  depth 0 (the default) turns the watch off; until then, or
+ * wcal_plan_destroy, the plan holds a side stream, 2 depth events and depth pinned host
+ * words.  Errors: WCAL_EINVAL (NULL plan, depth outside [0, WCAL_WATCH_MAX]), WCAL_EHIP. */
+#define WCAL_WATCH_MAX 64
+int wcal_plan_watch(wcal_plan* plan, int32_t depth);
 
 /* wcal_solve for callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): the same solve, arguments as in

@@ -1322,6 +1322,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
         hipLaunchKernelGGL(dd_ant_kernel, dim3(a.n_int * na), dim3(DT), asm_, s, a, st, it);
         hipLaunchKernelGGL(dd_finish_kernel, dim3(a.n_int), dim3(DT), 0, s, a, st, it);
         prof_end(plan, stats ? WCAL_K_SOLVE_STATS : WCAL_K_UPDATE, s);
+        if (watch_stop(plan, s, st.ctr + dd_nlist_slot(it + 1), it)) break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

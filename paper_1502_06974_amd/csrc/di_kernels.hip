@@ -1413,6 +1413,7 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
                 hipLaunchKernelGGL(di_update_kernel<1>, dim3(a.n_int), dim3(TB), us, s, at, it);
                 prof_end(plan, WCAL_K_UPDATE, s);
             }
+            if (watch_stop(plan, s, a.ctr + (a.max_iter + 2) + it + 1, it)) break;   // tiles listed for it + 1
         }
     } else {
         const size_t ps = pass_smem(na, NC);
@@ -1424,6 +1425,7 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
             prof_begin(plan, WCAL_K_UPDATE, s);
             hipLaunchKernelGGL(di_update_kernel<NC>, dim3(a.n_int), dim3(TB), us, s, a, it);
             prof_end(plan, WCAL_K_UPDATE, s);
+            if (watch_stop(plan, s, a.ctr + (a.max_iter + 2) + it + 1, it)) break;   // tiles listed for it + 1
         }
     }
     hipError_t e = hipGetLastError();

@@ -431,6 +431,7 @@ int wcal_solve_smooth(wcal_plan* plan, const wcal_c64* data, const wcal_c64* mod
                            sp->d_flag, sp->d_active, status, n_iter, it, p.max_iter, p.tol, ncell, toff, cp->d_lists,
                            npt, cp->d_ctr, cp->prob.max_iter + 2);
         prof_end(plan, WCAL_K_UPDATE, s);
+        if (watch_stop(plan, s, cp->d_ctr + (cp->prob.max_iter + 2) + it + 1, it)) break;   // tiles listed for it + 1
     }
     if (residual || chi2) {
         DiArgs r = a;

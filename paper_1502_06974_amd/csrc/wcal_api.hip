@@ -85,6 +85,72 @@ void prof_end(const wcal_plan* plan, int cls, hipStream_t s) {
 
 extern "C" {
 
+extern "C++" bool watch_stop(const wcal_plan* plan, hipStream_t s, const int32_t* d_count, int it) {
+    SlotWatch* w = plan->watch;
+    if (!w) return false;
+    if (it == 0) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        w->live = hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+    }
+    if (!w->live) return false;
+    const int r = it % w->depth;
+    if (hipEventRecord(w->slot_ev[r], s) != hipSuccess || hipStreamWaitEvent(w->side, w->slot_ev[r], 0) != hipSuccess ||
+        hipMemcpyAsync(w->host + r, d_count, sizeof(int32_t), hipMemcpyDeviceToHost, w->side) != hipSuccess ||
+        hipEventRecord(w->copy_ev[r], w->side) != hipSuccess) {
+        w->live = false;   // every remaining slot is enqueued, as without the watch
+        return false;
+    }
+    if (it + 1 < w->depth) return false;
+    const int r0 = (it + 1) % w->depth;   // the copy of slot it + 1 - depth
+    if (hipEventSynchronize(w->copy_ev[r0]) != hipSuccess) {
+        w->live = false;
+        return false;
+    }
+    return *static_cast<volatile int32_t*>(w->host + r0) == 0;
+}
+
+static void watch_free(wcal_plan* plan) {
+    SlotWatch* w = plan->watch;
+    if (!w) return;
+    if (w->side) (void)hipStreamSynchronize(w->side);
+    for (hipEvent_t e : w->slot_ev) if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : w->copy_ev) if (e) (void)hipEventDestroy(e);
+    if (w->side) (void)hipStreamDestroy(w->side);
+    if (w->host) (void)hipHostFree(w->host);
+    delete w;
+    plan->watch = nullptr;
+}
+
+int wcal_plan_watch(wcal_plan* plan, int32_t depth) {
+    g_err.clear();
+    if (!plan) return fail(WCAL_EINVAL, "plan is NULL");
+    if (depth < 0 || depth > WCAL_WATCH_MAX) return fail(WCAL_EINVAL, "watch depth must be in [0, WCAL_WATCH_MAX]");
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(plan->device);
+    watch_free(plan);
+    int rc = WCAL_OK;
+    if (depth > 0) {
+        SlotWatch* w = new SlotWatch;
+        plan->watch = w;
+        w->depth = depth;
+        w->slot_ev.assign(depth, nullptr);
+        w->copy_ev.assign(depth, nullptr);
+        hipError_t e = hipStreamCreateWithFlags(&w->side, hipStreamNonBlocking);
+        for (int i = 0; i < depth && e == hipSuccess; ++i) {
+            e = hipEventCreateWithFlags(&w->slot_ev[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&w->copy_ev[i], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&w->host), depth * sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            watch_free(plan);
+            rc = hip_fail(e, "wcal_plan_watch");
+        }
+    }
+    (void)hipSetDevice(dev);
+    return rc;
+}
+
 int wcal_profile_enable(wcal_plan* plan, int enable) {
     g_err.clear();
     if (!plan) return fail(WCAL_EINVAL, "plan is NULL");
@@ -477,6 +543,7 @@ void wcal_plan_destroy(wcal_plan* plan) {
     if (!plan) return;
     wcal_profile_enable(plan, 0);
     (void)hipSetDevice(plan->device);
+    watch_free(plan);
     smooth_free(plan->smooth);
     plan->smooth = nullptr;
     // only the host-built tables are plan-owned; scratch lives in the caller's workspace

@@ -19,6 +19,23 @@ struct Profiler;
 void prof_begin(const wcal_plan* plan, int cls, hipStream_t s);
 void prof_end(const wcal_plan* plan, int cls, hipStream_t s);
 
+// Host watch of the per-update launches (wcal_plan_watch).  After every update slot a side
+// stream copies the device count of work items listed for the next update into pinned host
+// memory; the host keeps at most `depth` slots enqueued past the last count it has read and
+// stops enqueuing once a count reads 0: every interval has stopped, and the slots left would
+// find nothing listed.  Not under stream capture, where every slot is recorded.
+struct SlotWatch {
+    int depth = 0;
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> slot_ev, copy_ev;   // [depth] each, reused round robin
+    int32_t* host = nullptr;                    // pinned [depth]
+    bool live = false;                          // the current call is watched
+};
+// Call after enqueuing update slot `it` of a per-update solve on stream s, with d_count the
+// device counter of the work items listed for update it + 1.  True: no slot after `it`
+// has work, so the caller stops enqueuing slots.
+bool watch_stop(const wcal_plan* plan, hipStream_t s, const int32_t* d_count, int it);
+
 // A unit of the triangle pass (baselines in the canonical order: all pairs p < q,
 // p-major, q increasing): the whole rows p in [p0, p1) of the triangle, at most 64; or, when
 // the plan packs rows (possible from TRI_PAIR_MIN antennas on), packed rows r in [p0, p1),
@@ -106,6 +123,7 @@ struct wcal_plan {
     int32_t* d_ttile_off = nullptr;
     int32_t nttiles = 0;
     Profiler* prof = nullptr;     // non-null while timing is enabled
+    SlotWatch* watch = nullptr;   // non-null while the host watches the per-update launches
     // time/frequency smoothing (scalar StefCal): the cell plan and its scratch, or null
     struct SmoothPlan* smooth = nullptr;
     // workspace: the plan's own regions, then (with smoothing) the smoothing scratch and the

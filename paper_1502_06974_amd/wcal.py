@@ -38,7 +38,8 @@ EXPORTS = ("wcal_last_error", "wcal_version", "wcal_plan_create", "wcal_plan_des
            "wcal_gains_to_bins", "wcal_reset_unconverged", "wcal_mlp_create", "wcal_mlp_destroy",
            "wcal_mlp_num_params", "wcal_mlp_set_params", "wcal_mlp_get_params", "wcal_mlp_forward",
            "wcal_mlp_gradients", "wcal_mlp_train_step", "wcal_mlp_save", "wcal_mlp_load",
-           "wcal_plan_smoothing", "wcal_solve_smooth", "wcal_solve_points", "wcal_points_workspace", "wcal_solve_static")
+           "wcal_plan_smoothing", "wcal_solve_smooth", "wcal_solve_points", "wcal_points_workspace", "wcal_solve_static",
+           "wcal_plan_watch")
 K_CLASSES = ("pass", "update", "stats", "solve_stats", "resid", "other")
 
 
@@ -113,6 +114,8 @@ def lib() -> C.CDLL:
     L.wcal_points_workspace.restype = C.c_int
     L.wcal_profile_enable.argtypes = [vp, C.c_int]
     L.wcal_profile_enable.restype = C.c_int
+    L.wcal_plan_watch.argtypes = [vp, C.c_int32]
+    L.wcal_plan_watch.restype = C.c_int
     L.wcal_profile_read.argtypes = [vp, vp, vp]
     L.wcal_profile_read.restype = C.c_int
     L.wcal_bin_knots.argtypes = [C.c_int32, C.c_int32, vp]
@@ -215,6 +218,13 @@ class Plan:
     def profile(self, enable: bool = True):
         """Bracket every kernel of later solve/residual calls with HIP events."""
         _check(lib().wcal_profile_enable(self._h, int(enable)))
+
+    def watch(self, depth: int = 4):
+        """Host watch of the per-update launches (wcal_plan_watch): later eager solves stop
+        enqueuing update slots once every interval has stopped, keeping at most `depth` slots
+        in flight past the last count read (the call then blocks the host until the solve is
+        that close to its end).  depth 0 turns it off."""
+        _check(lib().wcal_plan_watch(self._h, int(depth)))
 
     def profile_read(self) -> dict:
         """{class: (total ms, launches)} since the previous read (waits for the events)."""

@@ -91,6 +91,7 @@ def test_null_arguments():
     assert L.wcal_solve_smooth(*([None] * 10), 0, None) == wcal.EINVAL
     assert L.wcal_solve_points(None, None, *([None] * 8), 0, None) == wcal.EINVAL
     assert L.wcal_points_workspace(None, None, C.byref(n)) == wcal.EINVAL
+    assert L.wcal_plan_watch(None, 2) == wcal.EINVAL
     assert L.wcal_mlp_save(None, b"/tmp/x") == wcal.EINVAL
     assert L.wcal_mlp_load(None, b"/tmp/x") == wcal.EINVAL
     L.wcal_plan_destroy(None)
