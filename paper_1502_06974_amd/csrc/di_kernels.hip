@@ -866,16 +866,21 @@ __device__ void finish_interval(const DiArgs& a, int it, int k, int t0, int t1, 
 
 // FUSED: every interval is one tile, so the workgroup that sums a tile holds its interval's
 // complete sums and applies the update itself (no partials, no update launch).
+// Workgroup of the triangle pass: eight wavefronts walk an interval's units (three workgroups
+// per CU at its 58 VGPRs).  Against four wavefronts, the tail updates, in which a few intervals
+// are left and each runs on one workgroup, finish sooner, and full passes lose nothing
+// (bandpass_na256 solve 6.45-6.60 -> 6.39 ms); six and twelve wavefronts measured slower.
+constexpr int TRI_TB = 512;
 template <bool FUSED>
-__global__ void __launch_bounds__(TB) di_tri_pass_kernel(DiArgs a, const TriUnit* __restrict__ units, int it) {
+__global__ void __launch_bounds__(TRI_TB) di_tri_pass_kernel(DiArgs a, const TriUnit* __restrict__ units, int it) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NVP = Nv<1, 0>::v;
     const int na = a.n_ant;
     const int ns = (na + 1) * NVP;                  // slice: na antennas + the spare slot
     float2* G = reinterpret_cast<float2*>(smem);    // na + 1 (the last is 0)
     float* acc = reinterpret_cast<float*>(G + na + 1);
-    float2* Gn = reinterpret_cast<float2*>(acc + (TB / WAVE) * ns);   // FUSED: candidate gains
-    __shared__ double red[TB / WAVE];
+    float2* Gn = reinterpret_cast<float2*>(acc + (TRI_TB / WAVE) * ns);   // FUSED: candidate gains
+    __shared__ double red[TRI_TB / WAVE];
     __shared__ int s_flags[2];
     __shared__ int s_pos;
     __shared__ int s_t;
@@ -1396,17 +1401,17 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
         at.tile_off = plan->d_ttile_off;
         at.ntiles = plan->nttiles;
         const bool fused = plan->nttiles == a.n_int;    // one tile per interval
-        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TB / WAVE) * (na + 1) * 3 * sizeof(float) +
+        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TRI_TB / WAVE) * (na + 1) * 3 * sizeof(float) +
                           (fused ? (size_t)na * sizeof(float2) : 0);
         const void* fn = fused ? reinterpret_cast<const void*>(di_tri_pass_kernel<true>)
                                : reinterpret_cast<const void*>(di_tri_pass_kernel<false>);
-        const int gp = grid_resident(plan, fn, TB, ps, at.ntiles);
+        const int gp = grid_resident(plan, fn, TRI_TB, ps, at.ntiles);
         for (int it = 0; it < a.max_iter; ++it) {
             prof_begin(plan, WCAL_K_PASS, s);
             if (fused)
-                hipLaunchKernelGGL(di_tri_pass_kernel<true>, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
+                hipLaunchKernelGGL(di_tri_pass_kernel<true>, dim3(gp), dim3(TRI_TB), ps, s, at, (const TriUnit*)plan->d_units, it);
             else
-                hipLaunchKernelGGL(di_tri_pass_kernel<false>, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
+                hipLaunchKernelGGL(di_tri_pass_kernel<false>, dim3(gp), dim3(TRI_TB), ps, s, at, (const TriUnit*)plan->d_units, it);
             prof_end(plan, WCAL_K_PASS, s);
             if (!fused) {
                 prof_begin(plan, WCAL_K_UPDATE, s);
@@ -1459,9 +1464,9 @@ hipError_t launch_di_pass_partials(const wcal_plan* plan, const wcal_plan* prof_
         at.tiles = plan->d_ttiles;
         at.tile_off = plan->d_ttile_off;
         at.ntiles = plan->nttiles;
-        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TB / WAVE) * (na + 1) * 3 * sizeof(float);
-        const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_tri_pass_kernel<false>), TB, ps, at.ntiles);
-        hipLaunchKernelGGL(di_tri_pass_kernel<false>, dim3(gp), dim3(TB), ps, s, at, (const TriUnit*)plan->d_units, it);
+        const size_t ps = (size_t)(na + 1) * sizeof(float2) + (size_t)(TRI_TB / WAVE) * (na + 1) * 3 * sizeof(float);
+        const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_tri_pass_kernel<false>), TRI_TB, ps, at.ntiles);
+        hipLaunchKernelGGL(di_tri_pass_kernel<false>, dim3(gp), dim3(TRI_TB), ps, s, at, (const TriUnit*)plan->d_units, it);
     } else {
         const size_t ps = pass_smem(na, 1);
         const int gp = grid_resident(plan, reinterpret_cast<const void*>(di_pass_kernel<1>), TB, ps, a.ntiles);
