@@ -237,7 +237,9 @@ void wcal_graph_destroy(wcal_graph* graph);   /* NULL is a no-op */
  * omitted slots would do nothing).  The call blocks the calling thread until the solve is
  * within `depth` slots of its last update, so the stream must not wait on work that the
  * caller submits after the call.  Under stream capture (wcal_solve_graph) every slot is
- * recorded, as without the watch.  depth 0 (the default) turns the watch off; until then, or
+ * recorded, as without the watch.  The watch's events and pinned words belong to the plan:
+ * watched calls on one plan must not run concurrently from several host threads.  depth 0
+ * (the default) turns the watch off; until then, or
  * wcal_plan_destroy, the plan holds a side stream, 2 depth events and depth pinned host
  * words.  Errors: WCAL_EINVAL (NULL plan, depth outside [0, WCAL_WATCH_MAX]), WCAL_EHIP. */
 #define WCAL_WATCH_MAX 64
