@@ -365,8 +365,8 @@ int wcal_profile_read(wcal_plan* plan, double* ms, int32_t* launches);
 
 /* ------------------------------------------------------------------------------------
  * Learned warm start.  Not part of the paper's method: a starting point for the solve,
- * which stays the judge of the result (its convergence test decides, and intervals that
- * do not converge from the warm start are solved again from unit gains).
+ * which alone decides the result (its convergence test decides, and intervals that do not
+ * converge from the warm start are solved again from unit gains).
  * ---------------------------------------------------------------------------------- */
 
 /* Knots.  Consecutive intervals (one channel each) are grouped in bins of bin_width
