@@ -984,6 +984,11 @@ __device__ DdSmem dd_smem(unsigned char* smem, int nd, int na) {
 
 // LDS bytes of the gains [nd][na] in dd_ant_kernel, rounded up to 16 for the FP64 blocks
 __host__ __device__ inline size_t ant_g_bytes(int nd, int na) { return ((size_t)nd * na * 8 + 15) / 16 * 16; }
+// dynamic LDS of dd_ant_kernel: the gains, then 16-byte slots for the wavefront partials,
+// H, c and the solve
+inline size_t ant_smem(int nd, int na) {
+    return ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
+}
 
 // One update, per antenna: one workgroup forms H_p and c_p of one antenna.  Lanes run over
 // the Nd(Nd+1)/2 + Nd entries; the four wavefronts take every fourth of the antenna's
@@ -1263,7 +1268,10 @@ size_t points_table_bytes(const wcal_problem& p, int32_t n_time, int32_t n_chan)
     return ws_round(n * nseg * 4 * sizeof(float2)) + ws_round(n * sizeof(float2));
 }
 
-size_t dd_smem_bytes(int nd, int na) { return dd_smem_size(nd, na); }
+size_t dd_lds_need(int nd, int na) {
+    return std::max(dd_smem_size(nd, na) + kernel_static_lds(reinterpret_cast<const void*>(dd_reduce_kernel)),
+                    ant_smem(nd, na) + kernel_static_lds(reinterpret_cast<const void*>(dd_ant_kernel)));
+}
 
 int dd_max_dir() { return NDMAX; }
 
@@ -1294,7 +1302,7 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a0, hipStream_t 
                        : !bf ? (p16 ? dd_gram_dmaf_kernel<16> : dd_gram_dmaf_kernel<4>) : p16 ? dd_gram_dma_kernel<16> : dd_gram_dma_kernel<4>;
     const size_t gsm = !pred && !bf ? dmaf_smem_bytes(nd) : 0;
     const int gg = dd_grid(plan, reinterpret_cast<const void*>(gram), gsm, pred ? (int64_t)a.n_int * ((a.n_bl + PGB - 1) / PGB) : nblk);
-    const size_t asm_ = ant_g_bytes(nd, na) + ((size_t)(DT / WAVE) * 2 * WAVE + ntri(nd) + nd + NDMAX) * 16;
+    const size_t asm_ = ant_smem(nd, na);
     prof_begin(plan, WCAL_K_OTHER, s);
     hipLaunchKernelGGL(dd_init_kernel, dim3((std::max(a.n_int, nctr) + DT - 1) / DT), dim3(DT), 0, s, a, st, 1, nctr);
     if (pred) {
@@ -1341,7 +1349,7 @@ hipError_t launch_dd_accumulate(const wcal_plan* plan, const DdArgs& a, hipStrea
     const int64_t ntask = (int64_t)a.n_int * a.n_bl;
     const int gg = dd_grid(plan, reinterpret_cast<const void*>(dd_gram_kernel<true>), 0, (ntask + 3) / 4);
     hipLaunchKernelGGL(dd_gram_kernel<true>, dim3(gg), dim3(DT), 0, s, a, st, 0);
-    hipLaunchKernelGGL(dd_reduce_kernel, dim3(a.n_int), dim3(DT), dd_smem_bytes(nd, na), s, a, st);
+    hipLaunchKernelGGL(dd_reduce_kernel, dim3(a.n_int), dim3(DT), dd_smem_size(nd, na), s, a, st);
     return hipGetLastError();
 }
 

@@ -685,7 +685,13 @@ void launch_pres_tiles(const wcal_plan* plan, const DdArgs& a, const DdState& st
 }  // namespace
 
 size_t ddp_stats_bytes(const wcal_problem& p) { return dd_state_bytes(p, prec_floats(p.n_dir)); }
-size_t ddp_smem_bytes(int nd, int na) { return pant_smem(nd, na); }
+size_t ddp_lds_need(int nd, int na) {
+    const size_t ant = pant_smem(nd, na), g = pg_bytes(nd, na);
+    size_t need = ant + std::max(kernel_static_lds(reinterpret_cast<const void*>(ddp_ant_kernel<false>)),
+                                 kernel_static_lds(reinterpret_cast<const void*>(ddp_ant_kernel<true>)));
+    need = std::max(need, g + kernel_static_lds(reinterpret_cast<const void*>(ddp_resid_kernel)));
+    return std::max(need, g + kernel_static_lds(reinterpret_cast<const void*>(pick_gram_r(ptiles(nd, true)))));
+}
 int ddp_max_dir() { return PND; }
 const char* ddp_pass_kernel_name(int nd) {
     const int nt = ptiles(nd, false);

@@ -1349,6 +1349,11 @@ hipError_t launch_reset_queue(int32_t* q, hipStream_t s) {
     return hipGetLastError();
 }
 
+size_t kernel_static_lds(const void* fn) {
+    hipFuncAttributes at{};
+    return hipFuncGetAttributes(&at, fn) == hipSuccess ? at.sharedSizeBytes : (size_t)32 << 10;
+}
+
 template <int NC>
 static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s) {
     const int na = plan->prob.n_ant;

@@ -462,7 +462,7 @@ int wcal_plan_create(const wcal_problem* prob, const int32_t* ant1_h, const int3
     plan->n_cu = prop.multiProcessorCount;
     plan->max_smem = prop.sharedMemPerBlock;
     if (p.algo != WCAL_STEFCAL &&
-        (p.n_corr == 4 ? ddp_smem_bytes(p.n_dir, p.n_ant) : dd_smem_bytes(p.n_dir, p.n_ant)) > plan->max_smem) {
+        (p.n_corr == 4 ? ddp_lds_need(p.n_dir, p.n_ant) : dd_lds_need(p.n_dir, p.n_ant)) > plan->max_smem) {
         delete plan;
         return fail(WCAL_ESHAPE, "n_ant * n_dir too large for the per-interval LDS working set");
     }

@@ -253,7 +253,9 @@ hipError_t launch_dd_solve(const wcal_plan* plan, const DdArgs& a, hipStream_t s
 hipError_t launch_dd_accumulate(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
 hipError_t launch_dd_residual(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
 size_t dd_stats_bytes(const wcal_problem& p);
-size_t dd_smem_bytes(int nd, int na);
+// LDS a workgroup of the per-antenna and residual kernels needs at n_ant = na: the largest
+// dynamic size they are launched with plus their static LDS (as the runtime reports it)
+size_t dd_lds_need(int nd, int na);
 int dd_max_dir();
 
 // 2x2 Jones gains (n_corr == 4)
@@ -261,11 +263,13 @@ hipError_t launch_ddp_solve(const wcal_plan* plan, const DdArgs& a, hipStream_t 
 hipError_t launch_ddp_accumulate(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
 hipError_t launch_ddp_residual(const wcal_plan* plan, const DdArgs& a, hipStream_t s);
 size_t ddp_stats_bytes(const wcal_problem& p);
-size_t ddp_smem_bytes(int nd, int na);
+size_t ddp_lds_need(int nd, int na);
 int ddp_max_dir();
 const char* ddp_pass_kernel_name(int nd);
 
 hipError_t launch_reset_queue(int32_t* q, hipStream_t s);
+// static LDS of a kernel in bytes (hipFuncGetAttributes), or 32 KiB if the runtime cannot say
+size_t kernel_static_lds(const void* fn);
 
 // pieces of the scalar solve reused by the smoothed solve
 void fill_di_args(const wcal_plan* plan, DiArgs& a);
