@@ -51,8 +51,11 @@ def unit_cells(P, ncell):
     return torch.ones(P.n_int, ncell, P.n_ant, dtype=torch.complex64, device=DEV)
 
 
+# the last two cases have radii ceil(3 sigma) = 75 and 66 cells, above the 64 the LDS-tiled
+# convolution takes: they run the one-pass-per-value convolution instead
 @pytest.mark.parametrize("n_ant,n_time,n_chan,st,sf", [(12, 3, 8, 1.0, 2.0), (12, 1, 16, 0.0, 3.0),
-                                                       (64, 2, 6, 0.7, 1.5), (16, 4, 1, 1.5, 0.0)])
+                                                       (64, 2, 6, 0.7, 1.5), (16, 4, 1, 1.5, 0.0),
+                                                       (12, 1, 160, 0.0, 25.0), (12, 150, 1, 22.0, 0.0)])
 def test_smooth_lockstep(n_ant, n_time, n_chan, st, sf):
     log(f"[smooth lockstep] n_ant={n_ant} grid={n_time}x{n_chan} sigma=({st},{sf})")
     P = chunk_problem(n_ant, n_time, n_chan, seed=1)
