@@ -282,7 +282,10 @@ def test_bf16_gram_error_against_oracle(algo):
     problem the oracle itself, stopped at a relative change of 1e-6, is still 9e-6 (CohJones)
     and 1.2e-5 (AllJones) from its fixed point, and 1.1e-6 / 1.5e-6 at 1e-7, so only the
     tighter stop separates precision from the distance left to the fixed point.  The BF16
-    solve stops at 1e-6 (its bound, 1e-4, is far above that distance)."""
+    solve stops at 1e-6, far inside its own error: the BF16 rounding of the model fixes the
+    solution only to ~2.5e-5 of the gains' norm (interval-wide ratio), 1e-4 on the worst single
+    gain; its bound, 3e-4 on the worst gain, guards that stated error (the 1e-5 bar is the FP32
+    path's)."""
     log(f"[bf16 gram] algo={algo}")
     P = synth.workload("cohjones_na64", device=DEV, n_time=2, n_chan=8, n_int=1)
     o = glue.solve(P, 0, P.unit_gains()[0].cpu().numpy(), algo="cohjones", tol=1e-10, max_iter=3000)
@@ -294,10 +297,36 @@ def test_bf16_gram_error_against_oracle(algo):
         torch.cuda.synchronize()
         assert int(out["status"][0]) & oc.CONVERGED, (prec, int(out["status"][0]))
         g = out["gains"][0, :, :, 0].cpu().numpy()
-        errs[prec] = gain_err(glue.align(g, go, P.n_dir), go, 1)
-        log(f"  {prec}: gain error vs FP64 oracle {errs[prec]:.2e}, updates {int(out['n_iter'][0])}")
+        ga = glue.align(g, go, P.n_dir)
+        errs[prec] = gain_err(ga, go, 1)
+        fro = float(np.linalg.norm(ga - go) / np.linalg.norm(go))
+        log(f"  {prec}: gain error vs FP64 oracle {errs[prec]:.2e} (interval-wide ratio {fro:.2e}), "
+            f"updates {int(out['n_iter'][0])}")
     assert errs["fp32"] <= 1e-5
-    assert errs["bf16"] <= 1e-4
+    assert errs["bf16"] <= 3e-4
+
+
+def test_bf16_gram_most_directions():
+    """The BF16 Gram at its largest direction count, 13: the model columns, the data column and
+    the two residual columns fill the 16-wide tile exactly.  Converged gains of a 32-antenna,
+    13-direction problem (4 x 8 samples) against the FP64 oracle's (converged to 1e-10), to
+    the BF16 bound of test_bf16_gram_error_against_oracle."""
+    log("[bf16 gram] nd=13")
+    P = synth.dd_point(32, 13, n_time=4, n_chan=8, n_int=1, seed=51, device=DEV, flag_frac=0.05,
+                       fov_deg=2.0, disk_diam=2e4)
+    o = glue.solve(P, 0, P.unit_gains()[0].cpu().numpy(), algo="cohjones", tol=1e-10, max_iter=3000)
+    go = glue.gains_from_oracle(o["g"], 1, P.n_dir)[:, :, 0]
+    plan = wcal.plan_for(P, algo="cohjones", tol=1e-6, max_iter=500, precision="bf16")
+    out = plan.solve(P.data, P.model, P.flags, P.unit_gains())
+    torch.cuda.synchronize()
+    assert int(out["status"][0]) & oc.CONVERGED, int(out["status"][0])
+    g = out["gains"][0, :, :, 0].cpu().numpy()
+    ga = glue.align(g, go, P.n_dir)
+    e = gain_err(ga, go, 1)
+    fro = float(np.linalg.norm(ga - go) / np.linalg.norm(go))
+    log(f"  bf16: gain error vs FP64 oracle {e:.2e} (interval-wide ratio {fro:.2e}), updates "
+        f"{int(out['n_iter'][0])} (oracle {o['n_iter']})")
+    assert e <= 3e-4
 
 
 def test_bf16_gram_full_size_noise_free_recovery():
