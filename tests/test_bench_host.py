@@ -64,3 +64,20 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_committed_traffic_records_match_the_sources():
+    # a committed byte-counter record taken on the sources in the tree is reported for the
+    # default solve of its workload and for no other run; records taken on other sources
+    # are reported for none (the counter runs have to be taken again)
+    import json
+    import pytest
+    recs = json.load(open(os.path.join(ROOT, "profiles", "pmc_traffic.json")))
+    assert recs
+    stale = [k for k, r in recs.items() if r["src_sha"] != bench.source_hash(k.split("_", 1)[0])]
+    for key, rec in recs.items():
+        want = None if key in stale else rec["traffic_bytes_per_launch"]
+        assert bench.measured_traffic(key) == want
+        assert bench.measured_traffic(key, default_solve=False) is None
+    if stale:
+        pytest.skip(f"records taken on other sources (take the counter runs again): {stale}")
