@@ -906,30 +906,9 @@ __device__ __forceinline__ double2 hget(const double2* h, int i, int j, int nd) 
     return make_double2(v.x, -v.y);
 }
 
-// CohJones GN value for one antenna: Cholesky H = R^H R in place (upper packed), then
-// R^H z = c, R x = z.  Returns false (gain kept) when a pivot <= EPS * H_jj.
-__device__ bool chol_solve(double2* h, const double2* c, double2* x, int nd) {
-    for (int i = 0; i < nd; ++i) {
-        const double hii = h[tri(i, i, nd)].x;
-        double piv = hii;
-        for (int k = 0; k < i; ++k) {
-            const double2 r = h[tri(k, i, nd)];
-            piv -= r.x * r.x + r.y * r.y;
-        }
-        if (!(piv > WCAL_EPS_PIVOT * hii) || !isfinite(piv)) return false;
-        const double rii = sqrt(piv);
-        h[tri(i, i, nd)] = make_double2(rii, 0.0);
-        for (int j = i + 1; j < nd; ++j) {
-            double2 v = h[tri(i, j, nd)];
-            for (int k = 0; k < i; ++k) {
-                const double2 rki = h[tri(k, i, nd)], rkj = h[tri(k, j, nd)];
-                // v -= conj(R[k][i]) R[k][j]
-                v.x -= rki.x * rkj.x + rki.y * rkj.y;
-                v.y -= rki.x * rkj.y - rki.y * rkj.x;
-            }
-            h[tri(i, j, nd)] = make_double2(v.x / rii, v.y / rii);
-        }
-    }
+// Forward and back substitution with the Cholesky factor R of H = R^H R (upper, packed,
+// as dd_ant_kernel leaves it): R^H z = c, then R x = z.
+__device__ void chol_subst(const double2* h, const double2* c, double2* x, int nd) {
     // forward: R^H z = c
     for (int i = 0; i < nd; ++i) {
         double2 v = c[i];
@@ -952,7 +931,6 @@ __device__ bool chol_solve(double2* h, const double2* c, double2* x, int nd) {
         const double rii = h[tri(i, i, nd)].x;
         x[i] = make_double2(v.x / rii, v.y / rii);
     }
-    return true;
 }
 
 struct DdSmem {
@@ -993,9 +971,10 @@ inline size_t ant_smem(int nd, int na) {
 // One update, per antenna: one workgroup forms H_p and c_p of one antenna.  Lanes run over
 // the Nd(Nd+1)/2 + Nd entries; the four wavefronts take every fourth of the antenna's
 // baselines (in CSR order, 8 records in flight per lane) and their FP64 sums are folded in
-// wavefront order.  Then one lane solves (CohJones: Cholesky; AllJones: diagonal, residual
-// form), applies the schedule and writes the candidate gains and its share of the FP64
-// relative-change norms.  The interval's decision follows in dd_finish_kernel.
+// wavefront order.  CohJones factors H_p across the workgroup (Cholesky); then one lane
+// substitutes (CohJones) or takes the diagonal residual-form steps (AllJones), applies the
+// schedule and writes the candidate gains and its share of the FP64 relative-change norms.
+// The interval's decision follows in dd_finish_kernel.
 __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nd = a.n_dir, na = a.n_ant, nbl = a.n_bl;
@@ -1079,22 +1058,65 @@ __global__ void __launch_bounds__(DT) dd_ant_kernel(DdArgs a, DdState st, int it
         if (e < nx) H[e] = v;
         else C[e - nx] = v;
     }
+    __shared__ int s_fin;
+    __shared__ double s_hdiag[NDMAX];
+    if (threadIdx.x == 0) s_fin = 1;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        bool fin = true;
-        for (int i = 0; i < nx; ++i) fin = fin && isfinite(H[i].x) && isfinite(H[i].y);
-        for (int i = 0; i < nd; ++i) fin = fin && isfinite(C[i].x) && isfinite(C[i].y);
-        bool ok = true;
-        if (a.algo == WCAL_COHJONES && resid) {
-            // g + H^-1 J^H r
-            ok = fin && chol_solve(H, C, X, nd);
-            if (ok)
-                for (int d = 0; d < nd; ++d) {
-                    const float2 gd = G[d * na + p];
-                    X[d] = make_double2(gd.x + X[d].x, gd.y + X[d].y);
+    for (int e = threadIdx.x; e < per; e += blockDim.x) {
+        const double2 v = e < nx ? H[e] : C[e - nx];
+        if (!isfinite(v.x) || !isfinite(v.y)) s_fin = 0;
+    }
+    __syncthreads();
+    const bool fin = s_fin != 0;
+    bool ok = true;
+    if (a.algo == WCAL_COHJONES) {
+        // H = R^H R across the workgroup, right-looking: per pivot the row is scaled, then the
+        // trailing triangle updated in parallel.  Every entry takes the same subtractions in
+        // the same order as a serial left-looking factorisation; a pivot below
+        // WCAL_EPS_PIVOT times its original diagonal (or not finite) stops it (the decision
+        // reads one LDS value in every thread, so the workgroup leaves together)
+        ok = fin;
+        if (ok) {
+            for (int i = threadIdx.x; i < nd; i += blockDim.x) s_hdiag[i] = H[tri(i, i, nd)].x;
+            __syncthreads();
+            for (int i = 0; i < nd; ++i) {
+                const double piv = H[tri(i, i, nd)].x;
+                if (!(piv > WCAL_EPS_PIVOT * s_hdiag[i]) || !isfinite(piv)) {
+                    ok = false;
+                    break;
                 }
-        } else if (a.algo == WCAL_COHJONES) {
-            ok = fin && chol_solve(H, C, X, nd);
+                const double rii = sqrt(piv);
+                __syncthreads();
+                for (int c = i + threadIdx.x; c < nd; c += blockDim.x) {
+                    const double2 v = H[tri(i, c, nd)];
+                    H[tri(i, c, nd)] = c == i ? make_double2(rii, 0.0) : make_double2(v.x / rii, v.y / rii);
+                }
+                __syncthreads();
+                const int m = nd - i - 1;
+                for (int e = threadIdx.x; e < m * (m + 1) / 2; e += blockDim.x) {
+                    int r = 0, q = e;
+                    while (q >= m - r) { q -= m - r; ++r; }
+                    const int rr = i + 1 + r, cc = rr + q;
+                    const double2 rki = H[tri(i, rr, nd)], rkj = H[tri(i, cc, nd)];
+                    double2 v = H[tri(rr, cc, nd)];
+                    v.x -= rki.x * rkj.x + rki.y * rkj.y;   // conj(R[i][rr]) R[i][cc]
+                    v.y -= rki.x * rkj.y - rki.y * rkj.x;
+                    H[tri(rr, cc, nd)] = v;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (a.algo == WCAL_COHJONES) {
+            if (ok) {
+                chol_subst(H, C, X, nd);
+                if (resid)   // g + H^-1 J^H r
+                    for (int d = 0; d < nd; ++d) {
+                        const float2 gd = G[d * na + p];
+                        X[d] = make_double2(gd.x + X[d].x, gd.y + X[d].y);
+                    }
+            }
         } else {
             // AllJones: g^d + (c_d - sum_e H[d][e] g^e) / H[d][d], per direction
             for (int d = 0; d < nd; ++d) {
