@@ -706,7 +706,6 @@ template <int PIECE>
 __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
     extern __shared__ __align__(16) float2 mbuf[];   // dmaf_smem_bytes(Nd)
     __shared__ float2 dbuf[GSF * GB + 1];      // the last slot stays zero
-    __shared__ uint8_t fbuf[GSF][GB];
     __shared__ int s_cnt[GB];
     __shared__ int s_task;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -721,11 +720,13 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
     if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
     const bool has_flags = a.flags != nullptr;
     const int seg_bytes = GB * nd * 8;          // one sample's model segment
-    const int pps = seg_bytes / PIECE;          // pieces per sample
-    const int npc = GSF * pps;                  // pieces per chunk
+    const int npass = (seg_bytes / PIECE + WAVE - 1) / WAVE;   // copies of 64 pieces per segment
     // this lane's operand: element (sample sl, baseline bl) at base[(sl GB + bl) * stride]
     const float2* obase = col < nd ? mbuf + col : col == nd ? dbuf : dbuf + GSF * GB;
     const int ostride = col < nd ? nd : col == nd ? 1 : 0;
+    // this thread's row of every chunk: sample si, baseline bi
+    static_assert(GSF * GB == DT, "one staged row per thread");
+    const int si = threadIdx.x / GB, bi = threadIdx.x % GB;
     if (threadIdx.x == 0) dbuf[GSF * GB] = make_float2(0.f, 0.f);
     for (;;) {
         __syncthreads();
@@ -739,6 +740,9 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
         const int nch = (ns + GSF - 1) / GSF;
+        const int seg_have = min(GB, nbl - b0) * nd * 8;   // bytes of a segment that exist
+        const bool bi_ok = b0 + bi < nbl;
+        int cnt = 0;                                       // unflagged rows of this thread
         floatx4 crr[4], cri[4];   // sums of the current block of GFOLD chunks
         floatx4 trr[4], tri4[4];  // sums of the finished blocks
 #pragma unroll
@@ -752,35 +756,40 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
         const int ce = min(nch, cb + GFOLD);
         for (int c = cb; c < ce; ++c) {
             const int s0 = c * GSF;
-            // model: pieces p = p0 + lane of the chunk, p0 uniform per wavefront; piece p lands
-            // at byte p * PIECE of mbuf
-            for (int p0 = w * WAVE; p0 < npc; p0 += DT) {
-                const int p = p0 + lane;
-                const int sm = p / pps, jb = (p - sm * pps) * PIECE;
-                const bool ok = p < npc && s0 + sm < ns && b0 + jb / (8 * nd) < nbl;
-                if (ok) {
-                    const char* src = reinterpret_cast<const char*>(a.model + (off + (int64_t)(s0 + sm) * nbl + b0) * nd) + jb;
-                    auto dst = (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(mbuf) + p0 * PIECE);
-                    if constexpr (PIECE == 16) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
-                    else __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+            // model: each wavefront copies the segments of samples w, w + 4, ... of the chunk,
+            // 64 pieces at a time (lane l: piece h 64 + l); the segment's base is uniform, so
+            // the address arithmetic stays scalar
+            for (int sm = w; sm < GSF && s0 + sm < ns; sm += DT / WAVE) {
+                const char* seg = reinterpret_cast<const char*>(a.model + (off + (int64_t)(s0 + sm) * nbl + b0) * nd);
+                char* lds = reinterpret_cast<char*>(mbuf) + sm * seg_bytes;
+                for (int h = 0; h < npass; ++h) {
+                    const int jb = (h * WAVE + lane) * PIECE;
+                    if (jb < seg_have) {
+                        auto dst = (__attribute__((address_space(3))) void*)(lds + h * WAVE * PIECE);
+                        if constexpr (PIECE == 16) __builtin_amdgcn_global_load_lds(seg + jb, dst, 16, 0, 0);
+                        else __builtin_amdgcn_global_load_lds(seg + jb, dst, 4, 0, 0);
+                    }
                 }
             }
-            bool skip = false;
-            for (int i = threadIdx.x; i < GSF * GB; i += DT) {   // data and flag of row (i / GB, i % GB)
-                const int si = i / GB, bi = i - si * GB;
-                const bool ok = s0 + si < ns && b0 + bi < nbl;
-                const int64_t row = off + (int64_t)(s0 + si) * nbl + b0 + bi;
-                const bool sk = !ok || (has_flags && a.flags[row] != 0);
-                dbuf[i] = sk ? make_float2(0.f, 0.f) : a.data[row];
-                fbuf[si][bi] = (uint8_t)sk;
-                if (!sk) atomicAdd(&s_cnt[bi], 1);
-                skip = skip || sk;
+            // data and flag of this thread's row, both requested before either is used (the
+            // data of a flagged row is read and dropped by a selection)
+            const bool ok = s0 + si < ns && bi_ok;
+            const int64_t row = off + (int64_t)(s0 + si) * nbl + b0 + bi;
+            float2 dv = make_float2(0.f, 0.f);
+            uint8_t fl = 0;
+            if (ok) {
+                dv = a.data[row];
+                if (has_flags) fl = a.flags[row];
             }
-            // the model pieces have landed (the barrier waits for them); any row to clear?
-            if (__syncthreads_or(skip)) {
-                for (int e = threadIdx.x; e < GSF * GB * nd; e += DT) {
-                    const int rowc = e / nd;
-                    if (fbuf[rowc / GB][rowc % GB]) mbuf[e] = make_float2(0.f, 0.f);
+            const bool sk = !ok || fl != 0;
+            dbuf[threadIdx.x] = sk ? make_float2(0.f, 0.f) : dv;
+            cnt += sk ? 0 : 1;
+            // the model pieces have landed (the barrier waits for them); a flagged or absent
+            // row is cleared by its own thread
+            if (__syncthreads_or(sk)) {
+                if (sk) {
+                    float2* mr = mbuf + threadIdx.x * nd;
+                    for (int e = 0; e < nd; ++e) mr[e] = make_float2(0.f, 0.f);
                 }
                 __syncthreads();
             }
@@ -799,6 +808,8 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
         }
         fold_block<4>(crr, cri, trr, tri4);
         }
+        atomicAdd(&s_cnt[bi], cnt);
+        __syncthreads();
         // epilogue through each wavefront's own 2 x 256 floats of mbuf (free now)
         float* tile = reinterpret_cast<float*>(mbuf) + w * 512;
         for (int j = 0; j < 4; ++j) {
