@@ -686,6 +686,7 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
 }
 
 constexpr int GSF = 16;   // samples per chunk of dd_gram_dmaf_kernel
+typedef float lds_f2 __attribute__((ext_vector_type(2)));   // an operand read from LDS
 constexpr int GFOLD = FOLD_SAMPLES / GSF;   // chunks per FP64 fold
 // dynamic LDS of dd_gram_dmaf_kernel: a chunk's model rows, at least the 4 x 512-float
 // epilogue tiles
@@ -701,9 +702,13 @@ inline size_t dmaf_smem_bytes(int nd) {
 // flags go through registers; a chunk that holds a flagged or absent row (a block-wide OR at
 // the barrier) gets those rows' model values zeroed in LDS before use (a selection, so
 // non-finite values under a flag never reach a product).  Each lane reads its operand with
-// one precomputed base and stride: model column col < Nd, the data column Nd, or a zero slot.
+// one base and stride: model column col < Nd, the data column Nd, or a zero slot.
+// Vector instructions do not issue beside the MFMAs, so the pass is bound by the issue of
+// both, and resident wavefronts hide the chunk's memory round trip: five per SIMD (95 VGPRs,
+// no spills) against three at the compiler's own choice, 26.1 -> 22.9 ms of pass per
+// cohjones_na64 solve (four: 24.5 ms; six spill and run 26.8 ms).
 template <int PIECE>
-__global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(5))) dd_gram_dmaf_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
     extern __shared__ __align__(16) float2 mbuf[];   // dmaf_smem_bytes(Nd)
     __shared__ float2 dbuf[GSF * GB + 1];      // the last slot stays zero
     __shared__ int s_cnt[GB];
@@ -724,6 +729,9 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
     // this lane's operand: element (sample sl, baseline bl) at base[(sl GB + bl) * stride]
     const float2* obase = col < nd ? mbuf + col : col == nd ? dbuf : dbuf + GSF * GB;
     const int ostride = col < nd ? nd : col == nd ? 1 : 0;
+    // the lane's operand (sample 4 g + kk, baseline 4 w + j) sits at LDS byte ob0 + g sg + j sj
+    const uint32_t ob0 = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float2*)(obase + (kk * GB + 4 * w) * ostride);
+    const uint32_t sj = (uint32_t)ostride * 8u, sg = 4u * GB * (uint32_t)ostride * 8u;
     // this thread's row of every chunk: sample si, baseline bi
     static_assert(GSF * GB == DT, "one staged row per thread");
     const int si = threadIdx.x / GB, bi = threadIdx.x % GB;
@@ -793,12 +801,15 @@ __global__ void __launch_bounds__(DT) dd_gram_dmaf_kernel(DdArgs a, DdState st, 
                 }
                 __syncthreads();
             }
+            // the operand addresses are formed again for every chunk from an opaque base, so
+            // that 16 of them do not stay live (in registers) across the chunk loop
+            uint32_t ob = ob0;
+            asm volatile("" : "+v"(ob));
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int bl = 4 * w + j;
 #pragma unroll
                 for (int g = 0; g < GSF / 4; ++g) {
-                    const float2 v = obase[((4 * g + kk) * GB + bl) * ostride];
+                    const lds_f2 v = *(const __attribute__((address_space(3))) lds_f2*)(uintptr_t)(ob + g * sg + j * sj);
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.x, crr[j], 0, 0, 0);
                     crr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, v.y, crr[j], 0, 0, 0);
                     cri[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, v.y, cri[j], 0, 0, 0);
