@@ -540,11 +540,12 @@ __global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(3, 8)))
 // BF16 column for r would make J^H r jump with the rounding of r as the gains move, and
 // the iteration would chatter above the tolerance instead of converging.  Needs Nd <= 13.
 // (A double-buffered copy serialises: the compiler waits for every outstanding copy before
-// any LDS read.)
+// any LDS read.)  Five waves per SIMD (94 VGPRs, no spills; the static LDS allows no more):
+// 32.2 -> 29.0 ms of pass per cohjones_na64 solve against four.
 constexpr int GSD = 16;
 
 template <int PIECE>
-__global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
+__global__ void __launch_bounds__(DT) __attribute__((amdgpu_waves_per_eu(5))) dd_gram_dma_kernel(DdArgs a, DdState st, const int32_t* list, const int32_t* n_list) {
     __shared__ __align__(16) float2 mbuf[GSD * GB * NDMAX];
     __shared__ float2 dbuf[GSD][GB];
     __shared__ uint8_t fbuf[GSD][GB];
@@ -561,8 +562,7 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
     if ((int64_t)blockIdx.x >= ntask) return;   // tasks are popped dynamically
     const bool has_flags = a.flags != nullptr;
     const int seg_bytes = GB * nd * 8;          // one sample's model segment
-    const int pps = seg_bytes / PIECE;          // pieces per sample
-    const int npc = GSD * pps;                  // pieces per chunk
+    const int npass = (seg_bytes / PIECE + WAVE - 1) / WAVE;   // copies of 64 pieces per segment
     const int ds = threadIdx.x / GB, db = threadIdx.x % GB;   // data / flag element of this thread
     for (;;) {
         __syncthreads();
@@ -575,6 +575,7 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
         const int64_t off = a.row_off[k];
         const int ns = a.ns[k];
         const int nch = (ns + GSD - 1) / GSD;
+        const int seg_have = min(GB, nbl - b0) * nd * 8;   // bytes of a segment that exist
         floatx4 crr[4], cri[4];
         int cnt[4];
         float2 wgt[4];           // g^c_p conj(g^c_q) of this lane's column for its 4 baselines
@@ -590,17 +591,18 @@ __global__ void __launch_bounds__(DT) dd_gram_dma_kernel(DdArgs a, DdState st, c
         }
         for (int c = 0; c < nch; ++c) {
             const int s0 = c * GSD;
-            // model: pieces p = p0 + lane of the chunk, p0 uniform per wavefront; piece p lands
-            // at byte p * PIECE of mbuf
-            for (int p0 = w * WAVE; p0 < npc; p0 += DT) {
-                const int p = p0 + lane;
-                const int sm = p / pps, jb = (p - sm * pps) * PIECE;
-                const bool ok = p < npc && s0 + sm < ns && b0 + jb / (8 * nd) < nbl;
-                if (ok) {
-                    const char* src = reinterpret_cast<const char*>(a.model + (off + (int64_t)(s0 + sm) * nbl + b0) * nd) + jb;
-                    auto dst = (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(mbuf) + p0 * PIECE);
-                    if constexpr (PIECE == 16) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
-                    else __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+            // model: each wavefront copies the segments of samples w, w + 4, ... of the chunk,
+            // 64 pieces at a time, from a uniform base (as dd_gram_dmaf_kernel)
+            for (int sm = w; sm < GSD && s0 + sm < ns; sm += DT / WAVE) {
+                const char* seg = reinterpret_cast<const char*>(a.model + (off + (int64_t)(s0 + sm) * nbl + b0) * nd);
+                char* lds = reinterpret_cast<char*>(mbuf) + sm * seg_bytes;
+                for (int h = 0; h < npass; ++h) {
+                    const int jb = (h * WAVE + lane) * PIECE;
+                    if (jb < seg_have) {
+                        auto dst = (__attribute__((address_space(3))) void*)(lds + h * WAVE * PIECE);
+                        if constexpr (PIECE == 16) __builtin_amdgcn_global_load_lds(seg + jb, dst, 16, 0, 0);
+                        else __builtin_amdgcn_global_load_lds(seg + jb, dst, 4, 0, 0);
+                    }
                 }
             }
             {
