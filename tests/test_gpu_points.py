@@ -180,6 +180,25 @@ def test_points_na64_full_size():
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("mode", ["pass", "stats"])
+def test_points_garbage_under_flags_is_bit_identical(mode):
+    """NaN in the data under flags leaves every output of the predicted-model solve
+    bit-identical: a flagged sample enters the pass as a zeroed value with weight 0."""
+    log(f"[points garbage under flags] mode={mode}")
+    P = problem(n_time=3, n_chan=13, n_int=3, flag_frac=0.1, seed=9)
+    plan = wcal.plan_for(P, algo="cohjones", tol=1e-6, max_iter=60, mode=mode)
+    clean = plan.solve_points(**points_args(P), data=P.data, flags=P.flags, gains=P.unit_gains())
+    clean = {k: (v.clone() if v is not None else None) for k, v in clean.items()}
+    d2 = P.data.clone()
+    d2[P.flags.bool()] = float("nan")
+    dirty = plan.solve_points(**points_args(P), data=d2, flags=P.flags, gains=P.unit_gains())
+    torch.cuda.synchronize()
+    for key in ("gains", "residual", "n_iter", "status", "chi2"):
+        x, y = clean[key].cpu(), dirty[key].cpu()
+        assert torch.equal(x.view(torch.uint8) if x.is_complex() else x,
+                           y.view(torch.uint8) if y.is_complex() else y), key
+
+
 def test_points_rejects_bad_grids():
     P = problem(seed=2)
     plan = wcal.plan_for(P, algo="cohjones")
