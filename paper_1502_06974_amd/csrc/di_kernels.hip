@@ -579,6 +579,7 @@ __global__ void __launch_bounds__(TB) di_init_kernel(DiArgs a) {
         a.status[i] = 0;
         a.n_iter[i] = 0;
         a.active[i] = 1;
+        if (a.tri_cnt) a.tri_cnt[i] = 0;
     }
     if (i < 2 * (a.max_iter + 2)) a.ctr[i] = 0;
 }
@@ -865,12 +866,22 @@ __device__ void finish_interval(const DiArgs& a, int it, int k, int t0, int t1, 
                                 float2* Gn, double* red, int* s_flags, int* s_pos);
 
 // FUSED: every interval is one tile, so the workgroup that sums a tile holds its interval's
-// complete sums and applies the update itself (no partials, no update launch).
+// complete sums and applies the update itself (no update launch).  When few intervals are
+// listed (the last updates, or a small batch), each is shared by S = min(4, grid / listed)
+// workgroups, S chosen per launch from the listed count, so full passes keep S = 1: task
+// (i, part) walks units b0 + part nw + w + j S nw of the i-th listed tile, folds its wavefront
+// slices into partial (i, part) and counts itself in tri_cnt[i]; the workgroup that arrives
+// last folds the S partials in part order, applies the update and clears the counter.  The
+// sums keep a fixed order for a given S, so a solve is bit-reproducible; an interval's
+// rounding can depend on how many others are still listed.  Alone on one workgroup, an
+// interval of the bandpass takes ~45 us (a wavefront's 80 chunks at four in flight), which set
+// the length of the last updates.
 // Workgroup of the triangle pass: eight wavefronts walk an interval's units (three workgroups
 // per CU at its 58 VGPRs).  Against four wavefronts, the tail updates, in which a few intervals
 // are left and each runs on one workgroup, finish sooner, and full passes lose nothing
 // (bandpass_na256 solve 6.45-6.60 -> 6.39 ms); six and twelve wavefronts measured slower.
 constexpr int TRI_TB = 512;
+constexpr int TRI_SPLIT_MAX = 4;
 template <bool FUSED>
 __global__ void __launch_bounds__(TRI_TB) di_tri_pass_kernel(DiArgs a, const TriUnit* __restrict__ units, int it) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -884,10 +895,14 @@ __global__ void __launch_bounds__(TRI_TB) di_tri_pass_kernel(DiArgs a, const Tri
     __shared__ int s_flags[2];
     __shared__ int s_pos;
     __shared__ int s_t;
+    __shared__ int s_last;
     const int nw = blockDim.x / WAVE;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wavefront-uniform
     const int n = it == 0 ? a.ntiles : a.ctr[qoff(a) + it];
-    if ((int)blockIdx.x >= n) return;     // nothing to pop (see di_pass_kernel)
+    // workgroups per listed tile; the partials of n S tasks fit the plan's ntiles slots
+    int S = 1;
+    if (FUSED && a.tri_cnt && n > 0) S = max(1, min(TRI_SPLIT_MAX, min((int)gridDim.x / n, a.ntiles / n)));
+    if ((int)blockIdx.x >= n * S) return;     // nothing to pop (see di_pass_kernel)
     const int32_t* list = a.lists + (it & 1) * a.ntiles;
     float* myacc = acc + w * ns;
     for (;;) {
@@ -895,27 +910,57 @@ __global__ void __launch_bounds__(TRI_TB) di_tri_pass_kernel(DiArgs a, const Tri
         if (threadIdx.x == 0) s_t = atomicAdd(&a.ctr[it], 1);
         __syncthreads();
         const int idx = __builtin_amdgcn_readfirstlane(s_t);
-        if (idx >= n) break;
-        const int t = it == 0 ? idx : list[idx];
+        if (idx >= n * S) break;
+        const int ti = idx / S, part = idx - ti * S;
+        const int t = it == 0 ? ti : list[ti];
         const Tile T = a.tiles[t];
         const float2* gk = a.gains + (int64_t)T.k * na;
         for (int i = threadIdx.x; i <= na; i += blockDim.x) G[i] = i < na ? gk[i] : make_float2(0.f, 0.f);
         for (int i = threadIdx.x; i < nw * ns; i += blockDim.x) acc[i] = 0.f;
         __syncthreads();
+        const int u0 = T.b0 + part * nw + w, du = nw * S;
         if (a.tri_paired)
-            for (int u = T.b0 + w; u < T.b1; u += nw) tri_unit_paired(a, T, units[u], G, myacc);
+            for (int u = u0; u < T.b1; u += du) tri_unit_paired(a, T, units[u], G, myacc);
         else
-            for (int u = T.b0 + w; u < T.b1; u += nw) {
+            for (int u = u0; u < T.b1; u += du) {
                 if (T.s1 - T.s0 == 1) tri_unit<true>(a, T, units[u], G, myacc);
                 else tri_unit<false>(a, T, units[u], G, myacc);
             }
         __syncthreads();
         if constexpr (FUSED) {
-            // fold the wavefront slices into the first, in wavefront order
-            for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
-                float v = acc[i];
-                for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * ns + i];
-                acc[i] = v;
+            if (S > 1) {
+                // This part's sums (wavefront slices folded in wavefront order) go out with
+                // device-coherent stores; every wavefront waits until its stores are complete
+                // before the workgroup counts itself, and the last workgroup reads the parts
+                // with device-coherent loads.  (A device-scope fence would write back and
+                // invalidate the XCD's whole L2 on every task.)
+                float* out = a.partial + ((int64_t)ti * S + part) * na * NVP;
+                for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                    float v = acc[i];
+                    for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * ns + i];
+                    __hip_atomic_store(out + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    s_last = __hip_atomic_fetch_add(&a.tri_cnt[ti], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == S - 1;
+                __syncthreads();
+                if (!s_last) continue;          // another workgroup of the interval finishes it
+                const float* in = a.partial + (int64_t)ti * S * na * NVP;
+                for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                    float v = __hip_atomic_load(in + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    for (int q = 1; q < S; ++q)
+                        v += __hip_atomic_load(in + (int64_t)q * na * NVP + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    acc[i] = v;
+                }
+                if (threadIdx.x == 0) a.tri_cnt[ti] = 0;
+            } else {
+                // fold the wavefront slices into the first, in wavefront order
+                for (int i = threadIdx.x; i < na * NVP; i += blockDim.x) {
+                    float v = acc[i];
+                    for (int w2 = 1; w2 < nw; ++w2) v += acc[w2 * ns + i];
+                    acc[i] = v;
+                }
             }
             __syncthreads();
             finish_interval<1>(a, it, T.k, t, t + 1, acc, G, Gn, red, s_flags, &s_pos);
@@ -1410,7 +1455,8 @@ static hipError_t solve_nc(const wcal_plan* plan, const DiArgs& a, hipStream_t s
                           (fused ? (size_t)na * sizeof(float2) : 0);
         const void* fn = fused ? reinterpret_cast<const void*>(di_tri_pass_kernel<true>)
                                : reinterpret_cast<const void*>(di_tri_pass_kernel<false>);
-        const int gp = grid_resident(plan, fn, TRI_TB, ps, at.ntiles);
+        // the fused pass may share a listed interval among up to TRI_SPLIT_MAX workgroups
+        const int gp = grid_resident(plan, fn, TRI_TB, ps, (int64_t)at.ntiles * (fused ? TRI_SPLIT_MAX : 1));
         for (int it = 0; it < a.max_iter; ++it) {
             prof_begin(plan, WCAL_K_PASS, s);
             if (fused)

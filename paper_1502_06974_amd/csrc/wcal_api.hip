@@ -314,7 +314,7 @@ static size_t layout_for(const wcal_plan* plan, int32_t ntiles, int32_t nttiles,
     const size_t nvp = di ? (size_t)di_nvp(p.n_corr) : 0;
     size_t sz[WS_COUNT] = {};
     sz[WS_CTR] = sizeof(int32_t) * (2 * ((size_t)p.max_iter + 2) + 16);
-    sz[WS_ACTIVE] = sizeof(int32_t) * (size_t)p.n_int;
+    sz[WS_ACTIVE] = sizeof(int32_t) * (size_t)p.n_int * (di ? 2 : 1);
     sz[WS_QUEUE] = 4 * sizeof(int32_t);
     sz[WS_LISTS] = 2 * sizeof(int32_t) * (size_t)std::max(1, ntmax);
     sz[WS_PARTIAL] = sizeof(float) * std::max<size_t>(1, (size_t)ntmax * p.n_ant * nvp);
@@ -590,6 +590,7 @@ static void fill_tables_di(const wcal_plan* plan, DiArgs& a) {
     a.max_iter = plan->prob.max_iter;
     a.schedule = plan->prob.schedule;
     a.tri_paired = plan->tri_paired ? 1 : 0;
+    a.tri_cnt = plan->d_active + plan->prob.n_int;
     a.tol = plan->prob.tol;
 }
 

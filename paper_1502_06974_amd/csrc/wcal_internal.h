@@ -100,7 +100,7 @@ struct wcal_plan {
     int32_t* d_lists = nullptr;   // [2][ntiles] active tile lists
     int32_t* d_ctr = nullptr;     // [2][max_iter + 2] pop counters and list lengths
     float* d_partial = nullptr;   // [ntiles][n_ant][nvp] per-tile per-antenna sums
-    int32_t* d_active = nullptr;  // [n_int]
+    int32_t* d_active = nullptr;  // [n_int], then (StefCal) [n_int] arrival counters of the triangle pass
     double* d_chi_part = nullptr; // [ntiles]
     float* d_stats = nullptr;     // per-baseline statistics (STATS mode) or DD Gram records
     size_t stats_bytes = 0;
@@ -183,6 +183,7 @@ struct DiArgs {
     float* stats;
     int32_t n_ant, n_bl, n_int, max_iter, schedule;
     int32_t tri_paired;      // triangle units are packed row pairs (see TriUnit)
+    int32_t* tri_cnt;        // [n_int] fused triangle pass: workgroups of a shared interval done
     double tol;
 };
 

@@ -387,6 +387,32 @@ def test_triangle_pass_split_tiles(monkeypatch):
         assert gain_err(g[k], glue.gains_from_oracle(o["g"], 1, 1), 1) <= 1e-5
 
 
+def test_triangle_pass_shared_intervals(monkeypatch):
+    """Once at most half the intervals are listed, the fused triangle pass shares each among up
+    to four workgroups (the last to arrive folds their partials and applies the update).  A
+    converging solve of 48 one-sample intervals, whose last updates list only a few of them,
+    ends at the oracle's gains in every interval and is bit-identical when repeated."""
+    log("[triangle shared intervals]")
+    monkeypatch.setenv("WCAL_TRI", "1")
+    Q = synth.scalar_di(90, [1] * 48, sigma=0.05, seed=17, flag_frac=0.05, device=DEV)
+    plan = wcal.plan_for(Q, tol=1e-6, max_iter=100)
+    outs = [plan.solve(Q.data, Q.model, Q.flags, Q.unit_gains()) for _ in range(2)]
+    torch.cuda.synchronize()
+    for key in ("gains", "residual", "n_iter", "status", "chi2"):
+        x, y = outs[0][key].cpu(), outs[1][key].cpu()
+        assert torch.equal(x.view(torch.uint8) if x.is_complex() else x,
+                           y.view(torch.uint8) if y.is_complex() else y), key
+    n_iter = outs[0]["n_iter"].cpu().numpy()
+    log(f"  updates per interval: {n_iter.min()}..{n_iter.max()}")
+    assert n_iter.max() > n_iter.min()
+    assert np.all(outs[0]["status"].cpu().numpy() & oc.CONVERGED)
+    g = outs[0]["gains"].cpu().numpy()
+    for k in range(Q.n_int):
+        o = glue.solve(Q, k, Q.unit_gains()[k].cpu().numpy(), tol=1e-6, max_iter=100)
+        e = gain_err(g[k], glue.gains_from_oracle(o["g"], 1, 1), 1)
+        assert e <= 1e-5, (k, e)
+
+
 def test_triangle_pass_matches_generic_and_is_reproducible(monkeypatch):
     log("[triangle vs generic]")
     P = make("scalar", 70, [1, 4, 2], flag_frac=0.1, seed=13)
